@@ -1,0 +1,338 @@
+"""FP64 CPU oracle for the per-frame Dark-Channel-Prior dehazing path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) imports, calls or links this module; only the tests, the
+smoke check and the CPU-baseline leg of the benchmark do.  It shares no code,
+tables or constants with the GPU implementation.
+
+Every step follows the paper's statement of the method (Hazedefy, arXiv
+2512.16609) in the paper's order, in plain float64 NumPy:
+
+  Sec. IV-A, Eq. (2)   dark channel: per-pixel channel minimum, then the
+                       minimum over a square patch (morphological erosion)
+  Sec. IV-B, Eq. (3)   airlight: mean RGB of the K brightest dark-channel
+                       pixels, scaled by alpha = 0.8
+  Sec. IV-C, Eqs. (4)-(5)  transmission with a lower clamp
+  Sec. IV-D, Eq. (6)   guided-filter refinement (He et al. 2013 box form)
+  Sec. IV-E, Eqs. (7)-(8)  radiance recovery and gamma correction, then the
+                       optional colour balance
+  Sec. V               per-frame step order and the real-time/offline branch
+
+Where the paper is silent the oracle takes these readings (each is also a
+parameter or a documented choice of the GPU library):
+  * parameters are binary32 values (the C ABI carries floats); the oracle
+    converts each to its float32 value before computing in float64;
+  * erosion and box windows are clipped at the frame border (a clipped box is
+    normalised by its own pixel count);
+  * K = max(1, floor(top_frac * W * H)); the K pixels are the first K in the
+    order (D descending, raster index ascending), so the set is unique;
+  * A^c is the alpha-scaled mean of the hazy input over the set; as a divisor
+    it is guarded as max(A^c, 1) on the 0..255 scale;
+  * default transmission ("he"): t = max(1 - omega * dark(I / A), t0), where
+    dark(I / A) is the patch minimum of min_c I^c / A^c; the literal Eq. (4)
+    ("paper"): t = max(1 - omega * min_c I^c(x) / max_c A^c, t0), pointwise;
+  * the guided filter refines the clamped t with the BT.601 luma of the hazy
+    input scaled to [0, 1] as guide, and its output is clamped to [t0, 1];
+  * J is clamped to [0, 255] before the gamma of Eq. (8);
+  * colour balance is gray-world on the gamma-corrected image:
+    g_c = mean(mu) / mu_c (g_c = 1 when mu_c = 0), J_c <- min(255, g_c J_c);
+  * the output is rounded half to even and saturated to uint8.
+All functions are pinned by tests against brute force, closed forms,
+invariants or independent library routines (scipy.ndimage).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def f32(x) -> float:
+    """The float32 value of a parameter, as a float64 (the ABI carries binary32)."""
+    return float(np.float32(x))
+
+
+@dataclass
+class Params:
+    mode: str = "realtime"         # "realtime" (no guided filter) or "offline"
+    patch: int = 15                # odd side of the square patch Omega
+    omega: float = 0.95            # transmission weight of Eq. (4)
+    t0: float = 0.1                # lower bound t_min of Eq. (5)
+    top_frac: float = 0.001        # fraction of pixels averaged in Eq. (3)
+    alpha: float = 0.8             # airlight scale of Eq. (3)
+    gamma: float = 1.2             # gamma of Eq. (8)
+    gf_radius: int = 60            # guided-filter box radius r
+    gf_eps: float = 1e-3           # guided-filter regulariser epsilon
+    color_balance: bool = False
+    tx: str = "he"                 # "he" (dark(I/A)) or "paper" (literal Eq. (4))
+
+    def f(self, name):
+        return f32(getattr(self, name))
+
+
+# ------------------------------------------------------------- Sec. IV-A
+def channel_min(I: np.ndarray) -> np.ndarray:
+    """min over c in {r,g,b} of I^c(x): the inner minimum of Eq. (2)."""
+    return I.min(axis=2)
+
+
+def _pad_value(x: np.ndarray):
+    if np.issubdtype(x.dtype, np.integer):
+        return np.iinfo(x.dtype).max
+    return np.inf
+
+
+def erode(x: np.ndarray, patch: int) -> np.ndarray:
+    """Minimum of x over the patch x patch window centred at each pixel.
+
+    The window is clipped to the frame: the frame is padded with a value no
+    smaller than any pixel, so padded cells never win.  Written as the
+    definition (the minimum over every offset in the window), vectorised over
+    pixels only.
+    """
+    assert patch >= 1 and patch % 2 == 1
+    r = (patch - 1) // 2
+    h, w = x.shape
+    pv = _pad_value(x)
+    pad = np.full((h + 2 * r, w + 2 * r), pv, dtype=x.dtype)
+    pad[r:r + h, r:r + w] = x
+    out = np.full((h, w), pv, dtype=x.dtype)
+    for dy in range(patch):
+        for dx in range(patch):
+            np.minimum(out, pad[dy:dy + h, dx:dx + w], out=out)
+    return out
+
+
+def erode_bruteforce(x: np.ndarray, patch: int) -> np.ndarray:
+    """Per-pixel loop over the clipped window (tiny inputs only)."""
+    r = (patch - 1) // 2
+    h, w = x.shape
+    out = np.empty_like(x)
+    for y in range(h):
+        for xx in range(w):
+            out[y, xx] = x[max(0, y - r):min(h, y + r + 1),
+                           max(0, xx - r):min(w, xx + r + 1)].min()
+    return out
+
+
+def dark_channel(I: np.ndarray, patch: int) -> np.ndarray:
+    """Eq. (2): D(x) = min over Omega(x) of min_c I^c."""
+    return erode(channel_min(I), patch)
+
+
+def channel_erosions(I: np.ndarray, patch: int) -> np.ndarray:
+    """E^c = erosion of each colour plane (H, W, 3)."""
+    return np.stack([erode(np.ascontiguousarray(I[:, :, c]), patch)
+                     for c in range(3)], axis=2)
+
+
+# ------------------------------------------------------------- Sec. IV-B
+def top_count(top_frac: float, n: int) -> int:
+    """K = max(1, floor(top_frac * N)), top_frac taken as its float32 value."""
+    return max(1, int(math.floor(f32(top_frac) * n)))
+
+
+@dataclass
+class Airlight:
+    A: np.ndarray          # (3,) float64, 0..255 scale
+    K: int
+    vstar: float           # dark-channel value of the last selected pixel
+    cutoff: int            # raster index of the last selected pixel with D == vstar
+    sel: np.ndarray        # (K,) raster indices of the selected pixels, in sort order
+    S: np.ndarray          # (3,) sum of I over the set
+
+
+def airlight(I: np.ndarray, D: np.ndarray, top_frac: float, alpha: float) -> Airlight:
+    """Eq. (3): A = alpha * (1/K) * sum_{i<=K} I(p_i) over the top-K dark pixels.
+
+    The pixels are fully sorted by (D descending, raster index ascending) and
+    the first K are taken.
+    """
+    h, w = D.shape
+    n = h * w
+    K = top_count(top_frac, n)
+    d = D.reshape(-1)
+    idx = np.arange(n)
+    order = np.lexsort((idx, -d.astype(np.float64)))
+    sel = order[:K]
+    last = sel[-1]
+    vstar = d[last]
+    cutoff = int(last)
+    Iflat = I.reshape(n, 3)
+    if np.issubdtype(I.dtype, np.integer):
+        S = Iflat[sel].astype(np.int64).sum(axis=0).astype(np.float64)
+    else:
+        S = Iflat[sel].astype(np.float64).sum(axis=0)
+    A = f32(alpha) * S / K
+    return Airlight(A=A, K=K, vstar=vstar, cutoff=cutoff, sel=sel, S=S)
+
+
+def airlight_divisor(A: np.ndarray) -> np.ndarray:
+    """A^c guarded as a divisor: max(A^c, 1) on the 0..255 scale."""
+    return np.maximum(A, 1.0)
+
+
+# ------------------------------------------------------------- Sec. IV-C
+def transmission_he(I: np.ndarray, A: np.ndarray, omega: float, t0: float,
+                    patch: int) -> np.ndarray:
+    """t = max(1 - omega * dark(I / A), t0), dark(I/A) = erode(min_c I^c / A^c)."""
+    Ad = airlight_divisor(A)
+    norm = (I.astype(np.float64) / Ad[None, None, :]).min(axis=2)
+    t_hat = 1.0 - f32(omega) * erode(norm, patch)
+    return np.maximum(t_hat, f32(t0))
+
+
+def transmission_paper(I: np.ndarray, A: np.ndarray, omega: float, t0: float) -> np.ndarray:
+    """Eqs. (4)-(5) as printed: t = max(1 - omega * min_c I^c(x) / max(A), t_min)."""
+    Amax = airlight_divisor(A).max()
+    m = channel_min(I).astype(np.float64)
+    t_hat = 1.0 - f32(omega) * m / Amax
+    return np.maximum(t_hat, f32(t0))
+
+
+# ------------------------------------------------------------- Sec. IV-D
+def luma(I: np.ndarray) -> np.ndarray:
+    """Grayscale guide: BT.601 luma of the hazy input, scaled to [0, 1]."""
+    I = I.astype(np.float64)
+    return (0.299 * I[:, :, 0] + 0.587 * I[:, :, 1] + 0.114 * I[:, :, 2]) / 255.0
+
+
+def box_sum(x: np.ndarray, r: int) -> np.ndarray:
+    """Sum of x over the (2r+1)^2 window clipped to the frame (integral image)."""
+    h, w = x.shape
+    S = np.zeros((h + 1, w + 1))
+    S[1:, 1:] = np.cumsum(np.cumsum(x.astype(np.float64), axis=0), axis=1)
+    ys = np.arange(h)
+    xs = np.arange(w)
+    y0 = np.clip(ys - r, 0, h)
+    y1 = np.clip(ys + r + 1, 0, h)
+    x0 = np.clip(xs - r, 0, w)
+    x1 = np.clip(xs + r + 1, 0, w)
+    return (S[np.ix_(y1, x1)] - S[np.ix_(y0, x1)]
+            - S[np.ix_(y1, x0)] + S[np.ix_(y0, x0)])
+
+
+def box_count(h: int, w: int, r: int) -> np.ndarray:
+    ys = np.arange(h)
+    xs = np.arange(w)
+    ch = np.minimum(ys + r, h - 1) - np.maximum(ys - r, 0) + 1
+    cw = np.minimum(xs + r, w - 1) - np.maximum(xs - r, 0) + 1
+    return np.outer(ch, cw).astype(np.float64)
+
+
+def box_mean(x: np.ndarray, r: int) -> np.ndarray:
+    """Mean of x over the clipped (2r+1)^2 window, normalised by its pixel count."""
+    return box_sum(x, r) / box_count(x.shape[0], x.shape[1], r)
+
+
+def box_mean_bruteforce(x: np.ndarray, r: int) -> np.ndarray:
+    h, w = x.shape
+    out = np.empty((h, w))
+    for y in range(h):
+        for xx in range(w):
+            out[y, xx] = x[max(0, y - r):min(h, y + r + 1),
+                           max(0, xx - r):min(w, xx + r + 1)].astype(np.float64).mean()
+    return out
+
+
+@dataclass
+class GuidedOut:
+    q: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+
+
+def guided_filter(p: np.ndarray, G: np.ndarray, r: int, eps: float) -> GuidedOut:
+    """Eq. (6) in the box-filter formulation of He et al. (2013):
+    a = cov(G,p) / (var(G) + eps), b = mean(p) - a mean(G),
+    q = mean(a) G + mean(b), every mean over the clipped (2r+1)^2 window.
+    """
+    mean_G = box_mean(G, r)
+    mean_p = box_mean(p, r)
+    corr_GG = box_mean(G * G, r)
+    corr_Gp = box_mean(G * p, r)
+    var_G = corr_GG - mean_G * mean_G
+    cov_Gp = corr_Gp - mean_G * mean_p
+    a = cov_Gp / (var_G + eps)
+    b = mean_p - a * mean_G
+    q = box_mean(a, r) * G + box_mean(b, r)
+    return GuidedOut(q=q, a=a, b=b)
+
+
+# ------------------------------------------------------------- Sec. IV-E
+def reconstruct(I: np.ndarray, A: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Eq. (7): J^c = (I^c - A^c) / t + A^c, then clamped to [0, 255]."""
+    I = I.astype(np.float64)
+    J = (I - A[None, None, :]) / t[..., None] + A[None, None, :]
+    return np.clip(J, 0.0, 255.0)
+
+
+def gamma_correct(J: np.ndarray, gamma: float) -> np.ndarray:
+    """Eq. (8): J_gamma = 255 (J / 255)^(1/gamma)."""
+    return 255.0 * np.power(J / 255.0, 1.0 / f32(gamma))
+
+
+def gray_world(Jg: np.ndarray):
+    """Gray-world colour balance: g_c = mean(mu) / mu_c, output clamped to 255."""
+    mu = Jg.reshape(-1, 3).mean(axis=0)
+    mbar = mu.mean()
+    gains = np.where(mu > 0.0, mbar / np.where(mu > 0.0, mu, 1.0), 1.0)
+    return np.minimum(255.0, Jg * gains[None, None, :]), gains
+
+
+def rne_u8(x: np.ndarray) -> np.ndarray:
+    """Round half to even and saturate to uint8."""
+    return np.clip(np.rint(x), 0, 255).astype(np.uint8)
+
+
+# ------------------------------------------------------------- Sec. V
+@dataclass
+class Result:
+    out: np.ndarray
+    aux: dict = field(default_factory=dict)
+
+
+def dehaze(I: np.ndarray, p: Params, A_inject=None) -> Result:
+    """One frame through the per-frame algorithm of Sec. V (steps 2-7).
+
+    I: (H, W, 3) uint8 RGB, or float64 on the 0..255 scale (for the
+    exact-recovery checks; then A may be injected instead of estimated).
+    """
+    m = channel_min(I)
+    D = erode(m, p.patch)
+    aux = {"m": m, "D": D}
+    if A_inject is None:
+        air = airlight(I, D, p.top_frac, p.alpha)
+        A = air.A
+        aux.update(K=air.K, vstar=air.vstar, cutoff=air.cutoff, sel=air.sel, S=air.S)
+    else:
+        A = np.asarray(A_inject, dtype=np.float64)
+    aux["A"] = A
+    if p.tx == "he":
+        t = transmission_he(I, A, p.omega, p.t0, p.patch)
+    elif p.tx == "paper":
+        t = transmission_paper(I, A, p.omega, p.t0)
+    else:
+        raise ValueError(p.tx)
+    aux["t_coarse"] = t
+    if p.mode == "offline":
+        G = luma(I)
+        gf = guided_filter(t, G, p.gf_radius, p.f("gf_eps"))
+        t = np.clip(gf.q, p.f("t0"), 1.0)
+        aux["gf_a"] = gf.a
+        aux["gf_b"] = gf.b
+    elif p.mode != "realtime":
+        raise ValueError(p.mode)
+    aux["t"] = t
+    J = reconstruct(I, A, t)
+    aux["J"] = J
+    Jg = gamma_correct(J, p.gamma)
+    aux["Jg"] = Jg
+    if p.color_balance:
+        Jf, gains = gray_world(Jg)
+    else:
+        Jf, gains = Jg, np.ones(3)
+    aux["gains"] = gains
+    aux["Jf"] = Jf
+    return Result(out=rne_u8(Jf), aux=aux)

@@ -1,0 +1,362 @@
+"""Pins for the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a hand-worked
+example, brute force, an independent library routine (scipy.ndimage), a
+closed form, or an invariant that a plausible slip (a dropped term, a wrong
+sign, a transposed operand, a wrong tie-break) would break.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from oracle import Params
+from synth import make_frame
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ------------------------------------------------------------ dark channel
+SHAPES = [(1, 1), (1, 7), (7, 1), (5, 9), (16, 23), (3, 40), (12, 12)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("patch", [1, 3, 5, 15, 31])
+def test_erode_matches_bruteforce(shape, patch):
+    x = rng(hash((shape, patch)) & 0xffff).integers(0, 256, size=shape, dtype=np.uint8)
+    assert np.array_equal(oracle.erode(x, patch), oracle.erode_bruteforce(x, patch))
+
+
+@pytest.mark.parametrize("patch", [3, 7, 15])
+def test_erode_matches_scipy(patch):
+    # an independent library routine: padding with 255 equals a clipped window
+    x = rng(patch).integers(0, 256, size=(37, 53), dtype=np.uint8)
+    ref = ndimage.minimum_filter(x, size=patch, mode="constant", cval=255)
+    assert np.array_equal(oracle.erode(x, patch), ref)
+
+
+def test_erode_closed_forms():
+    x = np.full((20, 30), 77, dtype=np.uint8)
+    assert np.array_equal(oracle.erode(x, 15), x)                 # constant stays constant
+    y = rng(0).integers(0, 256, size=(9, 11), dtype=np.uint8)
+    assert np.array_equal(oracle.erode(y, 1), y)                  # p = 1 is the identity
+    z = np.full((20, 30), 200, dtype=np.uint8)
+    z[2, 27] = 5                                                  # one dark pixel near a corner
+    e = oracle.erode(z, 7)
+    expect = np.full((20, 30), 200, dtype=np.uint8)
+    expect[0:6, 24:30] = 5                                        # clipped 7x7 square
+    assert np.array_equal(e, expect)
+
+
+def test_dark_is_min_of_channel_erosions():
+    I = rng(1).integers(0, 256, size=(31, 45, 3), dtype=np.uint8)
+    D = oracle.dark_channel(I, 15)
+    E = oracle.channel_erosions(I, 15)
+    assert np.array_equal(D, E.min(axis=2))
+
+
+def test_hand_example_dark_and_airlight():
+    g = json.load(open(os.path.join(GOLDEN, "hand_dark_airlight.json")))
+    I = np.array(g["frame_rgb"], dtype=np.uint8)
+    assert np.array_equal(oracle.channel_min(I), np.array(g["channel_min"]))
+    D = oracle.dark_channel(I, g["patch"])
+    assert np.array_equal(D, np.array(g["dark"]))
+    for case in g["cases"]:
+        air = oracle.airlight(I, D, case["top_frac"], g["alpha"])
+        assert air.K == case["K"]
+        assert air.vstar == case["vstar"]
+        assert air.cutoff == case["cutoff"]
+        assert list(air.sel) == case["set"]
+        assert list(air.S) == case["S"]
+        a32 = float(np.float32(g["alpha"]))
+        assert np.array_equal(air.A, a32 * np.array(case["S"], dtype=np.float64) / case["K"])
+
+
+# ---------------------------------------------------------------- airlight
+def _python_topk(D, K):
+    h, w = D.shape
+    keyed = sorted(((-int(D[y, x]), y * w + x) for y in range(h) for x in range(w)))
+    return [i for _, i in keyed[:K]]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_airlight_set_matches_python_sort(seed):
+    r = rng(100 + seed)
+    h, w = int(r.integers(1, 24)), int(r.integers(1, 24))
+    # few distinct values -> massive ties, as with real uint8 dark channels
+    D = r.integers(0, 4, size=(h, w)).astype(np.uint8) * 60
+    I = r.integers(0, 256, size=(h, w, 3), dtype=np.uint8)
+    top = float(r.uniform(0.01, 0.5))
+    air = oracle.airlight(I, D, top, 0.8)
+    K = max(1, math.floor(float(np.float32(top)) * h * w))
+    assert air.K == K
+    assert list(air.sel) == _python_topk(D, K)
+
+
+def test_airlight_set_is_lexicographic_threshold():
+    r = rng(7)
+    D = r.integers(180, 200, size=(64, 80)).astype(np.uint8)
+    I = r.integers(0, 256, size=(64, 80, 3), dtype=np.uint8)
+    air = oracle.airlight(I, D, 0.01, 0.8)
+    d = D.reshape(-1)
+    inset = np.zeros(d.size, bool)
+    inset[air.sel] = True
+    assert inset.sum() == air.K
+    # every pixel outside the set is below (vstar, cutoff) in the (D desc, idx asc) order
+    out_idx = np.nonzero(~inset)[0]
+    assert np.all((d[out_idx] < air.vstar) | ((d[out_idx] == air.vstar) & (out_idx > air.cutoff)))
+    in_idx = np.nonzero(inset)[0]
+    assert np.all((d[in_idx] > air.vstar) | ((d[in_idx] == air.vstar) & (in_idx <= air.cutoff)))
+
+
+def test_uniform_frame_selects_first_k_raster_pixels():
+    I = np.full((20, 50, 3), (90, 120, 150), dtype=np.uint8)
+    D = oracle.dark_channel(I, 15)
+    air = oracle.airlight(I, D, 0.05, 0.8)
+    assert air.K == 50
+    assert list(air.sel) == list(range(50))
+    a32 = float(np.float32(0.8))
+    assert np.array_equal(air.A, a32 * np.array([90.0, 120.0, 150.0]))
+
+
+def test_sky_region_gives_alpha_times_sky():
+    fr = make_frame(320, 240, 11, beta=1.0)
+    I = fr.I.copy()
+    sky = np.array([217, 224, 229], dtype=np.uint8)
+    I[:40, :, :] = sky                  # 12800 px > K + erosion margin
+    D = oracle.dark_channel(I, 15)
+    air = oracle.airlight(I, D, 0.001, 0.8)
+    a32 = float(np.float32(0.8))
+    assert np.array_equal(air.A, a32 * sky.astype(np.float64))
+
+
+def test_unique_maxima_are_selected():
+    I = np.full((30, 40, 3), 40, dtype=np.uint8)
+    spots = [(3, 5), (20, 33), (27, 2)]
+    for (y, x) in spots:
+        I[max(0, y - 7):y + 8, max(0, x - 7):x + 8] = (200, 210, 220)
+    D = oracle.dark_channel(I, 1)
+    air = oracle.airlight(I, D, 3 / 1200 + 1e-6, 0.8)
+    assert air.K == 3
+    assert air.vstar == 200
+    # the first three raster pixels of the bright squares
+    bright = np.nonzero(D.reshape(-1) == 200)[0][:3]
+    assert list(air.sel) == list(bright)
+
+
+@pytest.mark.parametrize("wh,K", [((320, 240), 76), ((640, 480), 307), ((1280, 720), 921),
+                                  ((1920, 1080), 2073), ((3840, 2160), 8294)])
+def test_top_count_at_config_sizes(wh, K):
+    assert oracle.top_count(0.001, wh[0] * wh[1]) == K
+
+
+def test_bright_blob_captures_the_airlight():
+    # the limitation the paper notes: a large bright region (a headlight)
+    # takes over the top-K set and A follows it
+    fr = make_frame(320, 240, 12, beta=1.0)
+    I = fr.I.copy()
+    I[100:140, 100:160] = 255
+    D = oracle.dark_channel(I, 15)
+    air = oracle.airlight(I, D, 0.001, 0.8)
+    assert air.vstar == 255
+    assert np.allclose(air.A, float(np.float32(0.8)) * 255.0)
+
+
+# ------------------------------------------------------------ transmission
+def test_transmission_bounds_and_omega_zero():
+    fr = make_frame(96, 64, 3, beta=1.3)
+    D = oracle.dark_channel(fr.I, 15)
+    A = oracle.airlight(fr.I, D, 0.001, 0.8).A
+    for tx in ("he", "paper"):
+        for om in (0.0, 0.5, 0.95, 1.0):
+            if tx == "he":
+                t = oracle.transmission_he(fr.I, A, om, 0.1, 15)
+            else:
+                t = oracle.transmission_paper(fr.I, A, om, 0.1)
+            assert t.min() >= float(np.float32(0.1)) and t.max() <= 1.0
+            if om == 0.0:
+                assert np.all(t == 1.0)
+
+
+def test_transmission_he_commutes_with_erosion():
+    # dark(I/A) = min_c erode(I^c)/A^c exactly: erosion commutes with a positive
+    # per-channel scale and with the channel minimum
+    I = rng(5).integers(0, 256, size=(40, 33, 3), dtype=np.uint8)
+    A = np.array([180.3, 201.7, 222.9])
+    E = oracle.channel_erosions(I, 15).astype(np.float64)
+    via_E = (E / A[None, None, :]).min(axis=2)
+    t1 = np.maximum(1.0 - float(np.float32(0.95)) * via_E, float(np.float32(0.1)))
+    t2 = oracle.transmission_he(I, A, 0.95, 0.1, 15)
+    assert np.array_equal(t1, t2)
+
+
+def test_transmission_paper_hand_value():
+    I = np.zeros((1, 1, 3), dtype=np.uint8)
+    I[0, 0] = (100, 60, 200)
+    A = np.array([150.0, 160.0, 170.0])
+    t = oracle.transmission_paper(I, A, 0.5, 0.05)
+    w = float(np.float32(0.5))
+    assert t[0, 0] == 1.0 - w * 60.0 / 170.0
+
+
+# ---------------------------------------------------------- exact recovery
+def _zero_channel_scene(h, w, seed):
+    r = rng(seed)
+    J = r.uniform(0.05, 0.95, size=(h, w, 3)) * 255.0
+    zc = r.integers(0, 3, size=(h, w))
+    for c in range(3):
+        J[:, :, c][zc == c] = 0.0
+    return J
+
+
+@pytest.mark.parametrize("t_const", [0.35, 0.8])
+def test_exact_recovery_constant_t(t_const):
+    # I = J t + A (1 - t) in float64 with a zero channel at every pixel: the prior
+    # holds exactly, so dark(I/A) = 1 - t and, with omega = 1, J is recovered
+    J = _zero_channel_scene(40, 56, 1)
+    A = np.array([0.85, 0.88, 0.90]) * 255.0
+    t = np.full(J.shape[:2], t_const)
+    I = J * t[..., None] + A * (1.0 - t[..., None])
+    p = Params(mode="realtime", omega=1.0, t0=0.01, gamma=1.0, tx="he")
+    res = oracle.dehaze(I, p, A_inject=A)
+    assert np.max(np.abs(res.aux["t"] - t)) <= 1e-12
+    assert np.max(np.abs(res.aux["J"] - J)) <= 1e-12
+
+
+def test_exact_recovery_piecewise_t_interior():
+    J = _zero_channel_scene(64, 96, 2)
+    A = np.array([0.84, 0.87, 0.91]) * 255.0
+    t = np.full(J.shape[:2], 0.3)
+    t[:, 48:] = 0.7
+    t[32:, :] = 0.5
+    I = J * t[..., None] + A * (1.0 - t[..., None])
+    p = Params(mode="realtime", omega=1.0, t0=0.01, gamma=1.0, tx="he", patch=7)
+    res = oracle.dehaze(I, p, A_inject=A)
+    r = 3
+    interior = np.ones(t.shape, bool)
+    for edge in (48,):
+        interior[:, edge - r:edge + r] = False
+    interior[32 - r:32 + r, :] = False
+    err_t = np.abs(res.aux["t"] - t)[interior]
+    err_J = np.abs(res.aux["J"] - J)[interior]
+    assert err_t.max() <= 1e-12 and err_J.max() <= 1e-12
+
+
+def test_recovery_from_synth_uint8_is_close():
+    # the quantised generator frame: the recovered t tracks the true t
+    fr = make_frame(320, 240, 1, beta=1.0)
+    p = Params(mode="realtime", omega=1.0, t0=0.05, gamma=1.0, tx="he")
+    res = oracle.dehaze(fr.I, p, A_inject=fr.A * 255.0)
+    err = np.abs(res.aux["t"] - fr.t)
+    assert np.median(err) < 0.03
+
+
+# ----------------------------------------------------------- guided filter
+def test_box_mean_matches_bruteforce_and_scipy():
+    x = rng(9).uniform(size=(23, 31))
+    for r in (0, 1, 3, 8, 40):
+        bm = oracle.box_mean(x, r)
+        assert np.allclose(bm, oracle.box_mean_bruteforce(x, r), rtol=0, atol=1e-13)
+        ones = np.ones_like(x)
+        size = 2 * r + 1
+        ref = (ndimage.uniform_filter(x, size=size, mode="constant", cval=0.0)
+               / ndimage.uniform_filter(ones, size=size, mode="constant", cval=0.0))
+        assert np.allclose(bm, ref, rtol=0, atol=1e-12)
+
+
+def test_guided_filter_identity_on_constant_input():
+    G = rng(3).uniform(size=(40, 50))
+    p = np.full((40, 50), 0.42)
+    q = oracle.guided_filter(p, G, 6, 1e-3).q
+    assert np.max(np.abs(q - p)) <= 1e-12   # integral-image rounding only
+
+
+def test_guided_filter_identity_when_input_is_guide():
+    G = rng(4).uniform(size=(30, 30))   # var > 0 in every window
+    q = oracle.guided_filter(G, G, 3, 0.0).q
+    assert np.max(np.abs(q - G)) <= 1e-12
+
+
+def test_guided_filter_constant_guide_is_box_of_box():
+    G = np.full((25, 33), 0.5)
+    p = rng(6).uniform(size=(25, 33))
+    r = 4
+    q = oracle.guided_filter(p, G, r, 1e-3).q
+    ref = oracle.box_mean_bruteforce(oracle.box_mean_bruteforce(p, r), r)
+    assert np.max(np.abs(q - ref)) <= 1e-13
+
+
+def test_guided_filter_hand_scalar_case():
+    # 1x1 frame: every window is the pixel itself, var = cov = 0, q = p
+    G = np.array([[0.3]])
+    p = np.array([[0.7]])
+    gf = oracle.guided_filter(p, G, 5, 1e-3)
+    assert gf.a[0, 0] == 0.0 and gf.b[0, 0] == 0.7 and gf.q[0, 0] == 0.7
+
+
+def test_luma_weights():
+    I = np.array([[[255, 0, 0], [0, 255, 0], [0, 0, 255], [255, 255, 255]]], dtype=np.uint8)
+    g = oracle.luma(I)
+    assert np.allclose(g[0], [0.299, 0.587, 0.114, 1.0], rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------- reconstruction and post
+def test_reconstruct_hand_value_and_clamp():
+    I = np.array([[[100, 200, 50]]], dtype=np.uint8)
+    A = np.array([150.0, 150.0, 150.0])
+    t = np.array([[0.5]])
+    J = oracle.reconstruct(I, A, t)
+    assert np.array_equal(J[0, 0], [50.0, 250.0, 0.0])   # (50-150)/.5+150 = -50 -> 0
+
+
+def test_gamma_closed_forms():
+    J = np.linspace(0, 255, 101)
+    assert np.array_equal(oracle.gamma_correct(J, 1.0), J)
+    assert abs(oracle.gamma_correct(np.array([127.5]), 2.0)[0] - 255.0 * math.sqrt(0.5)) < 1e-12
+    g = float(np.float32(1.2))
+    assert abs(oracle.gamma_correct(np.array([51.0]), 1.2)[0] - 255.0 * 0.2 ** (1.0 / g)) < 1e-12
+
+
+def test_gray_world_identity_and_known_gains():
+    gray = np.full((8, 8, 3), 100.0)
+    out, gains = oracle.gray_world(gray)
+    assert np.array_equal(out, gray) and np.array_equal(gains, [1, 1, 1])
+    img = np.empty((4, 4, 3))
+    img[..., 0], img[..., 1], img[..., 2] = 60.0, 120.0, 180.0
+    out, gains = oracle.gray_world(img)
+    assert np.allclose(gains, [2.0, 1.0, 2.0 / 3.0], rtol=0, atol=1e-15)
+    assert np.allclose(out, 120.0)
+    img[..., 2] = 0.0
+    out, gains = oracle.gray_world(img)
+    assert gains[2] == 1.0
+
+
+def test_rne():
+    x = np.array([0.5, 1.5, 2.5, 254.5, 255.4, -3.0, 300.0])
+    assert list(oracle.rne_u8(x)) == [0, 2, 2, 254, 255, 0, 255]
+
+
+# ----------------------------------------------------------- whole frame
+@pytest.mark.parametrize("tx", ["he", "paper"])
+def test_pipeline_is_identity_with_omega_zero(tx):
+    fr = make_frame(64, 48, 8, beta=1.2)
+    p = Params(mode="realtime", omega=0.0, gamma=1.0, tx=tx)
+    res = oracle.dehaze(fr.I, p)
+    assert np.array_equal(res.out, fr.I)
+
+
+def test_pipeline_offline_runs_and_bounds():
+    fr = make_frame(96, 80, 9)
+    p = Params(mode="offline", gf_radius=8, color_balance=True)
+    res = oracle.dehaze(fr.I, p)
+    t = res.aux["t"]
+    assert t.min() >= float(np.float32(0.1)) and t.max() <= 1.0
+    assert res.out.dtype == np.uint8 and res.out.shape == fr.I.shape
