@@ -1,0 +1,235 @@
+/*
+ * hzd.h -- C ABI of the MI355X (gfx950) per-frame dark-channel-prior dehazing
+ * library (Hazedefy, arXiv 2512.16609).
+ *
+ * The library recovers the scene radiance J from a hazy frame I under the
+ * atmospheric scattering model I = J t + A (1 - t) (paper Sec. III, Eq. (1))
+ * by estimating the global airlight A and the transmission t.  One frame runs
+ * the paper's per-frame steps (Sec. V):
+ *
+ *   channel minimum + patch erosion -> dark channel D        Sec. IV-A, Eq. (2)
+ *   fractional top-pixel average    -> airlight A            Sec. IV-B, Eq. (3)
+ *   transmission with lower bound   -> t                     Sec. IV-C, Eqs. (4)-(5)
+ *   guided-filter refinement (offline mode only)             Sec. IV-D, Eq. (6)
+ *   radiance recovery, gamma, optional colour balance       Sec. IV-E, Eqs. (7)-(8)
+ *
+ * Conventions for every call:
+ *   - Pixel buffers are HIP device pointers to packed 8-bit RGB, row-major,
+ *     channel-interleaved (R,G,B per pixel), with a row pitch in bytes
+ *     (pitch >= 3 * width).  The caller owns them; they must stay valid until
+ *     the work is complete in stream order (frame/batch) or until the ticket
+ *     completes (served).
+ *   - `hip_stream` is a hipStream_t (NULL = the null stream).  frame/batch
+ *     calls are asynchronous: they return once the work is enqueued.
+ *   - Every call returns an hzd_status.  Arguments are validated before any
+ *     device work is enqueued, so a call that returns an error has no side
+ *     effects.  hzd_last_error() gives a thread-local description.
+ *   - No call aborts or throws across the ABI.  frame/batch never allocate
+ *     device memory: scratch comes from the caller's workspace.
+ */
+#ifndef HZD_H
+#define HZD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HZD_ABI_VERSION 1
+
+typedef enum {
+  HZD_OK = 0,
+  HZD_E_INVAL = -1,        /* an argument is out of range or inconsistent      */
+  HZD_E_NOMEM = -2,        /* workspace/arena too small                        */
+  HZD_E_DEVICE = -3,       /* a HIP call failed (detail in hzd_last_error)     */
+  HZD_E_AGAIN = -4,        /* no admission budget or queue space right now     */
+  HZD_E_CLOSED = -5,       /* the stream/server is closed; the frame was dropped */
+  HZD_E_UNSUPPORTED = -6,  /* valid request outside what this build implements */
+  HZD_E_TIMEOUT = -7       /* hzd_stream_wait timed out                        */
+} hzd_status;
+
+/* Sec. I / Sec. V: real-time video mode skips the guided filter; offline
+ * image mode refines t with it (Fig. 2, "Image Mode?" branch). */
+typedef enum { HZD_MODE_REALTIME = 0, HZD_MODE_OFFLINE = 1 } hzd_mode;
+
+/* Transmission estimate (Sec. IV-C).
+ *   HZD_TX_HE    t = max(1 - omega * dark(I / A), t0), where dark(I/A) is the
+ *                patch minimum of min_c I^c / A^c (the dark-channel form).
+ *   HZD_TX_PAPER t = max(1 - omega * min_c I^c(x) / max_c A^c, t0), the
+ *                pointwise expression printed as Eq. (4). */
+typedef enum { HZD_TX_HE = 0, HZD_TX_PAPER = 1 } hzd_tx;
+
+/* Precision of the transmission carried into Eq. (7).  FP32: binary32
+ * throughout.  FP16: t is rounded to binary16 (and stored maps are binary16);
+ * J and the gamma of Eq. (8) are still formed in binary32. */
+typedef enum { HZD_PREC_FP32 = 0, HZD_PREC_FP16 = 1 } hzd_prec;
+
+typedef enum {
+  HZD_PRESET_REALTIME = 0,       /* patch 15, omega .95, t0 .1, top .001, gamma 1.2 */
+  HZD_PRESET_OFFLINE = 1,        /* as REALTIME + guided filter r 60, eps 1e-3, colour balance */
+  HZD_PRESET_PAPER_REALTIME = 2  /* the shipped real-time values of Sec. IV-C: omega .5, t_min .05, TX_PAPER */
+} hzd_preset;
+
+/* Parameters of one frame.  Ranges are checked by every call.
+ *   size           must equal sizeof(hzd_params)
+ *   mode           hzd_mode
+ *   patch          odd side of the square patch Omega of Eq. (2), 1..31 (paper: 15)
+ *   omega          transmission weight of Eq. (4), [0, 1]
+ *   t0             lower bound t_min of Eq. (5), (0, 1]
+ *   top_frac       fraction of pixels averaged in Eq. (3), (0, 1];
+ *                  K = max(1, floor(top_frac * W * H)); ties in D are broken
+ *                  by the lower raster index y * W + x
+ *   alpha          airlight scale of Eq. (3), (0, 1] (paper: 0.8)
+ *   gamma          gamma of Eq. (8), [0.1, 10]
+ *   gf_radius      guided-filter box radius r (OFFLINE), 1..64
+ *   gf_eps         guided-filter regulariser (OFFLINE), [1e-8, 1]; the guide is
+ *                  the BT.601 luma of the hazy input scaled to [0, 1]
+ *   color_balance  0/1: gray-world gains on the gamma-corrected image (Sec. IV-E)
+ *   tx             hzd_tx
+ *   precision      hzd_prec */
+typedef struct hzd_params {
+  uint32_t size;
+  int32_t mode;
+  int32_t patch;
+  float omega;
+  float t0;
+  float top_frac;
+  float alpha;
+  float gamma;
+  int32_t gf_radius;
+  float gf_eps;
+  int32_t color_balance;
+  int32_t tx;
+  int32_t precision;
+} hzd_params;
+
+/* One frame: device pointers and geometry (see the conventions above).
+ * width, height >= 1 and width * height < 2^31.  src and dst must not overlap.
+ * params: NULL = the params given to the call; in a batch, a per-frame
+ * override (host pointer, read during the call only). */
+typedef struct hzd_frame {
+  const uint8_t* src;
+  int64_t src_pitch;
+  uint8_t* dst;
+  int64_t dst_pitch;
+  int32_t width;
+  int32_t height;
+  const hzd_params* params;
+} hzd_frame;
+
+/* Optional per-frame device outputs for inspection (NULL = not written).
+ *   A_out    3 floats: A^c of Eq. (3) on the 0..255 scale
+ *   sel_out  3 int32: {K, vstar, cutoff}; the selected set of Eq. (3) is
+ *            {D > vstar} U {D == vstar and raster index <= cutoff}
+ *   dark_out width*height bytes (pitch = width): D of Eq. (2)
+ *   t_out    width*height floats: the t used in Eq. (7) (after the guided
+ *            filter in OFFLINE mode)
+ *   J_out    width*height*3 floats: J of Eq. (7) clamped to [0, 255], before
+ *            the gamma of Eq. (8) */
+typedef struct hzd_frame_aux {
+  float* A_out;
+  int32_t* sel_out;
+  uint8_t* dark_out;
+  float* t_out;
+  float* J_out;
+} hzd_frame_aux;
+
+/* Fill *p with a preset (hzd_preset).  Returns HZD_E_INVAL for an unknown preset. */
+int hzd_params_default(hzd_params* p, int32_t preset);
+
+/* Bytes of device workspace that hzd_dehaze_frame (n = 1) or hzd_dehaze_batch
+ * needs for these frames (width/height/params are read; pointers are not).
+ * The workspace must be 256-byte aligned. */
+int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_t n,
+                       size_t* bytes);
+
+/* Dehaze one frame (Sec. V, steps 2-7) on `hip_stream`.
+ * workspace: device memory of at least hzd_workspace_size bytes, owned by the
+ * caller, used exclusively by this call until it completes in stream order.
+ * aux may be NULL.  Errors: INVAL (arguments), NOMEM (workspace too small),
+ * UNSUPPORTED (e.g. patch > 31), DEVICE (a launch failed). */
+int hzd_dehaze_frame(const hzd_params* params, const hzd_frame* frame,
+                     const hzd_frame_aux* aux, void* workspace, size_t ws_bytes,
+                     void* hip_stream);
+
+/* Dehaze n independent frames of possibly different sizes and parameters as
+ * one batch: frames sharing (mode, patch, tx, colour balance, precision,
+ * radius) are processed by the same launches.  Each frame's result equals
+ * its hzd_dehaze_frame result bit for bit.  aux: NULL or an array of n. */
+int hzd_dehaze_batch(const hzd_params* params, const hzd_frame* frames, int32_t n,
+                     const hzd_frame_aux* aux, void* workspace, size_t ws_bytes,
+                     void* hip_stream);
+
+/* ---------------------------------------------------------------- serving
+ * A server owns a scheduler thread and a few HIP streams on one device.
+ * Streams of frames (each of one size and one parameter set) are opened
+ * against it; each opened stream reserves its device state and workspace in
+ * the caller's arena (admission by HBM budget).  Submitted frames are queued
+ * and launched in batches as slots free up, so frames that arrive while
+ * others run join the next launch (continuous batching).  The method is
+ * feed-forward per frame (Sec. V), so a served frame's output equals its
+ * hzd_dehaze_frame output. */
+typedef struct hzd_server hzd_server;
+typedef struct hzd_stream hzd_stream;
+
+/* size              = sizeof(hzd_server_config)
+ * device            HIP device ordinal
+ * arena, arena_bytes caller-owned device memory (256-byte aligned) that
+ *                   stream state and workspaces are carved from
+ * max_inflight      frames on the device at once (>= 1)
+ * frames_per_launch largest batch per launch (1..16)
+ * hip_streams       HIP streams the server launches on (1..8)             */
+typedef struct hzd_server_config {
+  uint32_t size;
+  int32_t device;
+  void* arena;
+  size_t arena_bytes;
+  int32_t max_inflight;
+  int32_t frames_per_launch;
+  int32_t hip_streams;
+} hzd_server_config;
+
+/* Completion callback, called on the scheduler thread.  latency_ns is from
+ * hzd_stream_submit to the host observing completion. */
+typedef void (*hzd_done_fn)(void* user, uint64_t ticket, int32_t status, int64_t latency_ns);
+
+int hzd_server_create(const hzd_server_config* cfg, hzd_server** out);
+/* Cancels queued frames (their callbacks get HZD_E_CLOSED), waits for frames
+ * on the device, closes all streams and frees the server. */
+int hzd_server_destroy(hzd_server* s);
+
+/* Open a stream of width x height frames with these parameters.
+ * HZD_E_AGAIN when the arena cannot hold its state right now. */
+int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int32_t height,
+                    hzd_stream** out);
+/* Queue one frame (frame->width/height must match the stream; params ignored).
+ * Returns at once with a ticket.  HZD_E_AGAIN when the queue is full. */
+int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
+                      uint64_t* ticket);
+/* Wait until `ticket` completes (timeout_ns < 0: forever).  Returns the
+ * frame's status, or HZD_E_TIMEOUT. */
+int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns);
+/* Per-stream device state as of the last completed frame: A (3 floats) and
+ * {K, vstar, cutoff}; host pointers, either may be NULL. */
+int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host);
+/* Wait for the stream's frames, release its arena space and free it. */
+int hzd_stream_close(hzd_stream* st);
+
+typedef struct hzd_server_stats {
+  uint64_t submitted, completed, failed, launches;
+  uint64_t arena_used, arena_bytes;
+  int32_t open_streams, inflight;
+} hzd_server_stats;
+int hzd_server_stats_get(hzd_server* s, hzd_server_stats* out);
+
+const char* hzd_status_str(int32_t status);
+/* Thread-local text for the last failing call on this thread ("" if none). */
+const char* hzd_last_error(void);
+int hzd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HZD_H */

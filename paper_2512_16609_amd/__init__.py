@@ -1,0 +1,334 @@
+"""Python binding of libhzd, the MI355X per-frame dark-channel-prior dehazing library.
+
+Argument marshalling only: every step of the method runs in the library's
+gfx950 kernels.  torch supplies device memory and HIP streams.  The names
+follow the C ABI in include/hzd.h (hzd_dehaze_frame -> dehaze_frame, ...).
+
+The library is loaded from this package directory (built in-tree by
+build_lib.build()).  There is no fallback: if the library is missing or no
+GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhzd.so")
+
+HZD_OK, HZD_E_INVAL, HZD_E_NOMEM, HZD_E_DEVICE = 0, -1, -2, -3
+HZD_E_AGAIN, HZD_E_CLOSED, HZD_E_UNSUPPORTED, HZD_E_TIMEOUT = -4, -5, -6, -7
+MODE_REALTIME, MODE_OFFLINE = 0, 1
+TX_HE, TX_PAPER = 0, 1
+PREC_FP32, PREC_FP16 = 0, 1
+PRESET_REALTIME, PRESET_OFFLINE, PRESET_PAPER_REALTIME = 0, 1, 2
+
+
+class HzdError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: status {status} ({detail})")
+        self.status = status
+
+
+class hzd_params(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("patch", ctypes.c_int32),
+                ("omega", ctypes.c_float), ("t0", ctypes.c_float), ("top_frac", ctypes.c_float),
+                ("alpha", ctypes.c_float), ("gamma", ctypes.c_float), ("gf_radius", ctypes.c_int32),
+                ("gf_eps", ctypes.c_float), ("color_balance", ctypes.c_int32), ("tx", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class hzd_frame(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("src_pitch", ctypes.c_int64), ("dst", ctypes.c_void_p),
+                ("dst_pitch", ctypes.c_int64), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("params", ctypes.POINTER(hzd_params))]
+
+
+class hzd_frame_aux(ctypes.Structure):
+    _fields_ = [("A_out", ctypes.c_void_p), ("sel_out", ctypes.c_void_p), ("dark_out", ctypes.c_void_p),
+                ("t_out", ctypes.c_void_p), ("J_out", ctypes.c_void_p)]
+
+
+class hzd_server_config(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("device", ctypes.c_int32), ("arena", ctypes.c_void_p),
+                ("arena_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("frames_per_launch", ctypes.c_int32), ("hip_streams", ctypes.c_int32)]
+
+
+class hzd_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("arena_used", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("open_streams", ctypes.c_int32),
+                ("inflight", ctypes.c_int32)]
+
+
+DONE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64)
+
+_lib = None
+_lib_lock = threading.Lock()
+
+SYMBOLS = {
+    "hzd_abi_version": (ctypes.c_int, []),
+    "hzd_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "hzd_last_error": (ctypes.c_char_p, []),
+    "hzd_params_default": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.c_int32]),
+    "hzd_workspace_size": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame),
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "hzd_dehaze_frame": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame),
+                                        ctypes.POINTER(hzd_frame_aux), ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p]),
+    "hzd_dehaze_batch": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame),
+                                        ctypes.c_int32, ctypes.POINTER(hzd_frame_aux), ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p]),
+    "hzd_server_create": (ctypes.c_int, [ctypes.POINTER(hzd_server_config), ctypes.POINTER(ctypes.c_void_p)]),
+    "hzd_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "hzd_stream_open": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_params), ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "hzd_stream_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_frame), DONE_FN, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "hzd_stream_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64]),
+    "hzd_stream_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "hzd_stream_close": (ctypes.c_int, [ctypes.c_void_p]),
+    "hzd_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_server_stats)]),
+}
+
+
+def lib():
+    """Load libhzd.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is not built; run paper_2512_16609_amd.build_lib.build()")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SYMBOLS.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().hzd_last_error().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != HZD_OK:
+        raise HzdError(rc, what, f"{lib().hzd_status_str(rc).decode()}: {last_error()}")
+    return rc
+
+
+# ------------------------------------------------------------------ params
+@dataclass
+class Params:
+    mode: int = MODE_REALTIME
+    patch: int = 15
+    omega: float = 0.95
+    t0: float = 0.1
+    top_frac: float = 0.001
+    alpha: float = 0.8
+    gamma: float = 1.2
+    gf_radius: int = 60
+    gf_eps: float = 1e-3
+    color_balance: int = 0
+    tx: int = TX_HE
+    precision: int = PREC_FP32
+
+    def c(self) -> hzd_params:
+        return hzd_params(ctypes.sizeof(hzd_params), self.mode, self.patch, self.omega, self.t0,
+                          self.top_frac, self.alpha, self.gamma, self.gf_radius, self.gf_eps,
+                          int(self.color_balance), self.tx, self.precision)
+
+    @staticmethod
+    def preset(preset: int) -> "Params":
+        p = hzd_params()
+        _check(lib().hzd_params_default(ctypes.byref(p), preset), "hzd_params_default")
+        return Params(p.mode, p.patch, p.omega, p.t0, p.top_frac, p.alpha, p.gamma, p.gf_radius,
+                      p.gf_eps, p.color_balance, p.tx, p.precision)
+
+
+# ------------------------------------------------------------------ frames
+def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params_ptr=None) -> hzd_frame:
+    for name, t in (("src", src), ("dst", dst)):
+        if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3:
+            raise ValueError(f"{name} must be a uint8 (H, W, 3) tensor")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be on the GPU")
+        if t.stride(2) != 1 or t.stride(1) != 3:
+            raise ValueError(f"{name} must have packed RGB rows (strides (pitch, 3, 1))")
+    if src.shape != dst.shape:
+        raise ValueError("src and dst shapes differ")
+    h, w = int(src.shape[0]), int(src.shape[1])
+    f = hzd_frame(src.data_ptr(), src.stride(0) if h > 1 else 3 * w, dst.data_ptr(),
+                  dst.stride(0) if h > 1 else 3 * w, w, h, params_ptr)
+    return f
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _aux_struct(aux: dict | None) -> hzd_frame_aux | None:
+    if not aux:
+        return None
+    return hzd_frame_aux(_ptr(aux.get("A")), _ptr(aux.get("sel")), _ptr(aux.get("dark")),
+                         _ptr(aux.get("t")), _ptr(aux.get("J")))
+
+
+def make_aux(h: int, w: int, device="cuda", J: bool = True) -> dict:
+    """Device buffers for every optional per-frame output."""
+    d = {"A": torch.zeros(3, dtype=torch.float32, device=device),
+         "sel": torch.zeros(3, dtype=torch.int32, device=device),
+         "dark": torch.zeros((h, w), dtype=torch.uint8, device=device),
+         "t": torch.zeros((h, w), dtype=torch.float32, device=device)}
+    if J:
+        d["J"] = torch.zeros((h, w, 3), dtype=torch.float32, device=device)
+    return d
+
+
+def workspace_size(params: Params, shapes, per_frame_params=None) -> int:
+    """Workspace bytes for frames of the given (height, width) shapes."""
+    n = len(shapes)
+    pcs = [p.c() for p in per_frame_params] if per_frame_params else None
+    arr = (hzd_frame * n)()
+    for i, (h, w) in enumerate(shapes):
+        arr[i].width, arr[i].height = int(w), int(h)
+        if pcs:
+            arr[i].params = ctypes.pointer(pcs[i])
+    out = ctypes.c_size_t(0)
+    pc = params.c()
+    _check(lib().hzd_workspace_size(ctypes.byref(pc), arr, n, ctypes.byref(out)), "hzd_workspace_size")
+    return int(out.value)
+
+
+def alloc_workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def dehaze_frame(src: torch.Tensor, dst: torch.Tensor, params: Params, aux: dict | None = None,
+                 workspace: torch.Tensor | None = None, stream=None) -> None:
+    """hzd_dehaze_frame on a (H, W, 3) uint8 device tensor (asynchronous, stream-ordered)."""
+    f = _frame_struct(src, dst)
+    pc = params.c()
+    if workspace is None:
+        workspace = alloc_workspace(workspace_size(params, [(src.shape[0], src.shape[1])]), src.device)
+    a = _aux_struct(aux)
+    rc = lib().hzd_dehaze_frame(ctypes.byref(pc), ctypes.byref(f), ctypes.byref(a) if a else None,
+                                workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
+    _check(rc, "hzd_dehaze_frame")
+
+
+def dehaze_batch(srcs, dsts, params: Params, per_frame_params=None, auxs=None,
+                 workspace: torch.Tensor | None = None, stream=None) -> None:
+    """hzd_dehaze_batch over lists of (H_i, W_i, 3) uint8 device tensors."""
+    n = len(srcs)
+    pcs = [p.c() for p in per_frame_params] if per_frame_params else None
+    arr = (hzd_frame * n)()
+    for i in range(n):
+        arr[i] = _frame_struct(srcs[i], dsts[i], ctypes.pointer(pcs[i]) if pcs else None)
+    aarr = None
+    if auxs is not None:
+        aarr = (hzd_frame_aux * n)()
+        for i in range(n):
+            s = _aux_struct(auxs[i])
+            if s is not None:
+                aarr[i] = s
+    pc = params.c()
+    if workspace is None:
+        shapes = [(s.shape[0], s.shape[1]) for s in srcs]
+        workspace = alloc_workspace(workspace_size(params, shapes, per_frame_params), srcs[0].device)
+    rc = lib().hzd_dehaze_batch(ctypes.byref(pc), arr, n, aarr, workspace.data_ptr(), workspace.numel(),
+                                _stream_handle(stream))
+    _check(rc, "hzd_dehaze_batch")
+
+
+# ------------------------------------------------------------------ server
+class Server:
+    """hzd_server_*: continuous batching of many frame streams on one GPU."""
+
+    def __init__(self, arena_bytes: int, device: int = 0, max_inflight: int = 16,
+                 frames_per_launch: int = 8, hip_streams: int = 4):
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        cfg = hzd_server_config(ctypes.sizeof(hzd_server_config), device, self.arena.data_ptr(), arena_bytes,
+                                max_inflight, frames_per_launch, hip_streams)
+        h = ctypes.c_void_p()
+        _check(lib().hzd_server_create(ctypes.byref(cfg), ctypes.byref(h)), "hzd_server_create")
+        self.handle = h
+        self._cb = DONE_FN(self._on_done)
+        self._lock = threading.Lock()
+        self.latency_ns = {}
+        self.status = {}
+
+    def _on_done(self, user, ticket, status, latency_ns):
+        with self._lock:
+            self.latency_ns[(user or 0, int(ticket))] = int(latency_ns)
+            self.status[(user or 0, int(ticket))] = int(status)
+
+    def open(self, params: Params, width: int, height: int) -> "Stream":
+        h = ctypes.c_void_p()
+        pc = params.c()
+        _check(lib().hzd_stream_open(self.handle, ctypes.byref(pc), width, height, ctypes.byref(h)),
+               "hzd_stream_open")
+        return Stream(self, h, width, height)
+
+    def stats(self) -> dict:
+        s = hzd_server_stats()
+        _check(lib().hzd_server_stats_get(self.handle, ctypes.byref(s)), "hzd_server_stats_get")
+        return {k: getattr(s, k) for k, _ in hzd_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().hzd_server_destroy(self.handle), "hzd_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    def __init__(self, server: Server, handle, width, height):
+        self.server, self.handle, self.width, self.height = server, handle, width, height
+        self.tag = id(self) & 0xFFFFFFFF
+
+    def submit(self, src: torch.Tensor, dst: torch.Tensor) -> int:
+        f = _frame_struct(src, dst)
+        t = ctypes.c_uint64(0)
+        rc = lib().hzd_stream_submit(self.handle, ctypes.byref(f), self.server._cb, self.tag, ctypes.byref(t))
+        _check(rc, "hzd_stream_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ns: int = -1) -> int:
+        return lib().hzd_stream_wait(self.handle, ticket, timeout_ns)
+
+    def latency_ns(self, ticket: int):
+        with self.server._lock:
+            return self.server.latency_ns.get((self.tag, ticket))
+
+    def state(self):
+        A = (ctypes.c_float * 3)()
+        sel = (ctypes.c_int32 * 3)()
+        _check(lib().hzd_stream_state(self.handle, A, sel), "hzd_stream_state")
+        return list(A), list(sel)
+
+    def close(self):
+        if self.handle:
+            _check(lib().hzd_stream_close(self.handle), "hzd_stream_close")
+            self.handle = None

@@ -1,0 +1,357 @@
+// C ABI of the dehazing library: argument validation, workspace planning and
+// the per-group launch sequence of the per-frame pipeline (paper Sec. V).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hzd.h"
+#include "hzd_internal.h"
+#include "hzd_plan.h"
+
+namespace hzd {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static bool in_range(float v, float lo, float hi) { return v >= lo && v <= hi; }
+
+int validate_params(const hzd_params* p) {
+  if (!p) return fail(HZD_E_INVAL, "params is NULL");
+  if (p->size != sizeof(hzd_params))
+    return fail(HZD_E_INVAL, "params->size %u != sizeof(hzd_params) %zu", p->size, sizeof(hzd_params));
+  if (p->mode != HZD_MODE_REALTIME && p->mode != HZD_MODE_OFFLINE)
+    return fail(HZD_E_INVAL, "mode %d unknown", p->mode);
+  if (p->patch < 1 || p->patch % 2 == 0) return fail(HZD_E_INVAL, "patch %d must be odd and >= 1", p->patch);
+  if (p->patch > 2 * kMaxHalfPatch + 1)
+    return fail(HZD_E_UNSUPPORTED, "patch %d > %d", p->patch, 2 * kMaxHalfPatch + 1);
+  if (!in_range(p->omega, 0.0f, 1.0f)) return fail(HZD_E_INVAL, "omega %g outside [0,1]", p->omega);
+  if (!(p->t0 > 0.0f && p->t0 <= 1.0f)) return fail(HZD_E_INVAL, "t0 %g outside (0,1]", p->t0);
+  if (!(p->top_frac > 0.0f && p->top_frac <= 1.0f))
+    return fail(HZD_E_INVAL, "top_frac %g outside (0,1]", p->top_frac);
+  if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(HZD_E_INVAL, "alpha %g outside (0,1]", p->alpha);
+  if (!in_range(p->gamma, 0.1f, 10.0f)) return fail(HZD_E_INVAL, "gamma %g outside [0.1,10]", p->gamma);
+  if (p->color_balance != 0 && p->color_balance != 1)
+    return fail(HZD_E_INVAL, "color_balance %d must be 0 or 1", p->color_balance);
+  if (p->tx != HZD_TX_HE && p->tx != HZD_TX_PAPER) return fail(HZD_E_INVAL, "tx %d unknown", p->tx);
+  if (p->precision != HZD_PREC_FP32 && p->precision != HZD_PREC_FP16)
+    return fail(HZD_E_INVAL, "precision %d unknown", p->precision);
+  if (p->mode == HZD_MODE_OFFLINE) {
+    if (p->gf_radius < 1) return fail(HZD_E_INVAL, "gf_radius %d < 1", p->gf_radius);
+    if (p->gf_radius > kMaxRadius)
+      return fail(HZD_E_UNSUPPORTED, "gf_radius %d > %d", p->gf_radius, kMaxRadius);
+    if (!in_range(p->gf_eps, 1e-8f, 1.0f)) return fail(HZD_E_INVAL, "gf_eps %g outside [1e-8,1]", p->gf_eps);
+  }
+  return HZD_OK;
+}
+
+static bool ranges_overlap(const hzd_frame& f) {
+  const uintptr_t s0 = (uintptr_t)f.src, d0 = (uintptr_t)f.dst;
+  const uintptr_t s1 = s0 + (uintptr_t)((int64_t)(f.height - 1) * f.src_pitch + 3 * (int64_t)f.width);
+  const uintptr_t d1 = d0 + (uintptr_t)((int64_t)(f.height - 1) * f.dst_pitch + 3 * (int64_t)f.width);
+  return s0 < d1 && d0 < s1;
+}
+
+int validate_frame(const hzd_frame* f, int idx) {
+  if (!f) return fail(HZD_E_INVAL, "frame %d is NULL", idx);
+  if (f->width < 1 || f->height < 1)
+    return fail(HZD_E_INVAL, "frame %d: size %dx%d", idx, f->width, f->height);
+  if ((int64_t)f->width * (int64_t)f->height >= (int64_t(1) << 31))
+    return fail(HZD_E_INVAL, "frame %d: width*height >= 2^31", idx);
+  if (!f->src || !f->dst) return fail(HZD_E_INVAL, "frame %d: NULL pixel pointer", idx);
+  if (f->src_pitch < 3 * (int64_t)f->width || f->dst_pitch < 3 * (int64_t)f->width)
+    return fail(HZD_E_INVAL, "frame %d: pitch < 3*width", idx);
+  if (f->src_pitch >= (int64_t(1) << 40) || f->dst_pitch >= (int64_t(1) << 40))
+    return fail(HZD_E_INVAL, "frame %d: pitch too large", idx);
+  if (ranges_overlap(*f)) return fail(HZD_E_INVAL, "frame %d: src and dst overlap", idx);
+  return HZD_OK;
+}
+
+static size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+static int a16(int v) { return (v + 15) & ~15; }
+
+GroupKey group_key(const hzd_params& p) {
+  GroupKey g;
+  g.mode = p.mode;
+  g.half_patch = (p.patch - 1) / 2;
+  g.tx = p.tx;
+  g.cb = p.color_balance;
+  g.fp16 = p.precision == HZD_PREC_FP16;
+  g.radius = p.mode == HZD_MODE_OFFLINE ? p.gf_radius : 0;
+  return g;
+}
+
+bool operator<(const GroupKey& a, const GroupKey& b) {
+  return std::memcmp(&a, &b, sizeof(GroupKey)) < 0;
+}
+
+size_t frame_ws_bytes(const hzd_params& p, int W, int H) {
+  const bool offline = p.mode == HZD_MODE_OFFLINE;
+  const bool needE = p.tx == HZD_TX_HE;
+  size_t s = a256(sizeof(FrameState));
+  s += a256((size_t)H * a16(W));                       // D
+  if (needE) s += a256((size_t)H * a16(3 * W));        // E
+  s += a256((size_t)H * 16);                           // rowinfo
+  if (p.color_balance) {
+    int nb = recon_blocks(W, H);
+    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius));
+    s += a256((size_t)nb * 16);                        // colour-balance partials
+  }
+  if (offline) {
+    s += a256((size_t)W * H * 8);                      // LP
+    s += a256((size_t)W * H * 8);                      // AB
+    if (p.color_balance) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
+  }
+  return s;
+}
+
+// Fill the device descriptor of one frame; `ws` is the frame's workspace base.
+FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws) {
+  FrameDev d;
+  std::memset(&d, 0, sizeof(d));
+  const int W = fr.width, H = fr.height;
+  const bool offline = p.mode == HZD_MODE_OFFLINE;
+  d.src = fr.src;
+  d.dst = fr.dst;
+  d.src_pitch = fr.src_pitch;
+  d.dst_pitch = fr.dst_pitch;
+  d.W = W;
+  d.H = H;
+  size_t off = 0;
+  d.st = reinterpret_cast<FrameState*>(ws + off);
+  off += a256(sizeof(FrameState));
+  d.D_pitch = a16(W);
+  d.D = ws + off;
+  off += a256((size_t)H * d.D_pitch);
+  d.E_pitch = a16(3 * W);
+  if (p.tx == HZD_TX_HE) {
+    d.E = ws + off;
+    off += a256((size_t)H * d.E_pitch);
+  }
+  d.rowinfo = reinterpret_cast<uint4*>(ws + off);
+  off += a256((size_t)H * 16);
+  if (p.color_balance) {
+    int nb = recon_blocks(W, H);
+    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius));
+    d.cbpart = reinterpret_cast<float4*>(ws + off);
+    off += a256((size_t)nb * 16);
+  }
+  if (offline) {
+    d.LP = reinterpret_cast<uint2*>(ws + off);
+    off += a256((size_t)W * H * 8);
+    d.AB = reinterpret_cast<int2*>(ws + off);
+    off += a256((size_t)W * H * 8);
+    if (p.color_balance) {
+      d.tmap = ws + off;
+      off += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
+    }
+  }
+  if (aux) {
+    d.A_out = aux->A_out;
+    d.sel_out = aux->sel_out;
+    d.dark_out = aux->dark_out;
+    d.t_out = aux->t_out;
+    d.J_out = aux->J_out;
+  }
+  const double n = (double)W * (double)H;
+  d.K = (int32_t)std::max(1.0, std::floor((double)p.top_frac * n));
+  d.radius = offline ? p.gf_radius : 0;
+  d.omega = p.omega;
+  d.t0 = p.t0;
+  d.alpha = p.alpha;
+  const double g = (double)p.gamma;
+  d.inv_gamma = (float)(1.0 / g);
+  d.gamma_log_bias = (float)(std::log2(255.0) * (1.0 - 1.0 / g));
+  d.gamma_is_one = p.gamma == 1.0f;
+  d.eps = p.gf_eps;
+  if (offline) {
+    // |a| <= 1 / (4 sqrt(eps)) for p in [0,1]; |b| <= 1 + |a|; scale 2^k keeps both in int32
+    const double B = 1.0 + 0.25 / std::sqrt((double)p.gf_eps);
+    const int k = std::min(30, (int)std::floor(std::log2(2147483647.0 / B)));
+    d.ab_scale = std::ldexp(1.0f, k);
+    d.ab_inv_scale = std::ldexp(1.0f, -k);
+  }
+  d.aligned = ((uintptr_t)fr.src % 4 == 0) && ((uintptr_t)fr.dst % 4 == 0) && (fr.src_pitch % 4 == 0) &&
+              (fr.dst_pitch % 4 == 0);
+  return d;
+}
+
+int check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return HZD_OK;
+  return fail(HZD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames.
+int run_group(const GroupKey& g, const Batch& b, hipStream_t s) {
+  int rc;
+  if ((rc = check(launch_init(b, s), "init")) != HZD_OK) return rc;
+  const bool he = g.tx == HZD_TX_HE;
+  if ((rc = check(launch_dark(b, g, he, s), "dark")) != HZD_OK) return rc;
+  if ((rc = check(launch_select(b, s), "select")) != HZD_OK) return rc;
+  if (g.mode == HZD_MODE_OFFLINE) {
+    if ((rc = check(launch_gf_prep(b, g, s), "gf_prep")) != HZD_OK) return rc;
+    if ((rc = check(launch_gf_ab(b, g, s), "gf_ab")) != HZD_OK) return rc;
+    if ((rc = check(launch_gf_q(b, g, s), "gf_q")) != HZD_OK) return rc;
+    if (g.cb && (rc = check(launch_recon(b, g, TSRC_TMAP, 2, s), "recon")) != HZD_OK) return rc;
+  } else {
+    const int tsrc = he ? TSRC_HE : TSRC_PAPER;
+    if (g.cb) {
+      if ((rc = check(launch_recon(b, g, tsrc, 1, s), "recon-sums")) != HZD_OK) return rc;
+      if ((rc = check(launch_recon(b, g, tsrc, 2, s), "recon-apply")) != HZD_OK) return rc;
+    } else {
+      if ((rc = check(launch_recon(b, g, tsrc, 0, s), "recon")) != HZD_OK) return rc;
+    }
+  }
+  return HZD_OK;
+}
+
+int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, const hzd_frame_aux* aux,
+                void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 1) return fail(HZD_E_INVAL, "n = %d < 1", n);
+  if (!frames) return fail(HZD_E_INVAL, "frames is NULL");
+  std::vector<const hzd_params*> ps(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = validate_frame(&frames[i], i);
+    if (rc) return rc;
+    ps[i] = frames[i].params ? frames[i].params : params;
+    if ((rc = validate_params(ps[i])) != HZD_OK) return rc;
+  }
+  if (!workspace) return fail(HZD_E_INVAL, "workspace is NULL");
+  if ((uintptr_t)workspace % 256) return fail(HZD_E_INVAL, "workspace not 256-byte aligned");
+  std::vector<size_t> offs(n);
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    offs[i] = need;
+    need += frame_ws_bytes(*ps[i], frames[i].width, frames[i].height);
+  }
+  if (ws_bytes < need) return fail(HZD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+
+  std::map<GroupKey, std::vector<int>> groups;
+  for (int i = 0; i < n; ++i) groups[group_key(*ps[i])].push_back(i);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (auto& kv : groups) {
+    const std::vector<int>& idx = kv.second;
+    for (size_t c = 0; c < idx.size(); c += kMaxBatch) {
+      Batch b;
+      std::memset(&b, 0, sizeof(b));
+      b.n = (int)std::min<size_t>(kMaxBatch, idx.size() - c);
+      for (int j = 0; j < b.n; ++j) {
+        const int i = idx[c + j];
+        b.f[j] = make_frame_dev(*ps[i], frames[i], aux ? &aux[i] : nullptr,
+                                reinterpret_cast<uint8_t*>(workspace) + offs[i]);
+      }
+      int rc = run_group(kv.first, b, s);
+      if (rc) return rc;
+    }
+  }
+  return HZD_OK;
+}
+
+}  // namespace hzd
+
+using namespace hzd;
+
+extern "C" {
+
+int hzd_abi_version(void) { return HZD_ABI_VERSION; }
+
+const char* hzd_status_str(int32_t st) {
+  switch (st) {
+    case HZD_OK: return "ok";
+    case HZD_E_INVAL: return "invalid argument";
+    case HZD_E_NOMEM: return "workspace or arena too small";
+    case HZD_E_DEVICE: return "device error";
+    case HZD_E_AGAIN: return "try again";
+    case HZD_E_CLOSED: return "closed";
+    case HZD_E_UNSUPPORTED: return "unsupported";
+    case HZD_E_TIMEOUT: return "timeout";
+    default: return "unknown status";
+  }
+}
+
+const char* hzd_last_error(void) { return g_last_error.c_str(); }
+
+int hzd_params_default(hzd_params* p, int32_t preset) {
+  if (!p) return fail(HZD_E_INVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->size = sizeof(hzd_params);
+  p->mode = HZD_MODE_REALTIME;
+  p->patch = 15;
+  p->omega = 0.95f;
+  p->t0 = 0.1f;
+  p->top_frac = 0.001f;
+  p->alpha = 0.8f;
+  p->gamma = 1.2f;
+  p->gf_radius = 60;
+  p->gf_eps = 1e-3f;
+  p->color_balance = 0;
+  p->tx = HZD_TX_HE;
+  p->precision = HZD_PREC_FP32;
+  switch (preset) {
+    case HZD_PRESET_REALTIME: break;
+    case HZD_PRESET_OFFLINE:
+      p->mode = HZD_MODE_OFFLINE;
+      p->color_balance = 1;
+      break;
+    case HZD_PRESET_PAPER_REALTIME:
+      p->omega = 0.5f;
+      p->t0 = 0.05f;
+      p->tx = HZD_TX_PAPER;
+      break;
+    default: return fail(HZD_E_INVAL, "preset %d unknown", preset);
+  }
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_t n, size_t* bytes) {
+  if (!bytes) return fail(HZD_E_INVAL, "bytes is NULL");
+  if (!frames || n < 1) return fail(HZD_E_INVAL, "no frames");
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    const hzd_params* p = frames[i].params ? frames[i].params : params;
+    int rc = validate_params(p);
+    if (rc) return rc;
+    if (frames[i].width < 1 || frames[i].height < 1 ||
+        (int64_t)frames[i].width * frames[i].height >= (int64_t(1) << 31))
+      return fail(HZD_E_INVAL, "frame %d: size %dx%d", i, frames[i].width, frames[i].height);
+    need += frame_ws_bytes(*p, frames[i].width, frames[i].height);
+  }
+  *bytes = need;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_dehaze_frame(const hzd_params* params, const hzd_frame* frame, const hzd_frame_aux* aux,
+                     void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!frame) return fail(HZD_E_INVAL, "frame is NULL");
+  int rc = dehaze_many(params, frame, 1, aux, workspace, ws_bytes, hip_stream);
+  if (rc == HZD_OK) clear_error();
+  return rc;
+}
+
+int hzd_dehaze_batch(const hzd_params* params, const hzd_frame* frames, int32_t n,
+                     const hzd_frame_aux* aux, void* workspace, size_t ws_bytes, void* hip_stream) {
+  int rc = dehaze_many(params, frames, n, aux, workspace, ws_bytes, hip_stream);
+  if (rc == HZD_OK) clear_error();
+  return rc;
+}
+
+}  // extern "C"

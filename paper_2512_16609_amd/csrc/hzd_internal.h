@@ -1,0 +1,97 @@
+// Internal structures shared by the C-ABI layer (hzd_api.cpp) and the gfx950
+// kernels (hzd_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hzd.h"
+
+namespace hzd {
+
+constexpr int kMaxBatch = 16;   // frames per launch (descriptors travel in kernel arguments)
+constexpr int kMaxHalfPatch = 15;
+constexpr int kMaxRadius = 64;  // guided-filter radius supported by the 256-column strip kernels
+
+// Per-frame device state at the start of each frame's workspace.  Zeroed by the
+// init kernel at the start of every pipeline.
+struct FrameState {
+  uint32_t hist[256];               // histogram of the dark channel D
+  uint32_t ticket_select;           // last-block detection in the select kernel
+  uint32_t ticket_cb;               // last-block detection for colour-balance sums
+  uint32_t pad0[2];
+  unsigned long long gt[4];         // sum of I^c over {D > vstar}, and its pixel count
+  float A[4];                       // airlight A^c (0..255 scale)
+  int32_t sel[4];                   // K, vstar, cutoff, consistency flag (0 = ok)
+  float gains[4];                   // gray-world gains
+  uint32_t pad1[48];
+};
+static_assert(sizeof(FrameState) <= 2048, "FrameState too large");
+
+// Everything one frame needs on the device, passed by value in kernel arguments.
+struct FrameDev {
+  const uint8_t* src;
+  uint8_t* dst;
+  int64_t src_pitch;
+  int64_t dst_pitch;
+  FrameState* st;
+  uint8_t* D;        // dark channel, pitch D_pitch
+  uint8_t* E;        // per-channel erosions (packed RGB8), pitch E_pitch
+  uint4* rowinfo;    // per row: {ties, sum R, sum G, sum B} over D == vstar
+  float4* cbpart;    // per block colour-balance partial sums
+  uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
+  int2* AB;          // offline: guided-filter a, b in fixed point (pitch W)
+  void* tmap;        // offline + colour balance: refined t (float or half, pitch W)
+  float* A_out;
+  int32_t* sel_out;
+  uint8_t* dark_out;
+  float* t_out;
+  float* J_out;
+  int32_t W, H;
+  int32_t D_pitch, E_pitch;
+  int32_t K;
+  int32_t radius;
+  float omega, t0, alpha, inv_gamma, gamma_log_bias;  // gamma_log_bias = log2(255) (1 - 1/gamma)
+  float eps;
+  float ab_scale, ab_inv_scale;                      // fixed-point scale of a, b
+  int32_t gamma_is_one;
+  int32_t aligned;   // src, dst and both pitches are multiples of 4
+};
+
+struct Batch {
+  int32_t n;
+  int32_t tile0[kMaxBatch + 1];  // per-launch prefix of blocks per frame
+  FrameDev f[kMaxBatch];
+};
+static_assert(sizeof(Batch) <= 4000, "kernel argument block too large");
+
+// Group-wide kernel switches (identical for all frames of one launch).
+struct GroupKey {
+  int32_t mode, half_patch, tx, cb, fp16, radius;
+};
+
+// Launches (hzd_kernels.hip).  Each fills b.tile0 for its own tiling.
+hipError_t launch_init(Batch b, hipStream_t s);
+hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s);
+hipError_t launch_select(Batch b, hipStream_t s);
+hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s);
+hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s);
+hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s);
+// phase: 0 = write output, 1 = colour-balance sums only, 2 = apply gains and write
+hipError_t launch_recon(Batch b, const GroupKey& g, int tsrc, int phase, hipStream_t s);
+
+// Tiling shared by the workspace planner and the launches.
+constexpr int kDarkTW = 64, kDarkTH = 32;
+constexpr int kReconPx = 1024;   // pixels of one row per recon block
+constexpr int kGfCols = 256;     // loaded columns per guided-filter strip block
+constexpr int kGfRows = 32;      // output rows per guided-filter block
+inline int recon_blocks(int W, int H) { return H * ((W + kReconPx - 1) / kReconPx); }
+inline int gf_strip(int r) { return kGfCols - 2 * r; }
+inline int gf_blocks(int W, int H, int r) {
+  return ((W + gf_strip(r) - 1) / gf_strip(r)) * ((H + kGfRows - 1) / kGfRows);
+}
+
+enum { TSRC_HE = 0, TSRC_PAPER = 1, TSRC_TMAP = 2 };
+
+}  // namespace hzd

@@ -1,0 +1,1001 @@
+// gfx950 kernels of the per-frame dark-channel-prior dehazing path
+// (Hazedefy, arXiv 2512.16609, Sec. IV and Sec. V).
+//
+// Stage map (every kernel processes a batch of frames; a block finds its
+// frame from the per-launch block prefix in the kernel arguments):
+//   k_init     zero each frame's state (histogram, tickets, sums)
+//   k_dark     Eq. (2): channel minimum + patch erosion on LDS tiles with halo;
+//              writes D (u8), optionally the per-channel erosions E, and a
+//              256-bin histogram of D
+//   k_select   Eq. (3): vstar from the histogram, per-row tie counts, the tie
+//              cut in raster order by the last block, exact integer sums, A
+//   k_gf_prep  offline: per-pixel luma and coarse t (Eqs. (4)-(5)) in fixed point
+//   k_gf_ab    Eq. (6) stage 1: exact integer box sums -> a, b
+//   k_gf_q     Eq. (6) stage 2: box means of a, b -> refined t (+ fused Eq. (7))
+//   k_recon    Eqs. (4)-(5) pointwise + Eq. (7) + Eq. (8) + colour balance
+//
+// Nothing here is a dense contraction, so no MFMA: the path is bound by HBM
+// traffic and VALU work.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "hzd_internal.h"
+
+namespace hzd {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int frame_of(const Batch& b, int blk) {
+  int f = 0;
+  while (f + 1 < b.n && blk >= b.tile0[f + 1]) ++f;
+  return f;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin.  Give each XCD a contiguous
+// run of logical tiles so that neighbouring tiles (which share halo rows)
+// meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int x = b % X, i = b / X;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+// Two independent unsigned 16-bit minima in one VALU op (v_pk_min_u16).
+__device__ __forceinline__ uint32_t pkmin(uint32_t a, uint32_t b) {
+  us2 x = __builtin_bit_cast(us2, a), y = __builtin_bit_cast(us2, b);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(x, y));
+}
+
+// Sliding minimum over windows of WIN consecutive values (van Herk /
+// Gil-Werman): prefix minima g and suffix minima h inside aligned blocks of
+// WIN values; window [i, i+WIN-1] spans at most two blocks, so its minimum is
+// min(h[i], g[i+WIN-1]).  About 3 minima per output, independent of WIN.
+template <int L, int WIN, int S>
+__device__ __forceinline__ void sliding_min(const uint32_t (&v)[L], uint32_t (&o)[S]) {
+  static_assert(L == S + WIN - 1, "window geometry");
+  uint32_t g[L], h[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) g[i] = (i % WIN == 0) ? v[i] : pkmin(g[i > 0 ? i - 1 : 0], v[i]);
+#pragma unroll
+  for (int i = L - 1; i >= 0; --i)
+    h[i] = (i % WIN == WIN - 1 || i == L - 1) ? v[i] : pkmin(h[i < L - 1 ? i + 1 : i], v[i]);
+#pragma unroll
+  for (int i = 0; i < S; ++i) o[i] = pkmin(h[i], g[i + WIN - 1]);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Inclusive scan over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Inclusive scan over a 256-thread block.  s_tmp: 4 elements of LDS.
+template <typename T>
+__device__ __forceinline__ T block_incl_scan(T v, T* s_tmp) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T x = wave_incl_scan(v);
+  if (lane == 63) s_tmp[w] = x;
+  __syncthreads();
+  T add = 0;
+  for (int i = 0; i < w; ++i) add += s_tmp[i];
+  __syncthreads();
+  return x + add;
+}
+
+// Sum over a 256-thread block in a fixed order; every thread gets the total.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* s_tmp) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T x = wave_sum(v);
+  if (lane == 0) s_tmp[w] = x;
+  __syncthreads();
+  T tot = (s_tmp[0] + s_tmp[1]) + (s_tmp[2] + s_tmp[3]);
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ void load_rgb(const uint8_t* p, float& r, float& g, float& b) {
+  r = (float)p[0];
+  g = (float)p[1];
+  b = (float)p[2];
+}
+
+// Eqs. (7)-(8) for one pixel: J^c = (I^c - A^c)/t + A^c clamped to [0, 255],
+// then J_gamma = 255 (J/255)^(1/gamma) = 2^(log2(J)/gamma + log2(255)(1 - 1/gamma)).
+struct ReconConsts {
+  float A[3];
+  float inv_gamma, bias;
+  int gamma_is_one;
+};
+
+__device__ __forceinline__ void recon_pixel(const ReconConsts& rc, const float I[3], float t,
+                                            float J[3], float Jg[3]) {
+  const float it = __builtin_amdgcn_rcpf(t);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float j = fmaf(I[c] - rc.A[c], it, rc.A[c]);
+    j = __builtin_amdgcn_fmed3f(j, 0.0f, 255.0f);
+    J[c] = j;
+    Jg[c] = rc.gamma_is_one ? j
+                            : __builtin_amdgcn_exp2f(fmaf(__builtin_amdgcn_logf(j), rc.inv_gamma, rc.bias));
+  }
+}
+
+__device__ __forceinline__ uint32_t rne_u8(float v) {
+  v = __builtin_amdgcn_fmed3f(v, 0.0f, 255.0f);
+  return (uint32_t)__builtin_rintf(v);
+}
+
+__device__ __forceinline__ float round_half(float t) { return __half2float(__float2half_rn(t)); }
+
+// ------------------------------------------------------------------ k_init
+__global__ __launch_bounds__(256) void k_init(Batch b) {
+  const FrameDev& fd = b.f[blockIdx.x];
+  uint32_t* s = reinterpret_cast<uint32_t*>(fd.st);
+  for (int i = threadIdx.x; i < (int)(sizeof(FrameState) / 4); i += 256) s[i] = 0u;
+}
+
+// ------------------------------------------------------------------ k_dark
+// One 64x32 output tile per block.  The (64+2h) x (32+2h) region is staged in
+// LDS as two planes of packed 16-bit pairs: (R | B << 16) and (G | 255 << 16),
+// so each v_pk_min_u16 handles two channels.  Out-of-frame cells hold 255 (a
+// clipped window).  Vertical van Herk per column segment, then horizontal van
+// Herk per row segment, both in registers.
+template <int HP, bool WRITE_E>
+__global__ __launch_bounds__(256) void k_dark(Batch b) {
+  constexpr int TW = kDarkTW, TH = kDarkTH;
+  constexpr int RW = TW + 2 * HP, RH = TH + 2 * HP, WIN = 2 * HP + 1;
+  __shared__ uint32_t s_rb[RH][RW];
+  __shared__ uint32_t s_g[RH][RW];
+  __shared__ uint32_t s_vrb[TH][RW];
+  __shared__ uint32_t s_vg[TH][RW];
+  __shared__ uint32_t s_hist[256];
+
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  const int W = fd.W, H = fd.H;
+  const int tiles_x = (W + TW - 1) / TW;
+  const int x0 = (tile % tiles_x) * TW, y0 = (tile / tiles_x) * TH;
+  const int tid = threadIdx.x;
+
+  s_hist[tid] = 0u;
+  for (int i = tid; i < RH * RW; i += 256) {
+    const int rr = i / RW, cc = i - rr * RW;
+    const int y = y0 - HP + rr, x = x0 - HP + cc;
+    uint32_t rb = 0x00FF00FFu, g = 0x00FF00FFu;
+    if (y >= 0 && y < H && x >= 0 && x < W) {
+      const uint8_t* p = fd.src + (int64_t)y * fd.src_pitch + 3 * x;
+      rb = (uint32_t)p[0] | ((uint32_t)p[2] << 16);
+      g = (uint32_t)p[1] | 0x00FF0000u;
+    }
+    s_rb[rr][cc] = rb;
+    s_g[rr][cc] = g;
+  }
+  __syncthreads();
+
+  // vertical pass: RW columns x 2 segments of 16 output rows
+  {
+    constexpr int SEG = 16, NSEG = TH / SEG, L = SEG + WIN - 1;
+    for (int w = tid; w < RW * NSEG; w += 256) {
+      const int sg = w / RW, cc = w - sg * RW, r0 = sg * SEG;
+      uint32_t vrb[L], vg[L], orb[SEG], og[SEG];
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        vrb[i] = s_rb[r0 + i][cc];
+        vg[i] = s_g[r0 + i][cc];
+      }
+      sliding_min<L, WIN, SEG>(vrb, orb);
+      sliding_min<L, WIN, SEG>(vg, og);
+#pragma unroll
+      for (int i = 0; i < SEG; ++i) {
+        s_vrb[r0 + i][cc] = orb[i];
+        s_vg[r0 + i][cc] = og[i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // horizontal pass: 32 rows x 8 segments of 8 output columns
+  {
+    constexpr int HS = 8, L = HS + WIN - 1;
+    const int r = tid >> 3, c0 = (tid & 7) * HS;
+    uint32_t vrb[L], vg[L], orb[HS], og[HS];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      vrb[i] = s_vrb[r][c0 + i];
+      vg[i] = s_vg[r][c0 + i];
+    }
+    sliding_min<L, WIN, HS>(vrb, orb);
+    sliding_min<L, WIN, HS>(vg, og);
+    const int y = y0 + r, xb = x0 + c0;
+    if (y < H && xb < W) {
+      const int nx = min(HS, W - xb);
+      uint32_t d[HS];
+      uint64_t dpack = 0, e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+      for (int i = 0; i < HS; ++i) {
+        const uint32_t er = orb[i] & 0xFFu, eb = (orb[i] >> 16) & 0xFFu, eg = og[i] & 0xFFu;
+        d[i] = min(min(er, eg), eb);
+        dpack |= (uint64_t)d[i] << (8 * i);
+        const uint64_t rgb = (uint64_t)(er | (eg << 8) | (eb << 16));
+        const int bit = 24 * i;  // 8 pixels x 24 bits = 192 bits in e0|e1|e2
+        if (bit < 64) e0 |= rgb << bit;
+        if (bit + 24 > 64 && bit < 128) e1 |= (bit >= 64) ? rgb << (bit - 64) : rgb >> (64 - bit);
+        if (bit + 24 > 128) e2 |= (bit >= 128) ? rgb << (bit - 128) : rgb >> (128 - bit);
+      }
+      uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch + xb;
+      uint8_t* Erow = fd.E + (int64_t)y * fd.E_pitch + 3 * xb;
+      if (nx == HS) {
+        *reinterpret_cast<uint64_t*>(Drow) = dpack;
+        if (WRITE_E) {
+          uint64_t* e = reinterpret_cast<uint64_t*>(Erow);
+          e[0] = e0;
+          e[1] = e1;
+          e[2] = e2;
+        }
+      } else {
+        for (int i = 0; i < nx; ++i) {
+          Drow[i] = (uint8_t)d[i];
+          if (WRITE_E) {
+            Erow[3 * i + 0] = (uint8_t)(orb[i] & 0xFFu);
+            Erow[3 * i + 1] = (uint8_t)(og[i] & 0xFFu);
+            Erow[3 * i + 2] = (uint8_t)((orb[i] >> 16) & 0xFFu);
+          }
+        }
+      }
+      if (fd.dark_out) {
+        uint8_t* o = fd.dark_out + (int64_t)y * W + xb;
+        for (int i = 0; i < nx; ++i) o[i] = (uint8_t)d[i];
+      }
+      // histogram with run-length aggregation (D is locally smooth)
+      uint32_t cur = d[0], cnt = 1;
+      for (int i = 1; i < nx; ++i) {
+        if (d[i] == cur) {
+          ++cnt;
+        } else {
+          atomicAdd(&s_hist[cur], cnt);
+          cur = d[i];
+          cnt = 1;
+        }
+      }
+      atomicAdd(&s_hist[cur], cnt);
+    }
+  }
+  __syncthreads();
+  const uint32_t hv = s_hist[tid];
+  if (hv) atomicAdd(&fd.st->hist[tid], hv);
+}
+
+// ---------------------------------------------------------------- k_select
+// Eq. (3) with a unique top-K set: order pixels by (D descending, raster
+// index ascending) and take the first K.
+//   vstar  = largest v with #{D >= v} >= K (from the histogram; every block
+//            recomputes it from the 256 counts)
+//   need   = K - #{D > vstar} >= 1 pixels with D == vstar are taken, the
+//            first `need` of them in raster order.
+// Each wave handles one row: it sums I over D > vstar (exact u64, atomically
+// merged) and counts and sums the ties D == vstar of its row.  The last block
+// of the frame (atomic ticket) scans the per-row tie counts, finds the cut
+// row and, inside it, the cutoff pixel with ballot/popcount, and forms
+// A^c = alpha * S^c / K from exact integer sums.
+__global__ __launch_bounds__(256) void k_select(Batch b) {
+  __shared__ uint32_t s_u32[4];
+  __shared__ unsigned long long s_u64[4];
+  __shared__ int s_misc[4];
+  __shared__ unsigned long long s_sum[3];
+
+  const int blk = blockIdx.x;
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  const int nblk = b.tile0[f + 1] - b.tile0[f];
+  const int W = fd.W, H = fd.H, K = fd.K;
+  FrameState* st = fd.st;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+
+  // vstar and #{D > vstar}: thread t holds the count of value 255 - t
+  const uint32_t c = st->hist[255 - tid];
+  const uint32_t incl = block_incl_scan<uint32_t>(c, s_u32);
+  if (incl >= (uint32_t)K && incl - c < (uint32_t)K) {
+    s_misc[0] = 255 - tid;
+    s_misc[1] = (int)(incl - c);
+  }
+  __syncthreads();
+  const uint32_t vstar = (uint32_t)s_misc[0];
+  const uint32_t cnt_gt = (uint32_t)s_misc[1];
+
+  // one row per wave
+  const int y = tile * 4 + wv;
+  if (y < H) {
+    unsigned long long gR = 0, gG = 0, gB = 0, gN = 0;
+    uint32_t tN = 0, tR = 0, tG = 0, tB = 0;
+    const uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch;
+    const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
+    for (int x = lane; x < W; x += 64) {
+      const uint32_t d = Drow[x];
+      if (d >= vstar) {
+        const uint32_t r = Irow[3 * x], g = Irow[3 * x + 1], bl = Irow[3 * x + 2];
+        if (d > vstar) {
+          gR += r; gG += g; gB += bl; gN += 1;
+        } else {
+          tR += r; tG += g; tB += bl; tN += 1;
+        }
+      }
+    }
+    tN = wave_sum(tN); tR = wave_sum(tR); tG = wave_sum(tG); tB = wave_sum(tB);
+    gN = wave_sum(gN);
+    if (gN) { gR = wave_sum(gR); gG = wave_sum(gG); gB = wave_sum(gB); }
+    if (lane == 0) {
+      fd.rowinfo[y] = make_uint4(tN, tR, tG, tB);
+      if (gN) {
+        atomicAdd(&st->gt[0], gR);
+        atomicAdd(&st->gt[1], gG);
+        atomicAdd(&st->gt[2], gB);
+        atomicAdd(&st->gt[3], gN);
+      }
+    }
+  }
+
+  // last block of this frame finishes the selection
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_misc[2] = (atomicAdd(&st->ticket_select, 1u) == (uint32_t)(nblk - 1));
+  __syncthreads();
+  if (!s_misc[2]) return;
+  __threadfence();
+
+  const uint32_t need = (uint32_t)K - cnt_gt;  // >= 1
+  if (tid == 0) {
+    s_misc[0] = -1;
+    s_misc[1] = 0;
+  }
+  __syncthreads();
+  const int per = (H + 255) / 256;
+  const int ra = min(H, tid * per), rb = min(H, ra + per);
+  uint32_t mine = 0;
+  for (int yy = ra; yy < rb; ++yy) mine += fd.rowinfo[yy].x;
+  const uint32_t rincl = block_incl_scan<uint32_t>(mine, s_u32);
+  const uint32_t rexcl = rincl - mine;
+  if (rexcl < need && need <= rincl) {
+    uint32_t cum = rexcl;
+    for (int yy = ra; yy < rb; ++yy) {
+      const uint32_t tc = fd.rowinfo[yy].x;
+      if (cum + tc >= need) {
+        s_misc[0] = yy;
+        s_misc[1] = (int)cum;
+        break;
+      }
+      cum += tc;
+    }
+  }
+  __syncthreads();
+  const int rstar = s_misc[0];
+  const uint32_t before = (uint32_t)s_misc[1];
+  if (rstar < 0) {  // inconsistent counts: report instead of reading a row that is not there
+    if (tid == 0) {
+      st->sel[0] = K;
+      st->sel[1] = (int32_t)vstar;
+      st->sel[2] = -1;
+      st->sel[3] = 2;
+    }
+    return;
+  }
+
+  // ties in rows above the cut row are all in the set
+  unsigned long long sR = 0, sG = 0, sB = 0;
+  for (int yy = ra; yy < min(rb, rstar); ++yy) {
+    const uint4 ri = fd.rowinfo[yy];
+    sR += ri.y; sG += ri.z; sB += ri.w;
+  }
+  sR = block_sum(sR, s_u64);
+  sG = block_sum(sG, s_u64);
+  sB = block_sum(sB, s_u64);
+
+  // the cut row: the first (need - before) ties in raster order
+  if (wv == 0) {
+    const uint32_t k = need - before;
+    const uint8_t* Drow = fd.D + (int64_t)rstar * fd.D_pitch;
+    const uint8_t* Irow = fd.src + (int64_t)rstar * fd.src_pitch;
+    uint32_t run = 0;
+    unsigned long long cR = 0, cG = 0, cB = 0;
+    int cut_x = -1;
+    for (int base = 0; base < W; base += 64) {
+      const int x = base + lane;
+      const bool tie = (x < W) && (Drow[x] == vstar);
+      const unsigned long long m = __ballot(tie);
+      const uint32_t cnt = (uint32_t)__popcll(m);
+      const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      const uint32_t take = min(cnt, k - run);   // ties taken from this chunk
+      if (tie && rank < take) {
+        cR += Irow[3 * x]; cG += Irow[3 * x + 1]; cB += Irow[3 * x + 2];
+        if (rank == take - 1 && run + take == k) cut_x = x;
+      }
+      run += take;
+      if (run == k) break;
+    }
+    cR = wave_sum(cR); cG = wave_sum(cG); cB = wave_sum(cB);
+    int cx = cut_x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cx = max(cx, __shfl_xor(cx, o, 64));
+    if (lane == 0) {
+      s_sum[0] = cR; s_sum[1] = cG; s_sum[2] = cB;
+      s_misc[3] = cx;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned long long S[3] = {st->gt[0] + sR + s_sum[0], st->gt[1] + sG + s_sum[1],
+                                     st->gt[2] + sB + s_sum[2]};
+    const int32_t cutoff = rstar * W + s_misc[3];
+    const double a = (double)fd.alpha;
+    for (int ch = 0; ch < 3; ++ch) {
+      const float A = (float)(a * (double)S[ch] / (double)K);
+      st->A[ch] = A;
+      if (fd.A_out) fd.A_out[ch] = A;
+    }
+    st->sel[0] = K;
+    st->sel[1] = (int32_t)vstar;
+    st->sel[2] = cutoff;
+    // consistency: the atomically merged count over D > vstar must equal the histogram's
+    st->sel[3] = (st->gt[3] == (unsigned long long)cnt_gt && s_misc[3] >= 0) ? 0 : 1;
+    if (fd.sel_out) {
+      fd.sel_out[0] = K;
+      fd.sel_out[1] = (int32_t)vstar;
+      fd.sel_out[2] = cutoff;
+    }
+  }
+}
+
+// ----------------------------------------------------- transmission (device)
+struct TxConsts {
+  float iA[3];     // 1 / max(A^c, 1)
+  float iAmax;     // 1 / max_c max(A^c, 1)
+  float omega, t0;
+};
+
+__device__ __forceinline__ TxConsts tx_consts(const FrameDev& fd) {
+  TxConsts k;
+  float am = 1.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float a = fmaxf(fd.st->A[c], 1.0f);
+    k.iA[c] = 1.0f / a;
+    am = fmaxf(am, a);
+  }
+  k.iAmax = 1.0f / am;
+  k.omega = fd.omega;
+  k.t0 = fd.t0;
+  return k;
+}
+
+// Eqs. (4)-(5), dark-channel form: t = max(1 - omega * min_c E^c / A^c, t0)
+__device__ __forceinline__ float tx_he(const TxConsts& k, float er, float eg, float eb) {
+  const float e = fminf(fminf(er * k.iA[0], eg * k.iA[1]), eb * k.iA[2]);
+  return fmaxf(fmaf(-k.omega, e, 1.0f), k.t0);
+}
+
+// Eqs. (4)-(5) as printed: t = max(1 - omega * min_c I^c(x) / max(A), t0)
+__device__ __forceinline__ float tx_paper(const TxConsts& k, float m) {
+  return fmaxf(fmaf(-k.omega, m * k.iAmax, 1.0f), k.t0);
+}
+
+__device__ __forceinline__ ReconConsts recon_consts(const FrameDev& fd) {
+  ReconConsts rc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) rc.A[c] = fd.st->A[c];
+  rc.inv_gamma = fd.inv_gamma;
+  rc.bias = fd.gamma_log_bias;
+  rc.gamma_is_one = fd.gamma_is_one;
+  return rc;
+}
+
+// ---------------------------------------------------------------- k_gf_prep
+// Offline mode, after the airlight: per pixel, the guide as an exact integer
+// L = 299 R + 587 G + 114 B (= 255000 * BT.601 luma in [0,1]) and the coarse
+// t of Eqs. (4)-(5) in fixed point P = rint(t * 2^28) (exact for t >= 1/16).
+template <int TX>
+__global__ __launch_bounds__(256) void k_gf_prep(Batch b) {
+  const int blk = blockIdx.x;
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  const int W = fd.W;
+  const int per_row = (W + kReconPx - 1) / kReconPx;
+  const int y = tile / per_row;
+  const int xb = (tile - y * per_row) * kReconPx;
+  const TxConsts k = tx_consts(fd);
+  const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
+  const uint8_t* Erow = fd.E + (int64_t)y * fd.E_pitch;
+  uint2* out = fd.LP + (int64_t)y * W;
+  for (int x = xb + threadIdx.x; x < min(W, xb + kReconPx); x += 256) {
+    const uint32_t r = Irow[3 * x], g = Irow[3 * x + 1], bl = Irow[3 * x + 2];
+    float t;
+    if (TX == TSRC_HE) {
+      t = tx_he(k, (float)Erow[3 * x], (float)Erow[3 * x + 1], (float)Erow[3 * x + 2]);
+    } else {
+      t = tx_paper(k, (float)min(min(r, g), bl));
+    }
+    const uint32_t L = 299u * r + 587u * g + 114u * bl;
+    const uint32_t P = (uint32_t)__builtin_rintf(t * 268435456.0f);
+    out[x] = make_uint2(L, P);
+  }
+}
+
+// ------------------------------------------------------------------ k_gf_ab
+// Eq. (6), stage 1 (He et al. 2013 box form).  A block owns a strip of 256
+// loaded columns (one per thread) and produces 256 - 2r output columns for
+// kGfRows rows.  Each thread keeps exact u64 vertical window sums of L, L^2,
+// P, L*P for its column, sliding down the rows; per row the four column sums
+// are prefix-summed across the strip in LDS (one wave per quantity) and each
+// output's clipped (2r+1)^2 box sum is a difference of two prefixes.  Integer
+// sums are exact, so the result does not depend on the tiling.  The means,
+// var and cov are formed in FP64; a and b leave as int32 fixed point.
+__global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
+  __shared__ unsigned long long s_q[4][kGfCols];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  const int W = fd.W, H = fd.H, r = fd.radius;
+  const int SW = kGfCols - 2 * r;
+  const int strips = (W + SW - 1) / SW;
+  const int sx = tile % strips, sy = tile / strips;
+  const int x0 = sx * SW, y0 = sy * kGfRows, y1 = min(H, y0 + kGfRows);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int xl = x0 - r + tid;
+  const bool colin = (xl >= 0 && xl < W);
+  const uint2* LP = fd.LP;
+
+  unsigned long long sL = 0, sLL = 0, sP = 0, sLP = 0;
+  if (colin) {
+    for (int yy = max(0, y0 - r); yy <= min(H - 1, y0 + r); ++yy) {
+      const uint2 v = LP[(int64_t)yy * W + xl];
+      const unsigned long long L = v.x, P = v.y;
+      sL += L; sLL += L * L; sP += P; sLP += L * P;
+    }
+  }
+  const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
+  const double eps = (double)fd.eps;
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0 && colin) {
+      if (y + r < H) {
+        const uint2 v = LP[(int64_t)(y + r) * W + xl];
+        const unsigned long long L = v.x, P = v.y;
+        sL += L; sLL += L * L; sP += P; sLP += L * P;
+      }
+      if (y - r - 1 >= 0) {
+        const uint2 v = LP[(int64_t)(y - r - 1) * W + xl];
+        const unsigned long long L = v.x, P = v.y;
+        sL -= L; sLL -= L * L; sP -= P; sLP -= L * P;
+      }
+    }
+    s_q[0][tid] = colin ? sL : 0ull;
+    s_q[1][tid] = colin ? sLL : 0ull;
+    s_q[2][tid] = colin ? sP : 0ull;
+    s_q[3][tid] = colin ? sLP : 0ull;
+    __syncthreads();
+    {  // wave wv prefix-sums quantity wv over the 256 columns (4 per lane)
+      unsigned long long v0 = s_q[wv][4 * lane], v1 = s_q[wv][4 * lane + 1],
+                         v2 = s_q[wv][4 * lane + 2], v3 = s_q[wv][4 * lane + 3];
+      v1 += v0; v2 += v1; v3 += v2;
+      const unsigned long long ex = wave_incl_scan(v3) - v3;
+      s_q[wv][4 * lane] = v0 + ex;
+      s_q[wv][4 * lane + 1] = v1 + ex;
+      s_q[wv][4 * lane + 2] = v2 + ex;
+      s_q[wv][4 * lane + 3] = v3 + ex;
+    }
+    __syncthreads();
+    const int x = x0 + tid;
+    if (tid < SW && x < W) {
+      const int lo = max(x - r, 0), hi = min(x + r, W - 1);
+      const int clo = lo - (x0 - r), chi = hi - (x0 - r);
+      unsigned long long q[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = s_q[k][chi] - (clo > 0 ? s_q[k][clo - 1] : 0ull);
+      const int n = (hi - lo + 1) * (min(y + r, H - 1) - max(y - r, 0) + 1);
+      const double in = 1.0 / (double)n;
+      const double mG = (double)q[0] * in * kG;
+      const double mGG = (double)q[1] * in * (kG * kG);
+      const double mP = (double)q[2] * in * kP;
+      const double mGP = (double)q[3] * in * (kG * kP);
+      const double var = mGG - mG * mG;
+      const double cov = mGP - mG * mP;
+      const double a = cov / (var + eps);
+      const double bb = mP - a * mG;
+      const double s = (double)fd.ab_scale;
+      const double lim = 2147483647.0;
+      const double ia = fmin(fmax(__builtin_rint(a * s), -lim), lim);
+      const double ib = fmin(fmax(__builtin_rint(bb * s), -lim), lim);
+      fd.AB[(int64_t)y * W + x] = make_int2((int)ia, (int)ib);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------- k_gf_q
+// Eq. (6), stage 2: box means of a and b (exact i64 sums of the fixed-point
+// values, same strip scheme), q = mean(a) G + mean(b), clamped to [t0, 1].
+// PHASE 0: fuse Eqs. (7)-(8) and write the output.  PHASE 1: store the
+// refined t and the colour-balance partial sums of J_gamma.
+template <int PHASE, bool FP16>
+__global__ __launch_bounds__(256) void k_gf_q(Batch b) {
+  __shared__ long long s_q[2][kGfCols];
+  __shared__ float s_red[4];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  const int W = fd.W, H = fd.H, r = fd.radius;
+  const int SW = kGfCols - 2 * r;
+  const int strips = (W + SW - 1) / SW;
+  const int sx = tile % strips, sy = tile / strips;
+  const int x0 = sx * SW, y0 = sy * kGfRows, y1 = min(H, y0 + kGfRows);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int xl = x0 - r + tid;
+  const bool colin = (xl >= 0 && xl < W);
+  const int2* AB = fd.AB;
+  const ReconConsts rc = recon_consts(fd);
+
+  long long sa = 0, sb = 0;
+  if (colin) {
+    for (int yy = max(0, y0 - r); yy <= min(H - 1, y0 + r); ++yy) {
+      const int2 v = AB[(int64_t)yy * W + xl];
+      sa += v.x; sb += v.y;
+    }
+  }
+  float acc[3] = {0.f, 0.f, 0.f};
+  const double inv_s = (double)fd.ab_inv_scale;
+  const double t0 = (double)fd.t0;
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0 && colin) {
+      if (y + r < H) {
+        const int2 v = AB[(int64_t)(y + r) * W + xl];
+        sa += v.x; sb += v.y;
+      }
+      if (y - r - 1 >= 0) {
+        const int2 v = AB[(int64_t)(y - r - 1) * W + xl];
+        sa -= v.x; sb -= v.y;
+      }
+    }
+    s_q[0][tid] = colin ? sa : 0ll;
+    s_q[1][tid] = colin ? sb : 0ll;
+    __syncthreads();
+    if (wv < 2) {
+      long long v0 = s_q[wv][4 * lane], v1 = s_q[wv][4 * lane + 1], v2 = s_q[wv][4 * lane + 2],
+                v3 = s_q[wv][4 * lane + 3];
+      v1 += v0; v2 += v1; v3 += v2;
+      const long long ex = wave_incl_scan(v3) - v3;
+      s_q[wv][4 * lane] = v0 + ex;
+      s_q[wv][4 * lane + 1] = v1 + ex;
+      s_q[wv][4 * lane + 2] = v2 + ex;
+      s_q[wv][4 * lane + 3] = v3 + ex;
+    }
+    __syncthreads();
+    const int x = x0 + tid;
+    if (tid < SW && x < W) {
+      const int lo = max(x - r, 0), hi = min(x + r, W - 1);
+      const int clo = lo - (x0 - r), chi = hi - (x0 - r);
+      const long long qa = s_q[0][chi] - (clo > 0 ? s_q[0][clo - 1] : 0ll);
+      const long long qb = s_q[1][chi] - (clo > 0 ? s_q[1][clo - 1] : 0ll);
+      const int n = (hi - lo + 1) * (min(y + r, H - 1) - max(y - r, 0) + 1);
+      const double in = inv_s / (double)n;
+      const uint2 lp = fd.LP[(int64_t)y * W + x];
+      const double G = (double)lp.x * (1.0 / 255000.0);
+      const double q = (double)qa * in * G + (double)qb * in;
+      float t = (float)fmin(fmax(q, t0), 1.0);
+      if (FP16) t = round_half(t);
+      if (fd.t_out) fd.t_out[(int64_t)y * W + x] = t;
+      const uint8_t* p = fd.src + (int64_t)y * fd.src_pitch + 3 * x;
+      float I[3], J[3], Jg[3];
+      load_rgb(p, I[0], I[1], I[2]);
+      recon_pixel(rc, I, t, J, Jg);
+      if (fd.J_out) {
+        float* jo = fd.J_out + ((int64_t)y * W + x) * 3;
+        jo[0] = J[0]; jo[1] = J[1]; jo[2] = J[2];
+      }
+      if (PHASE == 0) {
+        uint8_t* o = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x;
+        o[0] = (uint8_t)rne_u8(Jg[0]);
+        o[1] = (uint8_t)rne_u8(Jg[1]);
+        o[2] = (uint8_t)rne_u8(Jg[2]);
+      } else {
+        if (FP16) reinterpret_cast<__half*>(fd.tmap)[(int64_t)y * W + x] = __float2half_rn(t);
+        else reinterpret_cast<float*>(fd.tmap)[(int64_t)y * W + x] = t;
+        acc[0] += Jg[0]; acc[1] += Jg[1]; acc[2] += Jg[2];
+      }
+    }
+    __syncthreads();
+  }
+  if (PHASE == 1) {
+    // deterministic per-block partials, then the last block forms the gains
+    float s0 = block_sum(acc[0], s_red), s1 = block_sum(acc[1], s_red), s2 = block_sum(acc[2], s_red);
+    if (tid == 0) fd.cbpart[tile] = make_float4(s0, s1, s2, 0.f);
+    __threadfence();
+    __syncthreads();
+    __shared__ int s_last;
+    const int nblk = b.tile0[f + 1] - b.tile0[f];
+    if (tid == 0) s_last = (atomicAdd(&fd.st->ticket_cb, 1u) == (uint32_t)(nblk - 1));
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    __shared__ double s_d[4];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int i = tid; i < nblk; i += 256) {
+      const float4 pp = fd.cbpart[i];
+      m[0] += pp.x; m[1] += pp.y; m[2] += pp.z;
+    }
+    for (int c = 0; c < 3; ++c) m[c] = block_sum(m[c], s_d);
+    if (tid == 0) {
+      const double n = (double)W * (double)H;
+      const double mu[3] = {m[0] / n, m[1] / n, m[2] / n};
+      const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
+      for (int c = 0; c < 3; ++c) fd.st->gains[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ k_recon
+// Pointwise Eqs. (4)-(5) (or the refined t), Eq. (7), Eq. (8) and the colour
+// balance.  A block covers kReconPx pixels of one row, 4 per thread.
+// PHASE 0: write the output.  PHASE 1: colour-balance partial sums only (the
+// last block forms the gains).  PHASE 2: apply the gains and write.
+template <int TSRC, int PHASE, bool FP16>
+__global__ __launch_bounds__(256) void k_recon(Batch b) {
+  __shared__ float s_red[4];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  const int W = fd.W;
+  const int per_row = (W + kReconPx - 1) / kReconPx;
+  const int y = tile / per_row;
+  const int x0 = (tile - y * per_row) * kReconPx + 4 * threadIdx.x;
+  const int tid = threadIdx.x;
+  const TxConsts k = tx_consts(fd);
+  const ReconConsts rc = recon_consts(fd);
+  float gain[3] = {1.f, 1.f, 1.f};
+  if (PHASE == 2) {
+    gain[0] = fd.st->gains[0]; gain[1] = fd.st->gains[1]; gain[2] = fd.st->gains[2];
+  }
+  float acc[3] = {0.f, 0.f, 0.f};
+  if (x0 < W) {
+    const int nx = min(4, W - x0);
+    const uint8_t* Ip = fd.src + (int64_t)y * fd.src_pitch + 3 * x0;
+    uint32_t iw[3];
+    if (fd.aligned && nx == 4) {
+      const uint32_t* q = reinterpret_cast<const uint32_t*>(Ip);
+      iw[0] = q[0]; iw[1] = q[1]; iw[2] = q[2];
+    } else {
+      uint8_t tmp[12] = {0};
+      for (int i = 0; i < 3 * nx; ++i) tmp[i] = Ip[i];
+      iw[0] = tmp[0] | (tmp[1] << 8) | (tmp[2] << 16) | ((uint32_t)tmp[3] << 24);
+      iw[1] = tmp[4] | (tmp[5] << 8) | (tmp[6] << 16) | ((uint32_t)tmp[7] << 24);
+      iw[2] = tmp[8] | (tmp[9] << 8) | (tmp[10] << 16) | ((uint32_t)tmp[11] << 24);
+    }
+    uint32_t ew[3] = {0, 0, 0};
+    if (TSRC == TSRC_HE) {
+      const uint8_t* Ep = fd.E + (int64_t)y * fd.E_pitch + 3 * x0;
+      if (nx == 4) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(Ep);
+        ew[0] = q[0]; ew[1] = q[1]; ew[2] = q[2];
+      } else {
+        uint8_t tmp[12] = {0};
+        for (int i = 0; i < 3 * nx; ++i) tmp[i] = Ep[i];
+        ew[0] = tmp[0] | (tmp[1] << 8) | (tmp[2] << 16) | ((uint32_t)tmp[3] << 24);
+        ew[1] = tmp[4] | (tmp[5] << 8) | (tmp[6] << 16) | ((uint32_t)tmp[7] << 24);
+        ew[2] = tmp[8] | (tmp[9] << 8) | (tmp[10] << 16) | ((uint32_t)tmp[11] << 24);
+      }
+    }
+    uint32_t ow[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i < nx) {
+        float I[3], J[3], Jg[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int byte = 3 * i + c;
+          I[c] = (float)((iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
+        }
+        float t;
+        if (TSRC == TSRC_HE) {
+          float e[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int byte = 3 * i + c;
+            e[c] = (float)((ew[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
+          }
+          t = tx_he(k, e[0], e[1], e[2]);
+        } else if (TSRC == TSRC_PAPER) {
+          t = tx_paper(k, fminf(fminf(I[0], I[1]), I[2]));
+        } else {
+          const int64_t pi = (int64_t)y * W + x0 + i;
+          t = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi])
+                   : reinterpret_cast<const float*>(fd.tmap)[pi];
+        }
+        if (FP16) t = round_half(t);
+        recon_pixel(rc, I, t, J, Jg);
+        if (PHASE == 1) {
+          acc[0] += Jg[0]; acc[1] += Jg[1]; acc[2] += Jg[2];
+        } else {
+          const int64_t pi = (int64_t)y * W + x0 + i;
+          if (fd.t_out) fd.t_out[pi] = t;
+          if (fd.J_out) {
+            fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float v = (PHASE == 2) ? fminf(255.0f, gain[c] * Jg[c]) : Jg[c];
+            const int byte = 3 * i + c;
+            ow[byte >> 2] |= rne_u8(v) << (8 * (byte & 3));
+          }
+        }
+      }
+    }
+    if (PHASE != 1) {
+      uint8_t* Op = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x0;
+      if (fd.aligned && nx == 4) {
+        uint32_t* q = reinterpret_cast<uint32_t*>(Op);
+        q[0] = ow[0]; q[1] = ow[1]; q[2] = ow[2];
+      } else {
+        for (int i = 0; i < 3 * nx; ++i) Op[i] = (uint8_t)(ow[i >> 2] >> (8 * (i & 3)));
+      }
+    }
+  }
+  if (PHASE == 1) {
+    float s0 = block_sum(acc[0], s_red), s1 = block_sum(acc[1], s_red), s2 = block_sum(acc[2], s_red);
+    if (tid == 0) fd.cbpart[tile] = make_float4(s0, s1, s2, 0.f);
+    __threadfence();
+    __syncthreads();
+    __shared__ int s_last;
+    const int nblk = b.tile0[f + 1] - b.tile0[f];
+    if (tid == 0) s_last = (atomicAdd(&fd.st->ticket_cb, 1u) == (uint32_t)(nblk - 1));
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    __shared__ double s_d[4];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int i = tid; i < nblk; i += 256) {
+      const float4 pp = fd.cbpart[i];
+      m[0] += pp.x; m[1] += pp.y; m[2] += pp.z;
+    }
+    for (int c = 0; c < 3; ++c) m[c] = block_sum(m[c], s_d);
+    if (tid == 0) {
+      const double n = (double)W * (double)fd.H;
+      const double mu[3] = {m[0] / n, m[1] / n, m[2] / n};
+      const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
+      for (int c = 0; c < 3; ++c) fd.st->gains[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
+    }
+  }
+}
+
+// ----------------------------------------------------------------- launches
+namespace {
+
+template <typename Fn>
+int fill_tiles(Batch& b, Fn blocks_of) {
+  int acc = 0;
+  for (int i = 0; i < b.n; ++i) {
+    b.tile0[i] = acc;
+    acc += blocks_of(b.f[i]);
+  }
+  b.tile0[b.n] = acc;
+  return acc;
+}
+
+template <int HP>
+hipError_t dark_hp(const Batch& b, int nblk, bool write_E, hipStream_t s) {
+  if (write_E) hipLaunchKernelGGL((k_dark<HP, true>), dim3(nblk), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL((k_dark<HP, false>), dim3(nblk), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init(Batch b, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(b.n), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s) {
+  const int nblk = fill_tiles(b, [](const FrameDev& f) {
+    return ((f.W + kDarkTW - 1) / kDarkTW) * ((f.H + kDarkTH - 1) / kDarkTH);
+  });
+  switch (g.half_patch) {
+    case 0: return dark_hp<0>(b, nblk, write_E, s);
+    case 1: return dark_hp<1>(b, nblk, write_E, s);
+    case 2: return dark_hp<2>(b, nblk, write_E, s);
+    case 3: return dark_hp<3>(b, nblk, write_E, s);
+    case 4: return dark_hp<4>(b, nblk, write_E, s);
+    case 5: return dark_hp<5>(b, nblk, write_E, s);
+    case 6: return dark_hp<6>(b, nblk, write_E, s);
+    case 7: return dark_hp<7>(b, nblk, write_E, s);
+    case 8: return dark_hp<8>(b, nblk, write_E, s);
+    case 9: return dark_hp<9>(b, nblk, write_E, s);
+    case 10: return dark_hp<10>(b, nblk, write_E, s);
+    case 11: return dark_hp<11>(b, nblk, write_E, s);
+    case 12: return dark_hp<12>(b, nblk, write_E, s);
+    case 13: return dark_hp<13>(b, nblk, write_E, s);
+    case 14: return dark_hp<14>(b, nblk, write_E, s);
+    case 15: return dark_hp<15>(b, nblk, write_E, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_select(Batch b, hipStream_t s) {
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return (f.H + 3) / 4; });
+  hipLaunchKernelGGL(k_select, dim3(nblk), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s) {
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return recon_blocks(f.W, f.H); });
+  if (g.tx == HZD_TX_HE) hipLaunchKernelGGL((k_gf_prep<TSRC_HE>), dim3(nblk), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL((k_gf_prep<TSRC_PAPER>), dim3(nblk), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s) {
+  (void)g;
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius); });
+  hipLaunchKernelGGL(k_gf_ab, dim3(nblk), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s) {
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius); });
+  if (g.cb) {
+    if (g.fp16) hipLaunchKernelGGL((k_gf_q<1, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<1, false>), dim3(nblk), dim3(256), 0, s, b);
+  } else {
+    if (g.fp16) hipLaunchKernelGGL((k_gf_q<0, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<0, false>), dim3(nblk), dim3(256), 0, s, b);
+  }
+  return hipGetLastError();
+}
+
+namespace {
+template <int TSRC, int PHASE>
+hipError_t recon_tp(const Batch& b, int nblk, bool fp16, hipStream_t s) {
+  if (fp16) hipLaunchKernelGGL((k_recon<TSRC, PHASE, true>), dim3(nblk), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL((k_recon<TSRC, PHASE, false>), dim3(nblk), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+template <int TSRC>
+hipError_t recon_t(const Batch& b, int nblk, int phase, bool fp16, hipStream_t s) {
+  switch (phase) {
+    case 0: return recon_tp<TSRC, 0>(b, nblk, fp16, s);
+    case 1: return recon_tp<TSRC, 1>(b, nblk, fp16, s);
+    case 2: return recon_tp<TSRC, 2>(b, nblk, fp16, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_recon(Batch b, const GroupKey& g, int tsrc, int phase, hipStream_t s) {
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return recon_blocks(f.W, f.H); });
+  switch (tsrc) {
+    case TSRC_HE: return recon_t<TSRC_HE>(b, nblk, phase, g.fp16, s);
+    case TSRC_PAPER: return recon_t<TSRC_PAPER>(b, nblk, phase, g.fp16, s);
+    case TSRC_TMAP: return recon_t<TSRC_TMAP>(b, nblk, phase, g.fp16, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace hzd

@@ -1,0 +1,23 @@
+// Host-side planning helpers shared by the frame/batch entry points and the
+// server (hzd_api.cpp, hzd_server.cpp).
+#pragma once
+
+#include <stddef.h>
+
+#include "hzd.h"
+#include "hzd_internal.h"
+
+namespace hzd {
+
+int fail(int status, const char* fmt, ...);
+void clear_error();
+int validate_params(const hzd_params* p);
+int validate_frame(const hzd_frame* f, int idx);
+GroupKey group_key(const hzd_params& p);
+bool operator<(const GroupKey& a, const GroupKey& b);
+size_t frame_ws_bytes(const hzd_params& p, int W, int H);
+FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws);
+int run_group(const GroupKey& g, const Batch& b, hipStream_t s);
+int check(hipError_t e, const char* what);
+
+}  // namespace hzd

@@ -1,0 +1,469 @@
+// Continuous-batching server for streams of frames.
+//
+// One scheduler thread per server.  Streams reserve their device state and
+// workspaces in the caller's arena at open (admission by HBM budget).
+// Submitted frames wait in a FIFO; whenever a HIP stream and in-flight
+// capacity are free, the scheduler takes the oldest frames that share one
+// launch group (same kernels), up to frames_per_launch, and launches them as
+// one batch; frames that arrive while others run join the next batch.  The
+// method is feed-forward per frame (paper Sec. V) and every kernel reduces in
+// an order fixed by the frame's own tiling, so a frame's result does not
+// depend on which batch it rode in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "hzd.h"
+#include "hzd_internal.h"
+#include "hzd_plan.h"
+
+using namespace hzd;
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// First-fit allocator over [0, size) of the arena, 256-byte granules.
+struct Arena {
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(size_t n) {
+    size = n & ~size_t(255);
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n, roff = it->first + n;
+        free_.erase(it);
+        if (rest) free_[roff] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const {
+    size_t f = 0;
+    for (auto& kv : free_) f += kv.second;
+    return size - f;
+  }
+};
+
+constexpr int kSlotsPerStream = 2;   // frames of one stream on the device at once
+constexpr int kMaxQueuedPerStream = 256;
+
+struct Job;
+
+}  // namespace
+
+struct hzd_stream {
+  hzd_server* srv = nullptr;
+  hzd_params p{};
+  int W = 0, H = 0;
+  size_t arena_off = 0, arena_len = 0;
+  size_t ws_bytes = 0;          // one slot's workspace
+  uint8_t* state_dev = nullptr; // A (3 floats) + sel (3 ints) of each slot
+  bool slot_busy[kSlotsPerStream] = {false, false};
+  int last_slot = -1;
+  uint64_t next_ticket = 1;
+  int queued = 0, inflight = 0;
+  bool closing = false;
+  std::map<uint64_t, int32_t> done;  // completed tickets not yet waited for
+  std::condition_variable cv;
+};
+
+namespace {
+struct Job {
+  hzd_stream* st;
+  hzd_frame fr;
+  hzd_done_fn cb;
+  void* user;
+  uint64_t ticket;
+  int64_t t_submit;
+  int slot = -1;
+};
+
+struct Launch {
+  hipEvent_t ev = nullptr;
+  int hs = -1;
+  std::vector<Job> jobs;
+  int status = HZD_OK;
+};
+}  // namespace
+
+struct hzd_server {
+  hzd_server_config cfg{};
+  std::vector<hipStream_t> hstreams;
+  std::vector<bool> hs_busy;
+  std::vector<hipEvent_t> events;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread thr;
+  bool stop = false;
+  Arena arena;
+  std::vector<hzd_stream*> streams;
+  std::deque<Job> queue;
+  std::vector<Launch> inflight;
+  int inflight_frames = 0;
+  hzd_server_stats stats{};
+};
+
+namespace {
+
+void finish(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
+  // called without the lock: completion callbacks may submit again
+  const int64_t t = now_ns();
+  for (auto& d : done) {
+    if (d.first.cb) d.first.cb(d.first.user, d.first.ticket, d.second, t - d.first.t_submit);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (auto& d : done) {
+    hzd_stream* st = d.first.st;
+    st->done[d.first.ticket] = d.second;
+    st->cv.notify_all();
+  }
+  done.clear();
+  s->cv.notify_all();
+}
+
+// Launch the oldest compatible frames on a free HIP stream.  Lock held.
+bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
+  if (s->queue.empty() || s->inflight_frames >= s->cfg.max_inflight) return false;
+  int hs = -1;
+  for (size_t i = 0; i < s->hs_busy.size(); ++i)
+    if (!s->hs_busy[i]) { hs = (int)i; break; }
+  if (hs < 0) return false;
+  Launch L;
+  GroupKey key{};
+  bool have_key = false;
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    if ((int)L.jobs.size() >= s->cfg.frames_per_launch ||
+        s->inflight_frames + (int)L.jobs.size() >= s->cfg.max_inflight)
+      break;
+    hzd_stream* st = it->st;
+    int slot = -1;
+    for (int k = 0; k < kSlotsPerStream; ++k)
+      if (!st->slot_busy[k]) { slot = k; break; }
+    const GroupKey gk = group_key(st->p);
+    if (slot < 0 || (have_key && (gk < key || key < gk))) { ++it; continue; }
+    // keep a stream's frames in submission order: skip later frames of a
+    // stream whose earlier frame could not be taken
+    bool earlier_waiting = false;
+    for (auto jt = s->queue.begin(); jt != it; ++jt)
+      if (jt->st == st) { earlier_waiting = true; break; }
+    if (earlier_waiting) { ++it; continue; }
+    key = gk;
+    have_key = true;
+    Job j = *it;
+    j.slot = slot;
+    st->slot_busy[slot] = true;
+    st->queued--;
+    st->inflight++;
+    L.jobs.push_back(j);
+    it = s->queue.erase(it);
+  }
+  if (L.jobs.empty()) return false;
+  Batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.n = (int)L.jobs.size();
+  for (int i = 0; i < b.n; ++i) {
+    const Job& j = L.jobs[i];
+    hzd_stream* st = j.st;
+    uint8_t* base = reinterpret_cast<uint8_t*>(s->cfg.arena) + st->arena_off;
+    uint8_t* state = base + 256 * j.slot;
+    hzd_frame_aux aux{};
+    aux.A_out = reinterpret_cast<float*>(state);
+    aux.sel_out = reinterpret_cast<int32_t*>(state + 16);
+    uint8_t* ws = base + 256 * kSlotsPerStream + st->ws_bytes * j.slot;
+    b.f[i] = make_frame_dev(st->p, j.fr, &aux, ws);
+  }
+  (void)hipSetDevice(s->cfg.device);
+  int rc = run_group(key, b, s->hstreams[hs]);
+  if (rc == HZD_OK) rc = check(hipEventRecord(s->events[hs], s->hstreams[hs]), "event record");
+  s->stats.launches++;
+  if (rc != HZD_OK) {
+    for (auto& j : L.jobs) {
+      j.st->slot_busy[j.slot] = false;
+      j.st->inflight--;
+      s->stats.failed++;
+      done.emplace_back(j, rc);
+    }
+    return true;
+  }
+  L.ev = s->events[hs];
+  L.hs = hs;
+  s->hs_busy[hs] = true;
+  s->inflight_frames += (int)L.jobs.size();
+  s->inflight.push_back(std::move(L));
+  return true;
+}
+
+// Collect finished launches.  Lock held.
+bool reap(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
+  bool any = false;
+  for (size_t i = 0; i < s->inflight.size();) {
+    Launch& L = s->inflight[i];
+    const hipError_t q = hipEventQuery(L.ev);
+    if (q == hipErrorNotReady) { ++i; continue; }
+    const int32_t status = (q == hipSuccess) ? HZD_OK : HZD_E_DEVICE;
+    for (auto& j : L.jobs) {
+      j.st->slot_busy[j.slot] = false;
+      j.st->last_slot = j.slot;
+      j.st->inflight--;
+      if (status == HZD_OK) s->stats.completed++;
+      else s->stats.failed++;
+      done.emplace_back(j, status);
+    }
+    s->hs_busy[L.hs] = false;
+    s->inflight_frames -= (int)L.jobs.size();
+    s->inflight.erase(s->inflight.begin() + i);
+    any = true;
+  }
+  return any;
+}
+
+void scheduler(hzd_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  std::vector<std::pair<Job, int32_t>> done;
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    bool progressed = reap(s, done);
+    while (admit(s, done)) progressed = true;
+    if (!done.empty()) {
+      lk.unlock();
+      finish(s, done);
+      lk.lock();
+      continue;
+    }
+    if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+    if (progressed) continue;
+    if (s->inflight.empty()) {
+      s->cv.wait(lk);
+    } else {
+      // device work in flight: poll its events at a fine grain
+      s->cv.wait_for(lk, std::chrono::microseconds(20));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int hzd_server_create(const hzd_server_config* cfg, hzd_server** out) {
+  if (!cfg || !out) return fail(HZD_E_INVAL, "NULL argument");
+  if (cfg->size != sizeof(hzd_server_config)) return fail(HZD_E_INVAL, "config size mismatch");
+  if (!cfg->arena || (uintptr_t)cfg->arena % 256) return fail(HZD_E_INVAL, "arena NULL or not 256-aligned");
+  if (cfg->max_inflight < 1) return fail(HZD_E_INVAL, "max_inflight < 1");
+  if (cfg->frames_per_launch < 1 || cfg->frames_per_launch > kMaxBatch)
+    return fail(HZD_E_INVAL, "frames_per_launch outside 1..%d", kMaxBatch);
+  if (cfg->hip_streams < 1 || cfg->hip_streams > 8) return fail(HZD_E_INVAL, "hip_streams outside 1..8");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+    return fail(HZD_E_INVAL, "device %d not available", cfg->device);
+  hzd_server* s = new hzd_server();
+  s->cfg = *cfg;
+  s->arena.init(cfg->arena_bytes);
+  (void)hipSetDevice(cfg->device);
+  for (int i = 0; i < cfg->hip_streams; ++i) {
+    hipStream_t hs;
+    hipEvent_t ev;
+    if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      for (auto h : s->hstreams) (void)hipStreamDestroy(h);
+      for (auto e : s->events) (void)hipEventDestroy(e);
+      delete s;
+      return fail(HZD_E_DEVICE, "stream/event creation failed");
+    }
+    s->hstreams.push_back(hs);
+    s->events.push_back(ev);
+    s->hs_busy.push_back(false);
+  }
+  s->stats.arena_bytes = s->arena.size;
+  s->thr = std::thread(scheduler, s);
+  *out = s;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_server_destroy(hzd_server* s) {
+  if (!s) return fail(HZD_E_INVAL, "server is NULL");
+  std::vector<std::pair<Job, int32_t>> cancelled;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto& j : s->queue) {
+      j.st->queued--;
+      cancelled.emplace_back(j, HZD_E_CLOSED);
+    }
+    s->queue.clear();
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  finish(s, cancelled);
+  s->thr.join();
+  for (hzd_stream* st : s->streams) delete st;
+  for (auto h : s->hstreams) (void)hipStreamDestroy(h);
+  for (auto e : s->events) (void)hipEventDestroy(e);
+  delete s;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int32_t height,
+                    hzd_stream** out) {
+  if (!s || !out) return fail(HZD_E_INVAL, "NULL argument");
+  int rc = validate_params(params);
+  if (rc) return rc;
+  if (width < 1 || height < 1 || (int64_t)width * height >= (int64_t(1) << 31))
+    return fail(HZD_E_INVAL, "size %dx%d", width, height);
+  hzd_stream* st = new hzd_stream();
+  st->srv = s;
+  st->p = *params;
+  st->W = width;
+  st->H = height;
+  st->ws_bytes = (frame_ws_bytes(*params, width, height) + 255) & ~size_t(255);
+  st->arena_len = 256 * kSlotsPerStream + st->ws_bytes * kSlotsPerStream;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete st;
+      return fail(HZD_E_CLOSED, "server is shutting down");
+    }
+    if (!s->arena.alloc(st->arena_len, &st->arena_off)) {
+      delete st;
+      return fail(HZD_E_AGAIN, "arena has no room for %zu bytes (%zu used of %zu)", st->arena_len,
+                  s->arena.used(), s->arena.size);
+    }
+    st->state_dev = reinterpret_cast<uint8_t*>(s->cfg.arena) + st->arena_off;
+    s->streams.push_back(st);
+    s->stats.open_streams = (int)s->streams.size();
+    s->stats.arena_used = s->arena.used();
+  }
+  *out = st;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
+                      uint64_t* ticket) {
+  if (!st || !frame) return fail(HZD_E_INVAL, "NULL argument");
+  int rc = validate_frame(frame, 0);
+  if (rc) return rc;
+  if (frame->width != st->W || frame->height != st->H)
+    return fail(HZD_E_INVAL, "frame %dx%d does not match stream %dx%d", frame->width, frame->height, st->W,
+                st->H);
+  hzd_server* s = st->srv;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (st->closing || s->stop) return fail(HZD_E_CLOSED, "stream is closing");
+  if (st->queued >= kMaxQueuedPerStream) return fail(HZD_E_AGAIN, "stream queue full");
+  Job j;
+  j.st = st;
+  j.fr = *frame;
+  j.fr.params = nullptr;
+  j.cb = cb;
+  j.user = user;
+  j.ticket = st->next_ticket++;
+  j.t_submit = now_ns();
+  st->queued++;
+  s->queue.push_back(j);
+  s->stats.submitted++;
+  if (ticket) *ticket = j.ticket;
+  s->cv.notify_all();
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns) {
+  if (!st) return fail(HZD_E_INVAL, "stream is NULL");
+  hzd_server* s = st->srv;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (ticket == 0 || ticket >= st->next_ticket) return fail(HZD_E_INVAL, "unknown ticket %llu",
+                                                            (unsigned long long)ticket);
+  auto ready = [&] { return st->done.count(ticket) > 0; };
+  if (timeout_ns < 0) {
+    st->cv.wait(lk, ready);
+  } else if (!st->cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready)) {
+    return fail(HZD_E_TIMEOUT, "ticket %llu not complete", (unsigned long long)ticket);
+  }
+  const int32_t status = st->done[ticket];
+  st->done.erase(ticket);
+  return status;
+}
+
+int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host) {
+  if (!st) return fail(HZD_E_INVAL, "stream is NULL");
+  int slot;
+  {
+    std::lock_guard<std::mutex> lk(st->srv->mu);
+    slot = st->last_slot;
+  }
+  if (slot < 0) return fail(HZD_E_AGAIN, "no frame of this stream has completed yet");
+  (void)hipSetDevice(st->srv->cfg.device);
+  uint8_t buf[32];
+  int rc = check(hipMemcpy(buf, st->state_dev + 256 * slot, 32, hipMemcpyDeviceToHost), "state copy");
+  if (rc) return rc;
+  if (A_host) std::memcpy(A_host, buf, 12);
+  if (sel_host) std::memcpy(sel_host, buf + 16, 12);
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_stream_close(hzd_stream* st) {
+  if (!st) return fail(HZD_E_INVAL, "stream is NULL");
+  hzd_server* s = st->srv;
+  std::unique_lock<std::mutex> lk(s->mu);
+  st->closing = true;
+  st->cv.wait(lk, [&] { return st->queued == 0 && st->inflight == 0; });
+  s->arena.release(st->arena_off, st->arena_len);
+  s->streams.erase(std::remove(s->streams.begin(), s->streams.end(), st), s->streams.end());
+  s->stats.open_streams = (int)s->streams.size();
+  s->stats.arena_used = s->arena.used();
+  lk.unlock();
+  delete st;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_server_stats_get(hzd_server* s, hzd_server_stats* out) {
+  if (!s || !out) return fail(HZD_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->inflight = s->inflight_frames;
+  out->arena_used = s->arena.used();
+  clear_error();
+  return HZD_OK;
+}
+
+}  // extern "C"

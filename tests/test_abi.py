@@ -1,0 +1,135 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/hzd.h declares, and rejects bad arguments before
+any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2512_16609_amd as hzd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hzd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(hzd_[a-z_]+)\s*\(", text))
+    return sorted(n for n in names if not n.endswith("_fn"))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return hzd.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hzd.SYMBOLS), "binding and header disagree"
+    assert L.hzd_abi_version() == 1
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(hzd.hzd_params) == 4 * 13
+    assert ctypes.sizeof(hzd.hzd_frame) == 8 + 8 + 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(hzd.hzd_frame_aux) == 5 * 8
+
+
+def test_presets(L):
+    p = hzd.Params.preset(hzd.PRESET_REALTIME)
+    assert (p.mode, p.patch, p.tx, p.color_balance) == (hzd.MODE_REALTIME, 15, hzd.TX_HE, 0)
+    assert abs(p.omega - 0.95) < 1e-7 and abs(p.t0 - 0.1) < 1e-7 and abs(p.alpha - 0.8) < 1e-7
+    q = hzd.Params.preset(hzd.PRESET_OFFLINE)
+    assert (q.mode, q.gf_radius, q.color_balance) == (hzd.MODE_OFFLINE, 60, 1)
+    r = hzd.Params.preset(hzd.PRESET_PAPER_REALTIME)
+    assert r.tx == hzd.TX_PAPER and abs(r.omega - 0.5) < 1e-7 and abs(r.t0 - 0.05) < 1e-7
+    with pytest.raises(hzd.HzdError):
+        hzd.Params.preset(7)
+
+
+FAKE_SRC = 0x10000000
+FAKE_DST = 0x20000000
+
+
+def call_frame(L, p: hzd.Params, w=64, h=48, src=FAKE_SRC, dst=FAKE_DST, sp=None, dp=None,
+               ws=0x40000000, ws_bytes=1 << 40, size=None):
+    pc = p.c()
+    if size is not None:
+        pc.size = size
+    f = hzd.hzd_frame(src, sp if sp is not None else 3 * w, dst, dp if dp is not None else 3 * w, w, h, None)
+    return L.hzd_dehaze_frame(ctypes.byref(pc), ctypes.byref(f), None, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("patch", 14, hzd.HZD_E_INVAL), ("patch", 0, hzd.HZD_E_INVAL), ("patch", 33, hzd.HZD_E_UNSUPPORTED),
+    ("omega", -0.1, hzd.HZD_E_INVAL), ("omega", 1.5, hzd.HZD_E_INVAL), ("omega", float("nan"), hzd.HZD_E_INVAL),
+    ("t0", 0.0, hzd.HZD_E_INVAL), ("t0", 1.5, hzd.HZD_E_INVAL), ("top_frac", 0.0, hzd.HZD_E_INVAL),
+    ("top_frac", 1.01, hzd.HZD_E_INVAL), ("alpha", 0.0, hzd.HZD_E_INVAL), ("gamma", 0.0, hzd.HZD_E_INVAL),
+    ("mode", 3, hzd.HZD_E_INVAL), ("tx", 2, hzd.HZD_E_INVAL), ("precision", 5, hzd.HZD_E_INVAL),
+    ("color_balance", 2, hzd.HZD_E_INVAL),
+])
+def test_param_validation(L, field, value, status):
+    p = hzd.Params()
+    setattr(p, field, value)
+    assert call_frame(L, p) == status
+    assert hzd.last_error() != ""
+
+
+def test_offline_param_validation(L):
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=0)
+    assert call_frame(L, p) == hzd.HZD_E_INVAL
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=65)
+    assert call_frame(L, p) == hzd.HZD_E_UNSUPPORTED
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_eps=0.0)
+    assert call_frame(L, p) == hzd.HZD_E_INVAL
+
+
+def test_frame_validation(L):
+    p = hzd.Params()
+    assert call_frame(L, p, size=12) == hzd.HZD_E_INVAL                 # struct size mismatch
+    assert call_frame(L, p, w=0) == hzd.HZD_E_INVAL
+    assert call_frame(L, p, h=-3) == hzd.HZD_E_INVAL
+    assert call_frame(L, p, w=65536, h=32768) == hzd.HZD_E_INVAL        # W*H >= 2^31
+    assert call_frame(L, p, sp=100) == hzd.HZD_E_INVAL                  # pitch < 3W
+    assert call_frame(L, p, src=0) == hzd.HZD_E_INVAL                   # NULL src
+    assert call_frame(L, p, dst=FAKE_SRC + 100) == hzd.HZD_E_INVAL      # overlap
+    assert call_frame(L, p, ws=0) == hzd.HZD_E_INVAL
+    assert call_frame(L, p, ws=0x40000010) == hzd.HZD_E_INVAL           # misaligned workspace
+    assert call_frame(L, p, ws_bytes=1000) == hzd.HZD_E_NOMEM
+    assert L.hzd_dehaze_frame(None, None, None, None, 0, None) == hzd.HZD_E_INVAL
+    pc = p.c()
+    assert L.hzd_dehaze_batch(ctypes.byref(pc), None, 0, None, None, 0, None) == hzd.HZD_E_INVAL
+
+
+def test_workspace_size_grows_with_mode(L):
+    rt = hzd.workspace_size(hzd.Params(), [(1080, 1920)])
+    off = hzd.workspace_size(hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1), [(1080, 1920)])
+    assert rt > 1920 * 1080 * 4      # D + E + state
+    assert off > rt + 1920 * 1080 * 16
+    two = hzd.workspace_size(hzd.Params(), [(1080, 1920), (480, 640)])
+    assert two == rt + hzd.workspace_size(hzd.Params(), [(480, 640)])
+
+
+def test_status_strings(L):
+    for s in range(-7, 1):
+        assert L.hzd_status_str(s).decode() != "unknown status"
+    assert L.hzd_status_str(-99).decode() == "unknown status"
+
+
+def test_server_create_rejects_bad_config(L):
+    cfg = hzd.hzd_server_config(ctypes.sizeof(hzd.hzd_server_config), 0, 0x40000000, 1 << 20, 0, 4, 2)
+    h = ctypes.c_void_p()
+    assert L.hzd_server_create(ctypes.byref(cfg), ctypes.byref(h)) == hzd.HZD_E_INVAL   # max_inflight 0
+    cfg.max_inflight = 4
+    cfg.frames_per_launch = 17
+    assert L.hzd_server_create(ctypes.byref(cfg), ctypes.byref(h)) == hzd.HZD_E_INVAL
+    cfg.frames_per_launch = 4
+    cfg.arena = 0x40000010
+    assert L.hzd_server_create(ctypes.byref(cfg), ctypes.byref(h)) == hzd.HZD_E_INVAL
+    cfg.size = 8
+    assert L.hzd_server_create(ctypes.byref(cfg), ctypes.byref(h)) == hzd.HZD_E_INVAL

@@ -1,0 +1,161 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded bytes (element by element), at the configuration sizes and at
+ragged edge shapes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_16609_amd as hzd
+from synth import make_frame
+
+from parity import compare, oracle_params, run_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def P(**kw):
+    return hzd.Params(**kw)
+
+
+def _frame(w, h, seed, beta=1.0):
+    return make_frame(w, h, seed, beta=beta).I
+
+
+def test_c1_realtime_320x240():
+    I = _frame(320, 240, 1)
+    g = run_gpu(I, P())
+    s = compare(I, P(), g, label="C1")
+    print("C1", s)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (29, 1), (5, 7), (23, 37), (33, 65), (97, 130), (197, 333)])
+@pytest.mark.parametrize("patch", [1, 3, 15, 31])
+def test_ragged_shapes_realtime(shape, patch):
+    h, w = shape
+    rng = np.random.default_rng(h * 1000 + w + patch)
+    if h * w >= 64 * 64:
+        I = _frame(w, h, 7)
+    else:
+        I = rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8)
+    p = P(patch=patch, top_frac=0.01)
+    compare(I, p, run_gpu(I, p), label=f"{shape} p{patch}")
+
+
+def test_pitch_larger_than_row():
+    I = _frame(130, 97, 9)
+    for pad in (1, 5, 64):
+        compare(I, P(), run_gpu(I, P(), pitch_pad=pad), label=f"pad{pad}")
+        compare(I, P(mode=hzd.MODE_OFFLINE, gf_radius=12, color_balance=1),
+                run_gpu(I, P(mode=hzd.MODE_OFFLINE, gf_radius=12, color_balance=1), pitch_pad=pad),
+                label=f"offline pad{pad}")
+
+
+@pytest.mark.parametrize("tx", [hzd.TX_HE, hzd.TX_PAPER])
+@pytest.mark.parametrize("cb", [0, 1])
+@pytest.mark.parametrize("prec", [hzd.PREC_FP32, hzd.PREC_FP16])
+def test_realtime_variants(tx, cb, prec):
+    I = _frame(320, 240, 3, beta=1.4)
+    p = P(tx=tx, color_balance=cb, precision=prec)
+    compare(I, p, run_gpu(I, p), label=f"rt tx{tx} cb{cb} prec{prec}")
+
+
+@pytest.mark.parametrize("tx", [hzd.TX_HE, hzd.TX_PAPER])
+@pytest.mark.parametrize("cb", [0, 1])
+@pytest.mark.parametrize("prec", [hzd.PREC_FP32, hzd.PREC_FP16])
+@pytest.mark.parametrize("radius", [1, 8, 60, 64])
+def test_offline_variants(tx, cb, prec, radius):
+    I = _frame(203, 151, 4, beta=0.8)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=radius, tx=tx, color_balance=cb, precision=prec)
+    compare(I, p, run_gpu(I, p), label=f"off r{radius} tx{tx} cb{cb} prec{prec}")
+
+
+@pytest.mark.parametrize("gamma", [1.0, 1.2, 2.2])
+def test_gamma_values(gamma):
+    I = _frame(160, 120, 5)
+    p = P(gamma=gamma)
+    compare(I, p, run_gpu(I, p), label=f"gamma {gamma}")
+
+
+def test_c2_offline_1080p():
+    fr = make_frame(1920, 1080, 2)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, gf_eps=1e-3, color_balance=1)
+    s = compare(fr.I, p, run_gpu(fr.I, p), label="C2")
+    print("C2", s)
+
+
+def test_4k_offline_frame():
+    fr = make_frame(3840, 2160, 4000)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, gf_eps=1e-3)
+    s = compare(fr.I, p, run_gpu(fr.I, p, with_J=False), label="4K")
+    print("4K", s)
+
+
+@pytest.mark.parametrize("mode", [hzd.MODE_REALTIME, hzd.MODE_OFFLINE])
+@pytest.mark.parametrize("tx", [hzd.TX_HE, hzd.TX_PAPER])
+def test_identity_when_omega_zero(mode, tx):
+    I = _frame(211, 99, 6)
+    p = P(mode=mode, tx=tx, omega=0.0, gamma=1.0, gf_radius=10)
+    g = run_gpu(I, p)
+    assert np.array_equal(g["out"], I)
+    assert np.all(g["t"] == 1.0)
+
+
+def test_degenerate_frames():
+    # all black (the airlight divisor guard), all white, constant colour
+    for val in (0, 255, 117):
+        I = np.full((48, 80, 3), val, dtype=np.uint8)
+        for p in (P(), P(mode=hzd.MODE_OFFLINE, gf_radius=9, color_balance=1)):
+            compare(I, p, run_gpu(I, p), label=f"const {val}")
+
+
+def test_bright_blob_limitation():
+    I = _frame(320, 240, 12).copy()
+    I[100:140, 100:160] = 255
+    g = run_gpu(I, P())
+    compare(I, P(), g, label="blob")
+    assert int(g["sel"][1]) == 255
+
+
+def test_run_to_run_determinism():
+    I = _frame(640, 480, 8)
+    for p in (P(), P(mode=hzd.MODE_OFFLINE, color_balance=1)):
+        a, b = run_gpu(I, p), run_gpu(I, p)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_batch_equals_frame():
+    shapes = [(120, 160), (97, 130), (240, 320), (31, 45), (480, 640)]
+    params = [P(), P(patch=7), P(mode=hzd.MODE_OFFLINE, gf_radius=20, color_balance=1),
+              P(tx=hzd.TX_PAPER), P(color_balance=1, precision=hzd.PREC_FP16)]
+    frames = [_frame(w, h, 20 + i) for i, (h, w) in enumerate(shapes)]
+    srcs = [to_dev(I) for I in frames]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    auxs = [hzd.make_aux(h, w) for (h, w) in shapes]
+    hzd.dehaze_batch(srcs, dsts, P(), per_frame_params=params, auxs=auxs)
+    torch.cuda.synchronize()
+    for i, I in enumerate(frames):
+        alone = run_gpu(I, params[i])
+        assert np.array_equal(dsts[i].cpu().numpy(), alone["out"]), i
+        for k in ("A", "sel", "dark", "t", "J"):
+            assert np.array_equal(auxs[i][k].cpu().numpy(), alone[k]), (i, k)
+
+
+def test_same_shape_batch_of_eight_720p_fp16():
+    # one launch of 8 real-time 720p frames (FP16 t), every frame equal to its single-frame result
+    from synth import make_video
+    v = make_video(1280, 720, nframes=300, seed=3)
+    idx = [0, 37, 74, 111, 148, 185, 222, 259]
+    frames = [v.frame(f).I for f in idx]
+    p = P(precision=hzd.PREC_FP16)
+    srcs = [to_dev(I) for I in frames]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    hzd.dehaze_batch(srcs, dsts, p)
+    torch.cuda.synchronize()
+    for i, I in enumerate(frames[:3]):
+        ref = oracle.dehaze(I, oracle_params(p))
+        d = np.abs(dsts[i].cpu().numpy().astype(int) - ref.out.astype(int))
+        assert d.max() <= 1
+    for i, I in enumerate(frames):
+        assert np.array_equal(dsts[i].cpu().numpy(), run_gpu(I, p, with_J=False)["out"])
