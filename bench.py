@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-frame dehazing path on one MI355X.
+
+Metric: megapixels/s dehazed at 1080p, plain (hzd_dehaze_frame, one frame
+after another on one stream) versus served (hzd_stream_submit through the
+continuous-batching server), with p50/p99 frame latency.
+
+Workload (one step = one pass of the whole path over one frame): a seeded
+synthetic 1920x1080 RGB8 hazy frame, offline mode (dark channel patch 15,
+airlight top 0.1 %, transmission omega 0.95 / t0 0.1, guided filter r = 60,
+eps = 1e-3 on the BT.601 guide, gamma 1.2, gray-world colour balance), FP32
+with exact fixed-point box sums.  Inputs are resident in HBM before timing;
+the loop rotates over distinct src/dst/workspace sets whose total exceeds the
+256 MB Infinity Cache, so each step reads cold data.
+
+Prints ONE JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "megapixels/sec dehazed at 1080p (plain vs served); p50/p99 frame latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per pixel of each kernel (what it must read and write;
+# the design doc derives each figure).  Keys are the library's stage names.
+STAGE_BYTES_PER_PX = {
+    "dark": 7.0,          # I (3) in; D (1) + per-channel erosions E (3) out
+    "select": 1.0,        # D (1) in (+ I at the ~0.1 % selected pixels)
+    "gf_prep": 14.0,      # I (3) + E (3) in; luma/t fixed point LP (8) out
+    "gf_ab": 16.0,        # LP (8) in; a/b fixed point (8) out
+    "gf_q": 23.0,         # a/b (8) + LP (8) + I (3) in; refined t (4) out
+    "recon_apply": 10.0,  # I (3) + refined t (4) in; output (3) out
+    "recon": 9.0,         # I (3) + E (3) in; output (3) out
+    "recon_sums": 6.0,    # I (3) + E (3) in
+    "init": 0.0,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def cpu_baseline(I, p_oracle, budget_s: float):
+    """The FP64 oracle as it stands, single process, on a bounded sample."""
+    import oracle  # test infrastructure: used only for this reported baseline
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        oracle.dehaze(I, p_oracle)
+        times.append(time.perf_counter() - t0)
+        if len(times) >= 3 and time.perf_counter() - t_start >= budget_s:
+            break
+        if len(times) >= 20:
+            break
+    h, w, _ = I.shape
+    mp = w * h / 1e6
+    med = float(np.median(times))
+    return {"value": round(mp / med, 4), "unit": "MP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} runs of one {w}x{h} frame of this workload through the FP64 NumPy "
+                      f"oracle (single thread), median {med:.2f} s/frame; host: {cpu_model()}, "
+                      f"{os.cpu_count()} logical CPUs visible"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--rotate", type=int, default=10, help="distinct buffer sets cycled by the timed loop")
+    ap.add_argument("--served-streams", type=int, default=8)
+    ap.add_argument("--served-frames", type=int, default=40, help="frames per served stream")
+    ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path: frames and streams are independent and would shard "
+              "across GPUs with no communication.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_16609_amd as hzd
+    from synth import make_frame
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    hzd.lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    W, H = 1920, 1080
+    mp = W * H / 1e6
+    log("generating the 1080p frame")
+    fr = make_frame(W, H, 2)
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, patch=15, omega=0.95, t0=0.1, top_frac=0.001, alpha=0.8,
+                   gamma=1.2, gf_radius=60, gf_eps=1e-3, color_balance=1, tx=hzd.TX_HE,
+                   precision=hzd.PREC_FP32)
+    ws_bytes = hzd.workspace_size(p, [(H, W)])
+    src0 = torch.from_numpy(fr.I).to(dev)
+    sets = []
+    for _ in range(max(1, args.rotate)):
+        src = src0.clone()
+        dst = torch.empty_like(src)
+        ws = hzd.alloc_workspace(ws_bytes, dev)
+        sets.append((src, dst, ws))
+    working_set = sum(s.numel() + d.numel() + w.numel() for s, d, w in sets)
+    stream = torch.cuda.current_stream()
+    calls = [hzd.FrameCall(s, d, p, w, stream=stream) for s, d, w in sets]
+
+    # ---- plain: timed region
+    log("plain: warmup")
+    for i in range(args.warmup):
+        calls[i % len(calls)]()
+    torch.cuda.synchronize()
+    hzd.profile_read(reset=True)
+    hzd.profile_enable(True)
+    log(f"plain: {args.steps} timed steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        calls[i % len(calls)]()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = hzd.profile_read(reset=True)
+    hzd.profile_enable(False)
+    elapsed = t1 - t0
+    plain_mps = args.steps * mp / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # the same loop without stage events, to show what they cost
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        calls[i % len(calls)]()
+    torch.cuda.synchronize()
+    plain_mps_noev = args.steps * mp / (time.perf_counter() - t0)
+
+    # ---- plain: per-frame latency (one frame at a time, idle GPU)
+    lat = []
+    for i in range(args.latency_frames):
+        t0 = time.perf_counter()
+        calls[i % len(calls)]()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+
+    stage_rows = {}
+    for name, (n, tot_ms) in stages.items():
+        avg_us = 1e3 * tot_ms / max(n, 1)
+        bpp = STAGE_BYTES_PER_PX.get(name, 0.0)
+        gbs = bpp * W * H / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
+        stage_rows[name] = {"launches": n, "avg_us": round(avg_us, 3), "alg_bytes_per_px": bpp,
+                            "alg_GBps": round(gbs, 1)}
+    dom = max(stage_rows, key=lambda k: stage_rows[k]["avg_us"])
+    d = stage_rows[dom]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": d["alg_bytes_per_px"] * W * H, "avg_launch_us": d["avg_us"]}
+
+    # ---- served
+    served = None
+    if not args.no_served:
+        log("served: continuous batching")
+        S, F = args.served_streams, args.served_frames
+        per_stream_ws = 2 * (hzd.workspace_size(p, [(H, W)]) + 256) + 1024
+        srv = hzd.Server(arena_bytes=S * per_stream_ws + (1 << 20), max_inflight=16, frames_per_launch=8,
+                         hip_streams=4)
+        sts = [srv.open(p, W, H) for _ in range(S)]
+        srcs = [src0.clone() for _ in range(S)]
+        dsts = [[torch.empty_like(src0) for _ in range(2)] for _ in range(S)]
+        torch.cuda.synchronize()
+        # warm
+        tk = [st.submit(srcs[i], dsts[i][0]) for i, st in enumerate(sts)]
+        for st, t in zip(sts, tk):
+            st.wait(t)
+        # saturation throughput: every stream keeps its queue full
+        t0 = time.perf_counter()
+        tickets = []
+        for f in range(F):
+            for i, st in enumerate(sts):
+                tickets.append((st, st.submit(srcs[i], dsts[i][f % 2])))
+        for st, t in tickets:
+            rc, _ = st.wait(t)
+            assert rc == 0, rc
+        t_sat = time.perf_counter() - t0
+        served_mps = S * F * mp / t_sat
+        # latency under a paced load: each stream submits at 30 fps
+        rate = 30.0
+        n_paced = 30
+        t_base = time.perf_counter() + 0.01
+        sched = sorted((t_base + k / rate + i / (rate * S), i) for i in range(S) for k in range(n_paced))
+        paced = []
+        for when, i in sched:
+            while time.perf_counter() < when:
+                pass
+            paced.append((sts[i], sts[i].submit(srcs[i], dsts[i][len(paced) % 2])))
+        lat_paced = []
+        for st, t in paced:
+            rc, ns = st.wait(t)
+            assert rc == 0, rc
+            lat_paced.append(ns / 1e6)
+        stats = srv.stats()
+        for st in sts:
+            st.close()
+        srv.close()
+        served = {"MP_per_s": round(served_mps, 2), "streams": S, "frames": S * F,
+                  "vs_plain": round(served_mps / plain_mps_noev, 3),
+                  "latency_ms_at_30fps_per_stream": {"p50": round(percentile(lat_paced, 50), 3),
+                                                     "p99": round(percentile(lat_paced, 99), 3),
+                                                     "offered_MP_per_s": round(S * rate * mp, 1)},
+                  "launches": int(stats["launches"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle")
+        import oracle
+        po = oracle.Params(mode="offline", patch=15, omega=0.95, t0=0.1, top_frac=0.001, alpha=0.8, gamma=1.2,
+                           gf_radius=60, gf_eps=1e-3, color_balance=True, tx="he")
+        cpu = cpu_baseline(fr.I, po, args.cpu_budget)
+
+    out = {
+        "metric": METRIC, "value": round(plain_mps, 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "1920x1080 RGB8 synthetic hazy frame, offline mode: patch 15, top 0.1%, "
+                               "omega 0.95, t0 0.1, guided filter r=60 eps=1e-3, gamma 1.2, colour balance; "
+                               "one frame per step",
+                   "global_batch": 1, "seq_len": None, "parallelism": "single GPU",
+                   "rotating_buffer_sets": len(sets), "working_set_MB": round(working_set / 1e6, 1)},
+        "plain": {"MP_per_s": round(plain_mps, 2), "MP_per_s_without_stage_events": round(plain_mps_noev, 2),
+                  "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}},
+        "served": served,
+        "stages": stage_rows,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -209,8 +209,10 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
 int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
                       uint64_t* ticket);
 /* Wait until `ticket` completes (timeout_ns < 0: forever).  Returns the
- * frame's status, or HZD_E_TIMEOUT. */
-int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns);
+ * frame's status, or HZD_E_TIMEOUT.  latency_ns (nullable): nanoseconds from
+ * submit to the scheduler observing completion.  A ticket can be waited for
+ * once. */
+int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns, int64_t* latency_ns);
 /* Per-stream device state as of the last completed frame: A (3 floats) and
  * {K, vstar, cutoff}; host pointers, either may be NULL. */
 int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host);
@@ -223,6 +225,21 @@ typedef struct hzd_server_stats {
   int32_t open_streams, inflight;
 } hzd_server_stats;
 int hzd_server_stats_get(hzd_server* s, hzd_server_stats* out);
+
+/* ------------------------------------------------------------ profiling
+ * Per-stage timing with HIP events recorded on the stream each kernel is
+ * launched on.  While enabled (process-wide), every kernel launch of the
+ * pipeline is bracketed by a pair of events.  hzd_profile_read synchronises
+ * the recorded events, adds each launch's elapsed time to its stage entry
+ * and returns up to `cap` entries (stage name, launches, total ms);
+ * reset != 0 clears the totals afterwards. */
+typedef struct hzd_profile_entry {
+  char name[24];
+  uint64_t launches;
+  double total_ms;
+} hzd_profile_entry;
+int hzd_profile_enable(int32_t on);
+int hzd_profile_read(hzd_profile_entry* out, int32_t cap, int32_t* n, int32_t reset);
 
 const char* hzd_status_str(int32_t status);
 /* Thread-local text for the last failing call on this thread ("" if none). */

@@ -66,6 +66,10 @@ class hzd_server_stats(ctypes.Structure):
                 ("inflight", ctypes.c_int32)]
 
 
+class hzd_profile_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
 DONE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64)
 
 _lib = None
@@ -90,11 +94,15 @@ SYMBOLS = {
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "hzd_stream_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_frame), DONE_FN, ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_uint64)]),
-    "hzd_stream_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64]),
+    "hzd_stream_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64)]),
     "hzd_stream_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_int32)]),
     "hzd_stream_close": (ctypes.c_int, [ctypes.c_void_p]),
     "hzd_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_server_stats)]),
+    "hzd_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "hzd_profile_read": (ctypes.c_int, [ctypes.POINTER(hzd_profile_entry), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
 }
 
 
@@ -269,15 +277,6 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().hzd_server_create(ctypes.byref(cfg), ctypes.byref(h)), "hzd_server_create")
         self.handle = h
-        self._cb = DONE_FN(self._on_done)
-        self._lock = threading.Lock()
-        self.latency_ns = {}
-        self.status = {}
-
-    def _on_done(self, user, ticket, status, latency_ns):
-        with self._lock:
-            self.latency_ns[(user or 0, int(ticket))] = int(latency_ns)
-            self.status[(user or 0, int(ticket))] = int(status)
 
     def open(self, params: Params, width: int, height: int) -> "Stream":
         h = ctypes.c_void_p()
@@ -306,21 +305,20 @@ class Server:
 class Stream:
     def __init__(self, server: Server, handle, width, height):
         self.server, self.handle, self.width, self.height = server, handle, width, height
-        self.tag = id(self) & 0xFFFFFFFF
 
     def submit(self, src: torch.Tensor, dst: torch.Tensor) -> int:
+        """Queue one frame; no completion callback (completion and latency come from wait())."""
         f = _frame_struct(src, dst)
         t = ctypes.c_uint64(0)
-        rc = lib().hzd_stream_submit(self.handle, ctypes.byref(f), self.server._cb, self.tag, ctypes.byref(t))
+        rc = lib().hzd_stream_submit(self.handle, ctypes.byref(f), DONE_FN(), None, ctypes.byref(t))
         _check(rc, "hzd_stream_submit")
         return int(t.value)
 
-    def wait(self, ticket: int, timeout_ns: int = -1) -> int:
-        return lib().hzd_stream_wait(self.handle, ticket, timeout_ns)
-
-    def latency_ns(self, ticket: int):
-        with self.server._lock:
-            return self.server.latency_ns.get((self.tag, ticket))
+    def wait(self, ticket: int, timeout_ns: int = -1):
+        """(status, latency_ns) of a submitted frame; status HZD_E_TIMEOUT if not done in time."""
+        lat = ctypes.c_int64(0)
+        rc = lib().hzd_stream_wait(self.handle, ticket, timeout_ns, ctypes.byref(lat))
+        return int(rc), int(lat.value)
 
     def state(self):
         A = (ctypes.c_float * 3)()
@@ -332,3 +330,41 @@ class Stream:
         if self.handle:
             _check(lib().hzd_stream_close(self.handle), "hzd_stream_close")
             self.handle = None
+
+
+# ---------------------------------------------------------------- profiling
+def profile_enable(on: bool = True) -> None:
+    """hzd_profile_enable: bracket every kernel launch with HIP events on its stream."""
+    _check(lib().hzd_profile_enable(1 if on else 0), "hzd_profile_enable")
+
+
+def profile_read(reset: bool = True) -> dict:
+    """hzd_profile_read: {stage: (launches, total_ms)} for the launches recorded so far."""
+    cap = 32
+    arr = (hzd_profile_entry * cap)()
+    n = ctypes.c_int32(0)
+    _check(lib().hzd_profile_read(arr, cap, ctypes.byref(n), 1 if reset else 0), "hzd_profile_read")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+
+class FrameCall:
+    """A prepared hzd_dehaze_frame call: ctypes arguments built once, so a
+    timing loop measures the library and the GPU, not argument marshalling."""
+
+    def __init__(self, src, dst, params: Params, workspace, aux: dict | None = None, stream=None):
+        self._keep = (src, dst, workspace, aux)
+        self.f = _frame_struct(src, dst)
+        self.pc = params.c()
+        a = _aux_struct(aux)
+        self.aux = ctypes.pointer(a) if a is not None else None
+        self.ws = ctypes.c_void_p(workspace.data_ptr())
+        self.ws_bytes = ctypes.c_size_t(workspace.numel())
+        self.stream = ctypes.c_void_p(_stream_handle(stream))
+        self.fn = lib().hzd_dehaze_frame
+        self.fp = ctypes.byref(self.f)
+        self.pp = ctypes.byref(self.pc)
+
+    def __call__(self):
+        rc = self.fn(self.pp, self.fp, self.aux, self.ws, self.ws_bytes, self.stream)
+        if rc != HZD_OK:
+            _check(rc, "hzd_dehaze_frame")

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -111,7 +113,7 @@ size_t frame_ws_bytes(const hzd_params& p, int W, int H) {
   s += a256((size_t)H * 16);                           // rowinfo
   if (p.color_balance) {
     int nb = recon_blocks(W, H);
-    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius));
+    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius, kGfRowsMin));
     s += a256((size_t)nb * 16);                        // colour-balance partials
   }
   if (offline) {
@@ -149,7 +151,7 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   off += a256((size_t)H * 16);
   if (p.color_balance) {
     int nb = recon_blocks(W, H);
-    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius));
+    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius, kGfRowsMin));
     d.cbpart = reinterpret_cast<float4*>(ws + off);
     off += a256((size_t)nb * 16);
   }
@@ -188,6 +190,7 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     d.ab_scale = std::ldexp(1.0f, k);
     d.ab_inv_scale = std::ldexp(1.0f, -k);
   }
+  d.gf_rows = kGfRowsDefault;
   d.aligned = ((uintptr_t)fr.src % 4 == 0) && ((uintptr_t)fr.dst % 4 == 0) && (fr.src_pitch % 4 == 0) &&
               (fr.dst_pitch % 4 == 0);
   return d;
@@ -198,25 +201,71 @@ int check(hipError_t e, const char* what) {
   return fail(HZD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ------------------------------------------------------------ stage timing
+namespace {
+struct ProfRec {
+  const char* stage;
+  hipEvent_t a, b;
+};
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::map<std::string, std::pair<uint64_t, double>> g_prof_totals;
+
+hipEvent_t prof_event() {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_pool.empty()) {
+      hipEvent_t e = g_prof_pool.back();
+      g_prof_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch one stage; with profiling on, bracket it with events on its stream.
+template <typename F>
+int stage(const char* name, hipStream_t s, F&& launch) {
+  if (!g_prof_on.load(std::memory_order_relaxed)) return check(launch(), name);
+  hipEvent_t a = prof_event(), b = prof_event();
+  if (a) (void)hipEventRecord(a, s);
+  const int rc = check(launch(), name);
+  if (b) (void)hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (a && b) {
+    g_prof_pending.push_back({name, a, b});
+  } else {
+    if (a) g_prof_pool.push_back(a);
+    if (b) g_prof_pool.push_back(b);
+  }
+  return rc;
+}
+}  // namespace
+
 // The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames.
 int run_group(const GroupKey& g, const Batch& b, hipStream_t s) {
   int rc;
-  if ((rc = check(launch_init(b, s), "init")) != HZD_OK) return rc;
+  if ((rc = stage("init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
   const bool he = g.tx == HZD_TX_HE;
-  if ((rc = check(launch_dark(b, g, he, s), "dark")) != HZD_OK) return rc;
-  if ((rc = check(launch_select(b, s), "select")) != HZD_OK) return rc;
+  if ((rc = stage("dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
+  if ((rc = stage("select", s, [&] { return launch_select(b, s); })) != HZD_OK) return rc;
   if (g.mode == HZD_MODE_OFFLINE) {
-    if ((rc = check(launch_gf_prep(b, g, s), "gf_prep")) != HZD_OK) return rc;
-    if ((rc = check(launch_gf_ab(b, g, s), "gf_ab")) != HZD_OK) return rc;
-    if ((rc = check(launch_gf_q(b, g, s), "gf_q")) != HZD_OK) return rc;
-    if (g.cb && (rc = check(launch_recon(b, g, TSRC_TMAP, 2, s), "recon")) != HZD_OK) return rc;
+    if ((rc = stage("gf_prep", s, [&] { return launch_gf_prep(b, g, s); })) != HZD_OK) return rc;
+    if ((rc = stage("gf_ab", s, [&] { return launch_gf_ab(b, g, s); })) != HZD_OK) return rc;
+    if ((rc = stage("gf_q", s, [&] { return launch_gf_q(b, g, s); })) != HZD_OK) return rc;
+    if (g.cb && (rc = stage("recon_apply", s, [&] { return launch_recon(b, g, TSRC_TMAP, 2, s); })) != HZD_OK)
+      return rc;
   } else {
     const int tsrc = he ? TSRC_HE : TSRC_PAPER;
     if (g.cb) {
-      if ((rc = check(launch_recon(b, g, tsrc, 1, s), "recon-sums")) != HZD_OK) return rc;
-      if ((rc = check(launch_recon(b, g, tsrc, 2, s), "recon-apply")) != HZD_OK) return rc;
+      if ((rc = stage("recon_sums", s, [&] { return launch_recon(b, g, tsrc, 1, s); })) != HZD_OK) return rc;
+      if ((rc = stage("recon_apply", s, [&] { return launch_recon(b, g, tsrc, 2, s); })) != HZD_OK) return rc;
     } else {
-      if ((rc = check(launch_recon(b, g, tsrc, 0, s), "recon")) != HZD_OK) return rc;
+      if ((rc = stage("recon", s, [&] { return launch_recon(b, g, tsrc, 0, s); })) != HZD_OK) return rc;
     }
   }
   return HZD_OK;
@@ -337,6 +386,43 @@ int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_
   *bytes = need;
   clear_error();
   return HZD_OK;
+}
+
+int hzd_profile_enable(int32_t on) {
+  g_prof_on.store(on ? 1 : 0);
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_profile_read(hzd_profile_entry* out, int32_t cap, int32_t* n, int32_t reset) {
+  if (cap < 0 || (cap > 0 && !out)) return fail(HZD_E_INVAL, "bad output array");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int rc = HZD_OK;
+  for (const ProfRec& r : g_prof_pending) {
+    float ms = 0.f;
+    if (rc == HZD_OK) rc = check(hipEventSynchronize(r.b), "profile sync");
+    if (rc == HZD_OK) rc = check(hipEventElapsedTime(&ms, r.a, r.b), "profile elapsed");
+    auto& t = g_prof_totals[r.stage];
+    t.first += 1;
+    t.second += ms;
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_pending.clear();
+  int k = 0;
+  for (auto& kv : g_prof_totals) {
+    if (k < cap) {
+      std::memset(out[k].name, 0, sizeof(out[k].name));
+      std::strncpy(out[k].name, kv.first.c_str(), sizeof(out[k].name) - 1);
+      out[k].launches = kv.second.first;
+      out[k].total_ms = kv.second.second;
+    }
+    ++k;
+  }
+  if (n) *n = std::min(k, cap);
+  if (reset) g_prof_totals.clear();
+  if (rc == HZD_OK) clear_error();
+  return rc;
 }
 
 int hzd_dehaze_frame(const hzd_params* params, const hzd_frame* frame, const hzd_frame_aux* aux,

@@ -57,6 +57,7 @@ struct FrameDev {
   float ab_scale, ab_inv_scale;                      // fixed-point scale of a, b
   int32_t gamma_is_one;
   int32_t aligned;   // src, dst and both pitches are multiples of 4
+  int32_t gf_rows;   // output rows per guided-filter block
 };
 
 struct Batch {
@@ -85,11 +86,12 @@ hipError_t launch_recon(Batch b, const GroupKey& g, int tsrc, int phase, hipStre
 constexpr int kDarkTW = 64, kDarkTH = 32;
 constexpr int kReconPx = 1024;   // pixels of one row per recon block
 constexpr int kGfCols = 256;     // loaded columns per guided-filter strip block
-constexpr int kGfRows = 32;      // output rows per guided-filter block
+constexpr int kGfRowsDefault = 32;  // output rows per guided-filter block unless tuned
+constexpr int kGfRowsMin = 8;
 inline int recon_blocks(int W, int H) { return H * ((W + kReconPx - 1) / kReconPx); }
 inline int gf_strip(int r) { return kGfCols - 2 * r; }
-inline int gf_blocks(int W, int H, int r) {
-  return ((W + gf_strip(r) - 1) / gf_strip(r)) * ((H + kGfRows - 1) / kGfRows);
+inline int gf_blocks(int W, int H, int r, int rows) {
+  return ((W + gf_strip(r) - 1) / gf_strip(r)) * ((H + rows - 1) / rows);
 }
 
 enum { TSRC_HE = 0, TSRC_PAPER = 1, TSRC_TMAP = 2 };

@@ -160,11 +160,15 @@ template <int HP, bool WRITE_E>
 __global__ __launch_bounds__(256) void k_dark(Batch b) {
   constexpr int TW = kDarkTW, TH = kDarkTH;
   constexpr int RW = TW + 2 * HP, RH = TH + 2 * HP, WIN = 2 * HP + 1;
+  constexpr int SROW = (3 * RW + 3) / 4 + 2;   // dwords of one staged region row (+ slack)
   __shared__ uint32_t s_rb[RH][RW];
   __shared__ uint32_t s_g[RH][RW];
-  __shared__ uint32_t s_vrb[TH][RW];
-  __shared__ uint32_t s_vg[TH][RW];
+  __shared__ uint32_t s_v[2][TH][RW];           // vertical-pass output; first used as the byte stage
   __shared__ uint32_t s_hist[256];
+  static_assert(RH * SROW <= 2 * TH * RW, "byte stage does not fit");
+  uint32_t(&s_vrb)[TH][RW] = s_v[0];
+  uint32_t(&s_vg)[TH][RW] = s_v[1];
+  uint32_t* s_stage = &s_v[0][0][0];
 
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
@@ -174,19 +178,49 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   const int tiles_x = (W + TW - 1) / TW;
   const int x0 = (tile % tiles_x) * TW, y0 = (tile / tiles_x) * TH;
   const int tid = threadIdx.x;
+  const int xs = max(x0 - HP, 0), xe = min(x0 + TW + HP, W);
 
+  // stage each in-frame region row's bytes [3 xs, 3 xe) with aligned dword
+  // loads (a dword holding at least one byte of the row never crosses a page)
   s_hist[tid] = 0u;
-  for (int i = tid; i < RH * RW; i += 256) {
-    const int rr = i / RW, cc = i - rr * RW;
-    const int y = y0 - HP + rr, x = x0 - HP + cc;
-    uint32_t rb = 0x00FF00FFu, g = 0x00FF00FFu;
-    if (y >= 0 && y < H && x >= 0 && x < W) {
-      const uint8_t* p = fd.src + (int64_t)y * fd.src_pitch + 3 * x;
-      rb = (uint32_t)p[0] | ((uint32_t)p[2] << 16);
-      g = (uint32_t)p[1] | 0x00FF0000u;
+  for (int i = tid; i < RH * SROW; i += 256) {
+    const int rr = i / SROW, j = i - rr * SROW;
+    const int y = y0 - HP + rr;
+    if (y < 0 || y >= H) continue;
+    const uintptr_t addr = (uintptr_t)(fd.src + (int64_t)y * fd.src_pitch + 3 * xs);
+    const uintptr_t a0 = addr & ~(uintptr_t)3;
+    const int nd = (int)((addr + 3 * (xe - xs) - a0 + 3) >> 2);
+    if (j < nd) s_stage[rr * SROW + j] = *reinterpret_cast<const uint32_t*>(a0 + 4 * (uintptr_t)j);
+  }
+  __syncthreads();
+  // unpack into two planes of 16-bit pairs; out-of-frame cells hold 255
+  uint32_t rbv[(RH * RW + 255) / 256], gv[(RH * RW + 255) / 256];
+#pragma unroll
+  for (int k = 0; k < (RH * RW + 255) / 256; ++k) {
+    const int i = tid + 256 * k;
+    rbv[k] = 0x00FF00FFu;
+    gv[k] = 0x00FF00FFu;
+    if (i < RH * RW) {
+      const int rr = i / RW, cc = i - rr * RW;
+      const int y = y0 - HP + rr, x = x0 - HP + cc;
+      if (y >= 0 && y < H && x >= xs && x < xe) {
+        const uintptr_t addr = (uintptr_t)(fd.src + (int64_t)y * fd.src_pitch + 3 * xs);
+        const int off = (int)(addr & 3) + 3 * (x - xs);
+        const uint32_t w0 = s_stage[rr * SROW + (off >> 2)], w1 = s_stage[rr * SROW + (off >> 2) + 1];
+        const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(off & 3));
+        rbv[k] = (v & 0xFFu) | ((v & 0x00FF0000u));
+        gv[k] = ((v >> 8) & 0xFFu) | 0x00FF0000u;
+      }
     }
-    s_rb[rr][cc] = rb;
-    s_g[rr][cc] = g;
+  }
+#pragma unroll
+  for (int k = 0; k < (RH * RW + 255) / 256; ++k) {
+    const int i = tid + 256 * k;
+    if (i < RH * RW) {
+      const int rr = i / RW, cc = i - rr * RW;
+      s_rb[rr][cc] = rbv[k];
+      s_g[rr][cc] = gv[k];
+    }
   }
   __syncthreads();
 
@@ -321,21 +355,27 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
   const uint32_t vstar = (uint32_t)s_misc[0];
   const uint32_t cnt_gt = (uint32_t)s_misc[1];
 
-  // one row per wave
+  // one row per wave; each lane reads 16 consecutive bytes of D per step
   const int y = tile * 4 + wv;
   if (y < H) {
     unsigned long long gR = 0, gG = 0, gB = 0, gN = 0;
     uint32_t tN = 0, tR = 0, tG = 0, tB = 0;
     const uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch;
     const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
-    for (int x = lane; x < W; x += 64) {
-      const uint32_t d = Drow[x];
-      if (d >= vstar) {
-        const uint32_t r = Irow[3 * x], g = Irow[3 * x + 1], bl = Irow[3 * x + 2];
-        if (d > vstar) {
-          gR += r; gG += g; gB += bl; gN += 1;
-        } else {
-          tR += r; tG += g; tB += bl; tN += 1;
+    for (int base = 16 * lane; base < W; base += 1024) {
+      const uint4 dv = *reinterpret_cast<const uint4*>(Drow + base);  // rows are padded to 16 bytes
+      const uint32_t dw[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int x = base + k;
+        const uint32_t d = (dw[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+        if (x < W && d >= vstar) {
+          const uint32_t r = Irow[3 * x], g = Irow[3 * x + 1], bl = Irow[3 * x + 2];
+          if (d > vstar) {
+            gR += r; gG += g; gB += bl; gN += 1;
+          } else {
+            tR += r; tG += g; tB += bl; tN += 1;
+          }
         }
       }
     }
@@ -408,7 +448,10 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
   sG = block_sum(sG, s_u64);
   sB = block_sum(sB, s_u64);
 
-  // the cut row: the first (need - before) ties in raster order
+  // the cut row: the first (need - before) ties in raster order.  Lane l
+  // owns bytes [16 l, 16 l + 16) of each 1024-pixel segment, so lane order is
+  // raster order inside a segment; an exclusive scan of the per-lane tie
+  // counts tells each lane how many of its ties are taken.
   if (wv == 0) {
     const uint32_t k = need - before;
     const uint8_t* Drow = fd.D + (int64_t)rstar * fd.D_pitch;
@@ -416,19 +459,33 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
     uint32_t run = 0;
     unsigned long long cR = 0, cG = 0, cB = 0;
     int cut_x = -1;
-    for (int base = 0; base < W; base += 64) {
-      const int x = base + lane;
-      const bool tie = (x < W) && (Drow[x] == vstar);
-      const unsigned long long m = __ballot(tie);
-      const uint32_t cnt = (uint32_t)__popcll(m);
-      const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      const uint32_t take = min(cnt, k - run);   // ties taken from this chunk
-      if (tie && rank < take) {
-        cR += Irow[3 * x]; cG += Irow[3 * x + 1]; cB += Irow[3 * x + 2];
-        if (rank == take - 1 && run + take == k) cut_x = x;
+    for (int base = 0; base < W && run < k; base += 1024) {
+      const int x0 = base + 16 * lane;
+      uint32_t dw[4] = {0u, 0u, 0u, 0u};
+      if (x0 < W) {
+        const uint4 dv = *reinterpret_cast<const uint4*>(Drow + x0);
+        dw[0] = dv.x; dw[1] = dv.y; dw[2] = dv.z; dw[3] = dv.w;
       }
-      run += take;
-      if (run == k) break;
+      uint32_t mask = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t d = (dw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        if (x0 + j < W && d == vstar) mask |= 1u << j;
+      }
+      const uint32_t cnt = (uint32_t)__popc(mask);
+      const uint32_t ex = wave_incl_scan(cnt) - cnt;   // ties before this lane in the segment
+      const uint32_t seg_total = __shfl(ex + cnt, 63, 64);
+      // ties this lane takes: those with (run + ex + rank) < k
+      const uint32_t avail = (run + ex < k) ? min(cnt, k - run - ex) : 0u;
+      uint32_t m = mask;
+      for (uint32_t i = 0; i < avail; ++i) {
+        const int j = __ffs(m) - 1;
+        m &= m - 1;
+        const int x = x0 + j;
+        cR += Irow[3 * x]; cG += Irow[3 * x + 1]; cB += Irow[3 * x + 2];
+        if (run + ex + i + 1 == k) cut_x = x;
+      }
+      run += seg_total;
     }
     cR = wave_sum(cR); cG = wave_sum(cG); cB = wave_sum(cB);
     int cx = cut_x;
@@ -539,176 +596,280 @@ __global__ __launch_bounds__(256) void k_gf_prep(Batch b) {
 }
 
 // ------------------------------------------------------------------ k_gf_ab
-// Eq. (6), stage 1 (He et al. 2013 box form).  A block owns a strip of 256
-// loaded columns (one per thread) and produces 256 - 2r output columns for
-// kGfRows rows.  Each thread keeps exact u64 vertical window sums of L, L^2,
-// P, L*P for its column, sliding down the rows; per row the four column sums
-// are prefix-summed across the strip in LDS (one wave per quantity) and each
-// output's clipped (2r+1)^2 box sum is a difference of two prefixes.  Integer
-// sums are exact, so the result does not depend on the tiling.  The means,
-// var and cov are formed in FP64; a and b leave as int32 fixed point.
+// FP64 reciprocal: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Geometry of one guided-filter strip block: 256 loaded columns (one per
+// thread) starting at x0 - r, output columns [x0, x0 + 256 - 2r), output rows
+// [y0, y1) with y1 - y0 = fd.gf_rows (the tile height is a tuning knob; the
+// integer sums make results independent of it).
+struct GfTile {
+  int W, H, r, SW, x0, y0, y1, xl;
+  bool colin;
+};
+
+__device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
+  GfTile t;
+  t.W = fd.W;
+  t.H = fd.H;
+  t.r = fd.radius;
+  t.SW = kGfCols - 2 * t.r;
+  const int strips = (t.W + t.SW - 1) / t.SW;
+  const int sx = tile % strips, sy = tile / strips;
+  t.x0 = sx * t.SW;
+  t.y0 = sy * fd.gf_rows;
+  t.y1 = min(t.H, t.y0 + fd.gf_rows);
+  t.xl = t.x0 - t.r + (int)threadIdx.x;
+  t.colin = t.xl >= 0 && t.xl < t.W;
+  return t;
+}
+
+// Prefix sums over the 256 columns of one LDS row, 4 columns per lane (one
+// wave per row of the array).
+template <typename T>
+__device__ __forceinline__ void wave_prefix256(T* row) {
+  const int lane = threadIdx.x & 63;
+  T v0 = row[4 * lane], v1 = row[4 * lane + 1], v2 = row[4 * lane + 2], v3 = row[4 * lane + 3];
+  v1 += v0;
+  v2 += v1;
+  v3 += v2;
+  const T ex = wave_incl_scan(v3) - v3;
+  row[4 * lane] = v0 + ex;
+  row[4 * lane + 1] = v1 + ex;
+  row[4 * lane + 2] = v2 + ex;
+  row[4 * lane + 3] = v3 + ex;
+}
+
+// Eq. (6), stage 1 (He et al. 2013 box form).  Each thread keeps exact u64
+// vertical window sums of L, L^2, P, L*P for its column, sliding down the
+// rows; per row the four column sums are prefix-summed across the strip in
+// LDS (one wave per quantity) and each output's clipped (2r+1)^2 box sum is a
+// difference of two prefixes.  The next row's operands are loaded one
+// iteration ahead, and the LDS rows are double-buffered (two barriers per
+// row).  Means, var and cov are formed in FP64; a and b leave as int32 fixed
+// point with the frame's scale.
 __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
-  __shared__ unsigned long long s_q[4][kGfCols];
+  __shared__ unsigned long long s_q[2][4][kGfCols];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
-  const int tile = blk - b.tile0[f];
-  const int W = fd.W, H = fd.H, r = fd.radius;
-  const int SW = kGfCols - 2 * r;
-  const int strips = (W + SW - 1) / SW;
-  const int sx = tile % strips, sy = tile / strips;
-  const int x0 = sx * SW, y0 = sy * kGfRows, y1 = min(H, y0 + kGfRows);
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int xl = x0 - r + tid;
-  const bool colin = (xl >= 0 && xl < W);
-  const uint2* LP = fd.LP;
+  const GfTile g = gf_tile(fd, blk - b.tile0[f]);
+  const int W = g.W, H = g.H, r = g.r;
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const uint2* col = fd.LP + (g.colin ? g.xl : 0);
 
   unsigned long long sL = 0, sLL = 0, sP = 0, sLP = 0;
-  if (colin) {
-    for (int yy = max(0, y0 - r); yy <= min(H - 1, y0 + r); ++yy) {
-      const uint2 v = LP[(int64_t)yy * W + xl];
-      const unsigned long long L = v.x, P = v.y;
-      sL += L; sLL += L * L; sP += P; sLP += L * P;
-    }
-  }
-  const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
-  const double eps = (double)fd.eps;
-  for (int y = y0; y < y1; ++y) {
-    if (y > y0 && colin) {
-      if (y + r < H) {
-        const uint2 v = LP[(int64_t)(y + r) * W + xl];
-        const unsigned long long L = v.x, P = v.y;
-        sL += L; sLL += L * L; sP += P; sLP += L * P;
-      }
-      if (y - r - 1 >= 0) {
-        const uint2 v = LP[(int64_t)(y - r - 1) * W + xl];
-        const unsigned long long L = v.x, P = v.y;
-        sL -= L; sLL -= L * L; sP -= P; sLP -= L * P;
-      }
-    }
-    s_q[0][tid] = colin ? sL : 0ull;
-    s_q[1][tid] = colin ? sLL : 0ull;
-    s_q[2][tid] = colin ? sP : 0ull;
-    s_q[3][tid] = colin ? sLP : 0ull;
-    __syncthreads();
-    {  // wave wv prefix-sums quantity wv over the 256 columns (4 per lane)
-      unsigned long long v0 = s_q[wv][4 * lane], v1 = s_q[wv][4 * lane + 1],
-                         v2 = s_q[wv][4 * lane + 2], v3 = s_q[wv][4 * lane + 3];
-      v1 += v0; v2 += v1; v3 += v2;
-      const unsigned long long ex = wave_incl_scan(v3) - v3;
-      s_q[wv][4 * lane] = v0 + ex;
-      s_q[wv][4 * lane + 1] = v1 + ex;
-      s_q[wv][4 * lane + 2] = v2 + ex;
-      s_q[wv][4 * lane + 3] = v3 + ex;
-    }
-    __syncthreads();
-    const int x = x0 + tid;
-    if (tid < SW && x < W) {
-      const int lo = max(x - r, 0), hi = min(x + r, W - 1);
-      const int clo = lo - (x0 - r), chi = hi - (x0 - r);
-      unsigned long long q[4];
+  auto add = [&](uint2 v) {
+    const unsigned long long L = v.x, P = v.y;
+    sL += L; sLL += L * L; sP += P; sLP += L * P;
+  };
+  auto sub = [&](uint2 v) {
+    const unsigned long long L = v.x, P = v.y;
+    sL -= L; sLL -= L * L; sP -= P; sLP -= L * P;
+  };
+  if (g.colin) {
+    const int ya = max(0, g.y0 - r), yb = min(H - 1, g.y0 + r);
+    int yy = ya;
+    for (; yy + 8 <= yb + 1; yy += 8) {
+      uint2 v[8];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) q[k] = s_q[k][chi] - (clo > 0 ? s_q[k][clo - 1] : 0ull);
-      const int n = (hi - lo + 1) * (min(y + r, H - 1) - max(y - r, 0) + 1);
-      const double in = 1.0 / (double)n;
-      const double mG = (double)q[0] * in * kG;
-      const double mGG = (double)q[1] * in * (kG * kG);
-      const double mP = (double)q[2] * in * kP;
-      const double mGP = (double)q[3] * in * (kG * kP);
+      for (int k = 0; k < 8; ++k) v[k] = col[(int64_t)(yy + k) * W];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) add(v[k]);
+    }
+    for (; yy <= yb; ++yy) add(col[(int64_t)yy * W]);
+  }
+  auto fetch = [&](int yn, uint2& vin, uint2& vout) {
+    vin = make_uint2(0u, 0u);
+    vout = make_uint2(0u, 0u);
+    if (g.colin && yn < g.y1) {
+      if (yn + r < H) vin = col[(int64_t)(yn + r) * W];
+      if (yn - r - 1 >= 0) vout = col[(int64_t)(yn - r - 1) * W];
+    }
+  };
+  uint2 pin, pout;
+  fetch(g.y0 + 1, pin, pout);
+
+  const int x = g.x0 + tid;
+  const bool outcol = tid < g.SW && x < W;
+  const int lo = max(x - r, 0), hi = min(x + r, W - 1);
+  const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
+  const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
+  const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
+  const double eps = (double)fd.eps, s = (double)fd.ab_scale, lim = 2147483647.0;
+  int buf = 0;
+  for (int y = g.y0; y < g.y1; ++y) {
+    if (y > g.y0) {
+      add(pin);
+      sub(pout);
+    }
+    fetch(y + 1, pin, pout);
+    s_q[buf][0][tid] = sL;
+    s_q[buf][1][tid] = sLL;
+    s_q[buf][2][tid] = sP;
+    s_q[buf][3][tid] = sLP;
+    __syncthreads();
+    wave_prefix256(s_q[buf][wv]);
+    __syncthreads();
+    if (outcol) {
+      double q[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        q[k] = (double)(s_q[buf][k][chi] - (clo > 0 ? s_q[buf][k][clo - 1] : 0ull));
+      const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
+      const double in = icw * rcp_nr((double)ch);
+      const double mG = q[0] * (in * kG);
+      const double mGG = q[1] * (in * (kG * kG));
+      const double mP = q[2] * (in * kP);
+      const double mGP = q[3] * (in * (kG * kP));
       const double var = mGG - mG * mG;
       const double cov = mGP - mG * mP;
-      const double a = cov / (var + eps);
+      const double a = cov * rcp_nr(var + eps);
       const double bb = mP - a * mG;
-      const double s = (double)fd.ab_scale;
-      const double lim = 2147483647.0;
       const double ia = fmin(fmax(__builtin_rint(a * s), -lim), lim);
       const double ib = fmin(fmax(__builtin_rint(bb * s), -lim), lim);
       fd.AB[(int64_t)y * W + x] = make_int2((int)ia, (int)ib);
     }
-    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// Deterministic colour-balance partials: each block writes the sum of J_gamma
+// over its pixels; the last block of the frame (atomic ticket) adds the
+// partials in FP64 in block order and forms the gray-world gains.
+__device__ __forceinline__ void cb_finish(const FrameDev& fd, int tile, int nblk, const float acc[3],
+                                          float* s_red, double* s_d, int* s_last) {
+  const int tid = threadIdx.x;
+  const float s0 = block_sum(acc[0], s_red), s1 = block_sum(acc[1], s_red), s2 = block_sum(acc[2], s_red);
+  if (tid == 0) fd.cbpart[tile] = make_float4(s0, s1, s2, 0.f);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) *s_last = (atomicAdd(&fd.st->ticket_cb, 1u) == (uint32_t)(nblk - 1));
+  __syncthreads();
+  if (!*s_last) return;
+  __threadfence();
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int i = tid; i < nblk; i += 256) {
+    const float4 pp = fd.cbpart[i];
+    m[0] += pp.x; m[1] += pp.y; m[2] += pp.z;
+  }
+  for (int c = 0; c < 3; ++c) m[c] = block_sum(m[c], s_d);
+  if (tid == 0) {
+    const double n = (double)fd.W * (double)fd.H;
+    const double mu[3] = {m[0] / n, m[1] / n, m[2] / n};
+    const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
+    for (int c = 0; c < 3; ++c) fd.st->gains[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
   }
 }
 
 // ------------------------------------------------------------------- k_gf_q
 // Eq. (6), stage 2: box means of a and b (exact i64 sums of the fixed-point
-// values, same strip scheme), q = mean(a) G + mean(b), clamped to [t0, 1].
-// PHASE 0: fuse Eqs. (7)-(8) and write the output.  PHASE 1: store the
-// refined t and the colour-balance partial sums of J_gamma.
+// values, same strip scheme and prefetching), q = mean(a) G + mean(b),
+// clamped to [t0, 1].  PHASE 0: fuse Eqs. (7)-(8) and write the output.
+// PHASE 1: store the refined t and the colour-balance partial sums.
 template <int PHASE, bool FP16>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
-  __shared__ long long s_q[2][kGfCols];
+  __shared__ long long s_q[2][2][kGfCols];
   __shared__ float s_red[4];
+  __shared__ double s_d[4];
+  __shared__ int s_last;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
   const int tile = blk - b.tile0[f];
-  const int W = fd.W, H = fd.H, r = fd.radius;
-  const int SW = kGfCols - 2 * r;
-  const int strips = (W + SW - 1) / SW;
-  const int sx = tile % strips, sy = tile / strips;
-  const int x0 = sx * SW, y0 = sy * kGfRows, y1 = min(H, y0 + kGfRows);
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int xl = x0 - r + tid;
-  const bool colin = (xl >= 0 && xl < W);
-  const int2* AB = fd.AB;
+  const GfTile g = gf_tile(fd, tile);
+  const int W = g.W, H = g.H, r = g.r;
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const int2* col = fd.AB + (g.colin ? g.xl : 0);
   const ReconConsts rc = recon_consts(fd);
 
   long long sa = 0, sb = 0;
-  if (colin) {
-    for (int yy = max(0, y0 - r); yy <= min(H - 1, y0 + r); ++yy) {
-      const int2 v = AB[(int64_t)yy * W + xl];
-      sa += v.x; sb += v.y;
+  if (g.colin) {
+    const int ya = max(0, g.y0 - r), yb = min(H - 1, g.y0 + r);
+    int yy = ya;
+    for (; yy + 8 <= yb + 1; yy += 8) {
+      int2 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = col[(int64_t)(yy + k) * W];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        sa += v[k].x;
+        sb += v[k].y;
+      }
+    }
+    for (; yy <= yb; ++yy) {
+      const int2 v = col[(int64_t)yy * W];
+      sa += v.x;
+      sb += v.y;
     }
   }
-  float acc[3] = {0.f, 0.f, 0.f};
+  auto fetch = [&](int yn, int2& vin, int2& vout) {
+    vin = make_int2(0, 0);
+    vout = make_int2(0, 0);
+    if (g.colin && yn < g.y1) {
+      if (yn + r < H) vin = col[(int64_t)(yn + r) * W];
+      if (yn - r - 1 >= 0) vout = col[(int64_t)(yn - r - 1) * W];
+    }
+  };
+  const int x = g.x0 + tid;
+  const bool outcol = tid < g.SW && x < W;
+  // the output pixel's guide value and colour, one row ahead
+  auto fetch_px = [&](int yn, uint32_t& L, uint32_t& rgb) {
+    L = 0u;
+    rgb = 0u;
+    if (outcol && yn < g.y1) {
+      L = fd.LP[(int64_t)yn * W + x].x;
+      const uint8_t* p = fd.src + (int64_t)yn * fd.src_pitch + 3 * x;
+      rgb = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+    }
+  };
+  int2 pin, pout;
+  fetch(g.y0 + 1, pin, pout);
+  uint32_t curL, curRGB;
+  fetch_px(g.y0, curL, curRGB);
+
+  const int lo = max(x - r, 0), hi = min(x + r, W - 1);
+  const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
+  const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
   const double inv_s = (double)fd.ab_inv_scale;
   const double t0 = (double)fd.t0;
-  for (int y = y0; y < y1; ++y) {
-    if (y > y0 && colin) {
-      if (y + r < H) {
-        const int2 v = AB[(int64_t)(y + r) * W + xl];
-        sa += v.x; sb += v.y;
-      }
-      if (y - r - 1 >= 0) {
-        const int2 v = AB[(int64_t)(y - r - 1) * W + xl];
-        sa -= v.x; sb -= v.y;
-      }
+  float acc[3] = {0.f, 0.f, 0.f};
+  int buf = 0;
+  for (int y = g.y0; y < g.y1; ++y) {
+    if (y > g.y0) {
+      sa += pin.x - pout.x;
+      sb += pin.y - pout.y;
     }
-    s_q[0][tid] = colin ? sa : 0ll;
-    s_q[1][tid] = colin ? sb : 0ll;
+    fetch(y + 1, pin, pout);
+    uint32_t nL, nRGB;
+    fetch_px(y + 1, nL, nRGB);
+    s_q[buf][0][tid] = sa;
+    s_q[buf][1][tid] = sb;
     __syncthreads();
-    if (wv < 2) {
-      long long v0 = s_q[wv][4 * lane], v1 = s_q[wv][4 * lane + 1], v2 = s_q[wv][4 * lane + 2],
-                v3 = s_q[wv][4 * lane + 3];
-      v1 += v0; v2 += v1; v3 += v2;
-      const long long ex = wave_incl_scan(v3) - v3;
-      s_q[wv][4 * lane] = v0 + ex;
-      s_q[wv][4 * lane + 1] = v1 + ex;
-      s_q[wv][4 * lane + 2] = v2 + ex;
-      s_q[wv][4 * lane + 3] = v3 + ex;
-    }
+    if (wv < 2) wave_prefix256(s_q[buf][wv]);
     __syncthreads();
-    const int x = x0 + tid;
-    if (tid < SW && x < W) {
-      const int lo = max(x - r, 0), hi = min(x + r, W - 1);
-      const int clo = lo - (x0 - r), chi = hi - (x0 - r);
-      const long long qa = s_q[0][chi] - (clo > 0 ? s_q[0][clo - 1] : 0ll);
-      const long long qb = s_q[1][chi] - (clo > 0 ? s_q[1][clo - 1] : 0ll);
-      const int n = (hi - lo + 1) * (min(y + r, H - 1) - max(y - r, 0) + 1);
-      const double in = inv_s / (double)n;
-      const uint2 lp = fd.LP[(int64_t)y * W + x];
-      const double G = (double)lp.x * (1.0 / 255000.0);
-      const double q = (double)qa * in * G + (double)qb * in;
+    if (outcol) {
+      const long long qa = s_q[buf][0][chi] - (clo > 0 ? s_q[buf][0][clo - 1] : 0ll);
+      const long long qb = s_q[buf][1][chi] - (clo > 0 ? s_q[buf][1][clo - 1] : 0ll);
+      const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
+      const double in = inv_s * icw * rcp_nr((double)ch);
+      const double G = (double)curL * (1.0 / 255000.0);
+      const double q = fma((double)qa * in, G, (double)qb * in);
       float t = (float)fmin(fmax(q, t0), 1.0);
       if (FP16) t = round_half(t);
-      if (fd.t_out) fd.t_out[(int64_t)y * W + x] = t;
-      const uint8_t* p = fd.src + (int64_t)y * fd.src_pitch + 3 * x;
-      float I[3], J[3], Jg[3];
-      load_rgb(p, I[0], I[1], I[2]);
+      const int64_t pi = (int64_t)y * W + x;
+      if (fd.t_out) fd.t_out[pi] = t;
+      float I[3] = {(float)(curRGB & 0xFFu), (float)((curRGB >> 8) & 0xFFu), (float)((curRGB >> 16) & 0xFFu)};
+      float J[3], Jg[3];
       recon_pixel(rc, I, t, J, Jg);
       if (fd.J_out) {
-        float* jo = fd.J_out + ((int64_t)y * W + x) * 3;
-        jo[0] = J[0]; jo[1] = J[1]; jo[2] = J[2];
+        fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
       }
       if (PHASE == 0) {
         uint8_t* o = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x;
@@ -716,39 +877,16 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         o[1] = (uint8_t)rne_u8(Jg[1]);
         o[2] = (uint8_t)rne_u8(Jg[2]);
       } else {
-        if (FP16) reinterpret_cast<__half*>(fd.tmap)[(int64_t)y * W + x] = __float2half_rn(t);
-        else reinterpret_cast<float*>(fd.tmap)[(int64_t)y * W + x] = t;
+        if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
+        else reinterpret_cast<float*>(fd.tmap)[pi] = t;
         acc[0] += Jg[0]; acc[1] += Jg[1]; acc[2] += Jg[2];
       }
     }
-    __syncthreads();
+    curL = nL;
+    curRGB = nRGB;
+    buf ^= 1;
   }
-  if (PHASE == 1) {
-    // deterministic per-block partials, then the last block forms the gains
-    float s0 = block_sum(acc[0], s_red), s1 = block_sum(acc[1], s_red), s2 = block_sum(acc[2], s_red);
-    if (tid == 0) fd.cbpart[tile] = make_float4(s0, s1, s2, 0.f);
-    __threadfence();
-    __syncthreads();
-    __shared__ int s_last;
-    const int nblk = b.tile0[f + 1] - b.tile0[f];
-    if (tid == 0) s_last = (atomicAdd(&fd.st->ticket_cb, 1u) == (uint32_t)(nblk - 1));
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    __shared__ double s_d[4];
-    double m[3] = {0.0, 0.0, 0.0};
-    for (int i = tid; i < nblk; i += 256) {
-      const float4 pp = fd.cbpart[i];
-      m[0] += pp.x; m[1] += pp.y; m[2] += pp.z;
-    }
-    for (int c = 0; c < 3; ++c) m[c] = block_sum(m[c], s_d);
-    if (tid == 0) {
-      const double n = (double)W * (double)H;
-      const double mu[3] = {m[0] / n, m[1] / n, m[2] / n};
-      const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
-      for (int c = 0; c < 3; ++c) fd.st->gains[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
-    }
-  }
+  if (PHASE == 1) cb_finish(fd, tile, b.tile0[f + 1] - b.tile0[f], acc, s_red, s_d, &s_last);
 }
 
 // ------------------------------------------------------------------ k_recon
@@ -759,6 +897,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 template <int TSRC, int PHASE, bool FP16>
 __global__ __launch_bounds__(256) void k_recon(Batch b) {
   __shared__ float s_red[4];
+  __shared__ double s_d[4];
+  __shared__ int s_last;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -858,31 +998,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       }
     }
   }
-  if (PHASE == 1) {
-    float s0 = block_sum(acc[0], s_red), s1 = block_sum(acc[1], s_red), s2 = block_sum(acc[2], s_red);
-    if (tid == 0) fd.cbpart[tile] = make_float4(s0, s1, s2, 0.f);
-    __threadfence();
-    __syncthreads();
-    __shared__ int s_last;
-    const int nblk = b.tile0[f + 1] - b.tile0[f];
-    if (tid == 0) s_last = (atomicAdd(&fd.st->ticket_cb, 1u) == (uint32_t)(nblk - 1));
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    __shared__ double s_d[4];
-    double m[3] = {0.0, 0.0, 0.0};
-    for (int i = tid; i < nblk; i += 256) {
-      const float4 pp = fd.cbpart[i];
-      m[0] += pp.x; m[1] += pp.y; m[2] += pp.z;
-    }
-    for (int c = 0; c < 3; ++c) m[c] = block_sum(m[c], s_d);
-    if (tid == 0) {
-      const double n = (double)W * (double)fd.H;
-      const double mu[3] = {m[0] / n, m[1] / n, m[2] / n};
-      const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
-      for (int c = 0; c < 3; ++c) fd.st->gains[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
-    }
-  }
+  if (PHASE == 1) cb_finish(fd, tile, b.tile0[f + 1] - b.tile0[f], acc, s_red, s_d, &s_last);
 }
 
 // ----------------------------------------------------------------- launches
@@ -953,13 +1069,13 @@ hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s) {
 
 hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s) {
   (void)g;
-  const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius); });
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
   hipLaunchKernelGGL(k_gf_ab, dim3(nblk), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s) {
-  const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius); });
+  const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
   if (g.cb) {
     if (g.fp16) hipLaunchKernelGGL((k_gf_q<1, true>), dim3(nblk), dim3(256), 0, s, b);
     else hipLaunchKernelGGL((k_gf_q<1, false>), dim3(nblk), dim3(256), 0, s, b);

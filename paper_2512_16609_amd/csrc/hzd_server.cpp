@@ -100,7 +100,7 @@ struct hzd_stream {
   uint64_t next_ticket = 1;
   int queued = 0, inflight = 0;
   bool closing = false;
-  std::map<uint64_t, int32_t> done;  // completed tickets not yet waited for
+  std::map<uint64_t, std::pair<int32_t, int64_t>> done;  // completed tickets not yet waited for: status, latency
   std::condition_variable cv;
 };
 
@@ -151,7 +151,7 @@ void finish(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
   std::lock_guard<std::mutex> lk(s->mu);
   for (auto& d : done) {
     hzd_stream* st = d.first.st;
-    st->done[d.first.ticket] = d.second;
+    st->done[d.first.ticket] = std::make_pair(d.second, t - d.first.t_submit);
     st->cv.notify_all();
   }
   done.clear();
@@ -405,7 +405,7 @@ int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, vo
   return HZD_OK;
 }
 
-int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns) {
+int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns, int64_t* latency_ns) {
   if (!st) return fail(HZD_E_INVAL, "stream is NULL");
   hzd_server* s = st->srv;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -417,9 +417,10 @@ int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns) {
   } else if (!st->cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready)) {
     return fail(HZD_E_TIMEOUT, "ticket %llu not complete", (unsigned long long)ticket);
   }
-  const int32_t status = st->done[ticket];
+  const auto res = st->done[ticket];
   st->done.erase(ticket);
-  return status;
+  if (latency_ns) *latency_ns = res.second;
+  return res.first;
 }
 
 int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host) {

@@ -1,0 +1,101 @@
+"""The continuous-batching server on the GPU: every served frame equals the
+same frame run alone through hzd_dehaze_frame, admission follows the arena
+budget, and closing/destroying drains or cancels correctly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_16609_amd as hzd
+from synth import make_frame
+
+from parity import oracle_params, run_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+RT = hzd.Params()
+OFF = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
+
+
+def _need(p, w, h):
+    return 2 * (hzd.workspace_size(p, [(h, w)]) + 256) + 512
+
+
+def test_served_equals_alone_in_a_mix():
+    specs = [(320, 240, RT), (640, 480, OFF), (160, 120, RT), (640, 480, RT), (320, 240, OFF),
+             (1280, 720, RT)]
+    arena = sum(_need(p, w, h) for w, h, p in specs) + (1 << 20)
+    srv = hzd.Server(arena_bytes=arena, max_inflight=8, frames_per_launch=4, hip_streams=3)
+    streams = [srv.open(p, w, h) for w, h, p in specs]
+    frames = {i: [make_frame(w, h, 100 + 10 * i + k).I for k in range(4)] for i, (w, h, _) in enumerate(specs)}
+    srcs = {i: [to_dev(I) for I in frames[i]] for i in frames}
+    dsts = {i: [torch.zeros_like(s) for s in srcs[i]] for i in frames}
+    tickets = []
+    for k in range(4):                       # interleave the streams so launches mix them
+        for i, st in enumerate(streams):
+            tickets.append((i, k, st.submit(srcs[i][k], dsts[i][k])))
+    for i, k, t in tickets:
+        rc, lat = streams[i].wait(t)
+        assert rc == 0 and lat > 0
+    stats = srv.stats()
+    assert stats["completed"] == len(tickets) and stats["failed"] == 0
+    for i, (w, h, p) in enumerate(specs):
+        for k in range(4):
+            alone = run_gpu(frames[i][k], p, with_J=False)["out"]
+            assert np.array_equal(dsts[i][k].cpu().numpy(), alone), (i, k)
+    # per-stream device state: A and the airlight selection of the last frame
+    A, sel = streams[0].state()
+    ref = oracle.dehaze(frames[0][3], oracle_params(RT))
+    assert sel[0] == ref.aux["K"] and sel[1] == int(ref.aux["vstar"])
+    assert np.allclose(A, ref.aux["A"].astype(np.float32))
+    for st in streams:
+        st.close()
+    srv.close()
+
+
+def test_admission_by_arena_budget():
+    need = _need(OFF, 640, 480)
+    srv = hzd.Server(arena_bytes=2 * need, max_inflight=4, frames_per_launch=2, hip_streams=2)
+    a = srv.open(OFF, 640, 480)
+    b = srv.open(OFF, 640, 480)
+    with pytest.raises(hzd.HzdError) as e:
+        srv.open(OFF, 640, 480)
+    assert e.value.status == hzd.HZD_E_AGAIN
+    a.close()
+    c = srv.open(OFF, 640, 480)          # the released space is reused
+    assert srv.stats()["open_streams"] == 2
+    b.close()
+    c.close()
+    srv.close()
+
+
+def test_close_waits_for_inflight_and_destroy_cancels_queued():
+    I = make_frame(640, 480, 7).I
+    src = to_dev(I)
+    srv = hzd.Server(arena_bytes=_need(OFF, 640, 480) + (1 << 20), max_inflight=1, frames_per_launch=1,
+                     hip_streams=1)
+    st = srv.open(OFF, 640, 480)
+    dsts = [torch.zeros_like(src) for _ in range(6)]
+    ts = [st.submit(src, d) for d in dsts]
+    st.close()                           # drains all six
+    alone = run_gpu(I, OFF, with_J=False)["out"]
+    for d in dsts:
+        assert np.array_equal(d.cpu().numpy(), alone)
+    st2 = srv.open(OFF, 640, 480)
+    many = [st2.submit(src, dsts[k % 6]) for k in range(40)]
+    srv.close()                          # cancels what is still queued
+    # the stream object was freed by destroy; statuses are not observable after it, so only
+    # check that destroy returned and the GPU is idle and consistent
+    torch.cuda.synchronize()
+    assert len(ts) == 6 and len(many) == 40
+
+
+def test_submit_rejects_wrong_size():
+    srv = hzd.Server(arena_bytes=_need(RT, 320, 240) + (1 << 20))
+    st = srv.open(RT, 320, 240)
+    bad = torch.zeros((100, 100, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(hzd.HzdError) as e:
+        st.submit(bad, torch.zeros_like(bad))
+    assert e.value.status == hzd.HZD_E_INVAL
+    st.close()
+    srv.close()
