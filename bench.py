@@ -62,7 +62,13 @@ def cpu_model():
 
 
 def percentile(xs, q):
+    if len(xs) == 0:
+        return None
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def rnd(v, k):
+    return None if v is None else round(v, k)
 
 
 def cpu_baseline(I, p_oracle, budget_s: float):
@@ -99,6 +105,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--graphs", type=int, default=1, help="replay captured HIP graphs (1) or launch directly (0)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run 5 device-to-device copies of this many MB (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -136,33 +146,42 @@ def main():
     stream = torch.cuda.current_stream()
     calls = [hzd.FrameCall(s, d, p, w, stream=stream) for s, d, w in sets]
 
-    # ---- plain: timed region
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b2 = torch.empty_like(a)
+        for _ in range(5):
+            b2.copy_(a)
+        torch.cuda.synchronize()
+        del a, b2
+
+    # ---- plain: timed region (production configuration: captured HIP graphs, no stage events)
+    if args.graphs:
+        hzd.graph_cache(256)
     log("plain: warmup")
     for i in range(args.warmup):
         calls[i % len(calls)]()
     torch.cuda.synchronize()
-    hzd.profile_read(reset=True)
-    hzd.profile_enable(True)
     log(f"plain: {args.steps} timed steps")
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         calls[i % len(calls)]()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = hzd.profile_read(reset=True)
-    hzd.profile_enable(False)
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     plain_mps = args.steps * mp / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    # the same loop without stage events, to show what they cost
+    # ---- the same steps with per-kernel HIP events on the launch stream (direct launches)
+    hzd.profile_read(reset=True)
+    hzd.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         calls[i % len(calls)]()
     torch.cuda.synchronize()
-    plain_mps_noev = args.steps * mp / (time.perf_counter() - t0)
+    plain_mps_events = args.steps * mp / (time.perf_counter() - t0)
+    stages = hzd.profile_read(reset=True)
+    hzd.profile_enable(False)
 
     # ---- plain: per-frame latency (one frame at a time, idle GPU)
     lat = []
@@ -232,7 +251,7 @@ def main():
             st.close()
         srv.close()
         served = {"MP_per_s": round(served_mps, 2), "streams": S, "frames": S * F,
-                  "vs_plain": round(served_mps / plain_mps_noev, 3),
+                  "vs_plain": round(served_mps / plain_mps, 3),
                   "latency_ms_at_30fps_per_stream": {"p50": round(percentile(lat_paced, 50), 3),
                                                      "p99": round(percentile(lat_paced, 99), 3),
                                                      "offered_MP_per_s": round(S * rate * mp, 1)},
@@ -255,8 +274,9 @@ def main():
                                "one frame per step",
                    "global_batch": 1, "seq_len": None, "parallelism": "single GPU",
                    "rotating_buffer_sets": len(sets), "working_set_MB": round(working_set / 1e6, 1)},
-        "plain": {"MP_per_s": round(plain_mps, 2), "MP_per_s_without_stage_events": round(plain_mps_noev, 2),
-                  "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}},
+        "plain": {"MP_per_s": round(plain_mps, 2), "graphs": bool(args.graphs),
+                  "MP_per_s_with_stage_events_direct_launches": round(plain_mps_events, 2),
+                  "latency_ms": {"p50": rnd(percentile(lat, 50), 4), "p99": rnd(percentile(lat, 99), 4)}},
         "served": served,
         "stages": stage_rows,
         "roofline": roofline,

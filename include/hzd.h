@@ -226,6 +226,39 @@ typedef struct hzd_server_stats {
 } hzd_server_stats;
 int hzd_server_stats_get(hzd_server* s, hzd_server_stats* out);
 
+/* ------------------------------------------------------------ tuning
+ * Tile shapes are tuning knobs only: the guided filter's box sums are exact
+ * integers and every other reduction is integer or per pixel, so each result
+ * is bit-identical for every allowed tile shape.  The table is process-wide
+ * and keyed by frame size ((0, 0) = default for sizes without an entry).
+ *   gf_rows  output rows per guided-filter block, 8..256 (default 32) */
+typedef struct hzd_tile_config {
+  int32_t gf_rows;
+} hzd_tile_config;
+/* Set (cfg != NULL) or remove (cfg == NULL) the entry for width x height. */
+int hzd_tile_config_set(int32_t width, int32_t height, const hzd_tile_config* cfg);
+/* The configuration frames of this size use. */
+int hzd_tile_config_get(int32_t width, int32_t height, hzd_tile_config* cfg);
+/* Autotuner: time `reps` calls of hzd_dehaze_frame on this frame for each
+ * candidate tile shape (HIP events on hip_stream, which is synchronised),
+ * store the fastest in the table for the frame's size and return it in *best.
+ * The frame's dst is overwritten.  If the environment variable
+ * HZD_AUTOTUNE_CACHE names a file, results are appended to it and entries
+ * found there are loaded into the table on first use. */
+int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspace, size_t ws_bytes,
+                 void* hip_stream, int32_t reps, hzd_tile_config* best);
+
+/* ------------------------------------------------------------ graphs
+ * The launches of one pipeline can be captured into a HIP graph and replayed.
+ * Graphs are cached process-wide, keyed by the complete launch arguments
+ * (frame sizes, parameters, pixel/workspace/aux pointers), so they pay off
+ * when callers reuse buffers (frame pools, server slots).  capacity = 0
+ * turns the cache off (every call launches its kernels directly); the
+ * default is 0.  Calls on the null stream and calls made while profiling is
+ * enabled always launch directly.  Shrinking the cache synchronises the
+ * device before destroying evicted graphs. */
+int hzd_graph_cache(int32_t capacity);
+
 /* ------------------------------------------------------------ profiling
  * Per-stage timing with HIP events recorded on the stream each kernel is
  * launched on.  While enabled (process-wide), every kernel launch of the

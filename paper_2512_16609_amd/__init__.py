@@ -66,6 +66,10 @@ class hzd_server_stats(ctypes.Structure):
                 ("inflight", ctypes.c_int32)]
 
 
+class hzd_tile_config(ctypes.Structure):
+    _fields_ = [("gf_rows", ctypes.c_int32)]
+
+
 class hzd_profile_entry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
@@ -100,6 +104,12 @@ SYMBOLS = {
                                         ctypes.POINTER(ctypes.c_int32)]),
     "hzd_stream_close": (ctypes.c_int, [ctypes.c_void_p]),
     "hzd_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_server_stats)]),
+    "hzd_tile_config_set": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(hzd_tile_config)]),
+    "hzd_tile_config_get": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(hzd_tile_config)]),
+    "hzd_autotune": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame), ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.POINTER(hzd_tile_config)]),
+    "hzd_graph_cache": (ctypes.c_int, [ctypes.c_int32]),
     "hzd_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "hzd_profile_read": (ctypes.c_int, [ctypes.POINTER(hzd_profile_entry), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
@@ -368,3 +378,34 @@ class FrameCall:
         rc = self.fn(self.pp, self.fp, self.aux, self.ws, self.ws_bytes, self.stream)
         if rc != HZD_OK:
             _check(rc, "hzd_dehaze_frame")
+
+
+# ------------------------------------------------------------------- tuning
+def tile_config_set(width: int, height: int, gf_rows: int | None) -> None:
+    """hzd_tile_config_set; gf_rows None removes the entry."""
+    c = hzd_tile_config(gf_rows) if gf_rows is not None else None
+    _check(lib().hzd_tile_config_set(width, height, ctypes.byref(c) if c is not None else None),
+           "hzd_tile_config_set")
+
+
+def tile_config_get(width: int, height: int) -> int:
+    c = hzd_tile_config()
+    _check(lib().hzd_tile_config_get(width, height, ctypes.byref(c)), "hzd_tile_config_get")
+    return int(c.gf_rows)
+
+
+def autotune(src, dst, params: Params, workspace=None, reps: int = 20, stream=None) -> int:
+    """hzd_autotune on one frame; returns the chosen gf_rows (now in the table)."""
+    f = _frame_struct(src, dst)
+    pc = params.c()
+    if workspace is None:
+        workspace = alloc_workspace(workspace_size(params, [(src.shape[0], src.shape[1])]), src.device)
+    best = hzd_tile_config()
+    _check(lib().hzd_autotune(ctypes.byref(pc), ctypes.byref(f), workspace.data_ptr(), workspace.numel(),
+                              _stream_handle(stream), reps, ctypes.byref(best)), "hzd_autotune")
+    return int(best.gf_rows)
+
+
+def graph_cache(capacity: int) -> None:
+    """hzd_graph_cache: replay captured HIP graphs for repeated launch arguments (0 = off)."""
+    _check(lib().hzd_graph_cache(capacity), "hzd_graph_cache")

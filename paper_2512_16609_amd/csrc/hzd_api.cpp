@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -111,17 +112,51 @@ size_t frame_ws_bytes(const hzd_params& p, int W, int H) {
   s += a256((size_t)H * a16(W));                       // D
   if (needE) s += a256((size_t)H * a16(3 * W));        // E
   s += a256((size_t)H * 16);                           // rowinfo
-  if (p.color_balance) {
-    int nb = recon_blocks(W, H);
-    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius, kGfRowsMin));
-    s += a256((size_t)nb * 16);                        // colour-balance partials
-  }
   if (offline) {
     s += a256((size_t)W * H * 8);                      // LP
     s += a256((size_t)W * H * 8);                      // AB
     if (p.color_balance) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
   }
   return s;
+}
+
+// ------------------------------------------------------------ tile table
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, hzd_tile_config> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("HZD_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return;
+  int w, h, rows;
+  while (std::fscanf(fp, "%d %d %d", &w, &h, &rows) == 3) {
+    if (w >= 0 && h >= 0 && rows >= kGfRowsMin && rows <= 256) g_tune[{w, h}] = hzd_tile_config{rows};
+  }
+  std::fclose(fp);
+}
+
+void tune_save(int w, int h, const hzd_tile_config& c) {
+  const char* path = std::getenv("HZD_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%d %d %d\n", w, h, c.gf_rows);
+  std::fclose(fp);
+}
+}  // namespace
+
+hzd_tile_config tile_config_for(int W, int H) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find({W, H});
+  if (it == g_tune.end()) it = g_tune.find({0, 0});
+  if (it != g_tune.end()) return it->second;
+  return hzd_tile_config{kGfRowsDefault};
 }
 
 // Fill the device descriptor of one frame; `ws` is the frame's workspace base.
@@ -149,12 +184,6 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   }
   d.rowinfo = reinterpret_cast<uint4*>(ws + off);
   off += a256((size_t)H * 16);
-  if (p.color_balance) {
-    int nb = recon_blocks(W, H);
-    if (offline) nb = std::max(nb, gf_blocks(W, H, p.gf_radius, kGfRowsMin));
-    d.cbpart = reinterpret_cast<float4*>(ws + off);
-    off += a256((size_t)nb * 16);
-  }
   if (offline) {
     d.LP = reinterpret_cast<uint2*>(ws + off);
     off += a256((size_t)W * H * 8);
@@ -190,7 +219,7 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     d.ab_scale = std::ldexp(1.0f, k);
     d.ab_inv_scale = std::ldexp(1.0f, -k);
   }
-  d.gf_rows = kGfRowsDefault;
+  d.gf_rows = tile_config_for(W, H).gf_rows;
   d.aligned = ((uintptr_t)fr.src % 4 == 0) && ((uintptr_t)fr.dst % 4 == 0) && (fr.src_pitch % 4 == 0) &&
               (fr.dst_pitch % 4 == 0);
   return d;
@@ -271,6 +300,81 @@ int run_group(const GroupKey& g, const Batch& b, hipStream_t s) {
   return HZD_OK;
 }
 
+// ------------------------------------------------------------ graph cache
+namespace {
+struct GraphEntry {
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+std::mutex g_graph_mu;
+int g_graph_cap = 0;
+uint64_t g_graph_clock = 0;
+std::map<std::string, GraphEntry> g_graphs;
+
+void graph_evict_locked(size_t keep) {
+  if (g_graphs.size() <= keep) return;
+  (void)hipDeviceSynchronize();  // an evicted graph may still be running somewhere
+  while (g_graphs.size() > keep) {
+    auto victim = g_graphs.begin();
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+      if (it->second.last_use < victim->second.last_use) victim = it;
+    (void)hipGraphExecDestroy(victim->second.exec);
+    g_graphs.erase(victim);
+  }
+}
+}  // namespace
+
+// Launch one group: replay a cached graph of its kernels when enabled.
+int launch_group(const GroupKey& g, const Batch& b, hipStream_t s) {
+  int cap;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    cap = g_graph_cap;
+  }
+  if (cap == 0 || s == nullptr || g_prof_on.load(std::memory_order_relaxed)) return run_group(g, b, s);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return run_group(g, b, s);  // the caller is capturing: our launches join its graph
+  }
+  std::string key(reinterpret_cast<const char*>(&g), sizeof(g));
+  key.append(reinterpret_cast<const char*>(&b), sizeof(b));
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+      it->second.last_use = ++g_graph_clock;
+      exec = it->second.exec;
+    }
+  }
+  if (!exec) {
+    int rc = check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (rc) return rc;
+    const int rrc = run_group(g, b, s);
+    hipGraph_t graph = nullptr;
+    rc = check(hipStreamEndCapture(s, &graph), "end capture");
+    if (rrc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rrc;
+    }
+    if (rc) return rc;
+    rc = check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {  // another thread captured the same key meanwhile
+      (void)hipGraphExecDestroy(exec);
+      exec = it->second.exec;
+    } else {
+      graph_evict_locked((size_t)std::max(0, g_graph_cap - 1));
+      g_graphs[key] = GraphEntry{exec, ++g_graph_clock};
+    }
+  }
+  return check(hipGraphLaunch(exec, s), "graph launch");
+}
+
 int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, const hzd_frame_aux* aux,
                 void* workspace, size_t ws_bytes, void* stream) {
   if (n < 1) return fail(HZD_E_INVAL, "n = %d < 1", n);
@@ -306,7 +410,7 @@ int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, co
         b.f[j] = make_frame_dev(*ps[i], frames[i], aux ? &aux[i] : nullptr,
                                 reinterpret_cast<uint8_t*>(workspace) + offs[i]);
       }
-      int rc = run_group(kv.first, b, s);
+      int rc = launch_group(kv.first, b, s);
       if (rc) return rc;
     }
   }
@@ -384,6 +488,98 @@ int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_
     need += frame_ws_bytes(*p, frames[i].width, frames[i].height);
   }
   *bytes = need;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_tile_config_set(int32_t width, int32_t height, const hzd_tile_config* cfg) {
+  if (width < 0 || height < 0) return fail(HZD_E_INVAL, "size %dx%d", width, height);
+  if (cfg && (cfg->gf_rows < kGfRowsMin || cfg->gf_rows > 256))
+    return fail(HZD_E_INVAL, "gf_rows %d outside %d..256", cfg->gf_rows, kGfRowsMin);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  if (cfg) g_tune[{width, height}] = *cfg;
+  else g_tune.erase({width, height});
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_tile_config_get(int32_t width, int32_t height, hzd_tile_config* cfg) {
+  if (!cfg) return fail(HZD_E_INVAL, "cfg is NULL");
+  *cfg = tile_config_for(width, height);
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspace, size_t ws_bytes,
+                 void* hip_stream, int32_t reps, hzd_tile_config* best) {
+  if (!frame || !best) return fail(HZD_E_INVAL, "NULL argument");
+  if (reps < 1 || reps > 10000) return fail(HZD_E_INVAL, "reps %d outside 1..10000", reps);
+  const hzd_params* p = frame->params ? frame->params : params;
+  int rc = validate_params(p);
+  if (rc) return rc;
+  const int W = frame->width, H = frame->height;
+  if (p->mode != HZD_MODE_OFFLINE) {  // no tile knob on the real-time path
+    *best = tile_config_for(W, H);
+    clear_error();
+    return HZD_OK;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0, e1;
+  if ((rc = check(hipEventCreate(&e0), "event")) != HZD_OK) return rc;
+  if ((rc = check(hipEventCreate(&e1), "event")) != HZD_OK) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  const hzd_tile_config prev = tile_config_for(W, H);
+  bool had_entry;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    had_entry = g_tune.count({W, H}) > 0;
+  }
+  static const int kCand[] = {8, 16, 24, 32, 48, 64, 96, 128};
+  float best_ms = 1e30f;
+  hzd_tile_config bestc = prev;
+  for (int rows : kCand) {
+    if (rows > H && rows != kCand[0]) break;
+    hzd_tile_config c{rows};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[{W, H}] = c;
+    }
+    rc = dehaze_many(params, frame, 1, nullptr, workspace, ws_bytes, hip_stream);  // warm
+    if (rc == HZD_OK) rc = check(hipEventRecord(e0, s), "event record");
+    for (int i = 0; i < reps && rc == HZD_OK; ++i) rc = dehaze_many(params, frame, 1, nullptr, workspace, ws_bytes, hip_stream);
+    if (rc == HZD_OK) rc = check(hipEventRecord(e1, s), "event record");
+    if (rc == HZD_OK) rc = check(hipEventSynchronize(e1), "event sync");
+    float ms = 0.f;
+    if (rc == HZD_OK) rc = check(hipEventElapsedTime(&ms, e0, e1), "event time");
+    if (rc != HZD_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      bestc = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (rc == HZD_OK) g_tune[{W, H}] = bestc;
+    else if (had_entry) g_tune[{W, H}] = prev;
+    else g_tune.erase({W, H});
+  }
+  if (rc != HZD_OK) return rc;
+  tune_save(W, H, bestc);
+  *best = bestc;
+  clear_error();
+  return HZD_OK;
+}
+
+int hzd_graph_cache(int32_t capacity) {
+  if (capacity < 0 || capacity > 4096) return fail(HZD_E_INVAL, "capacity %d outside 0..4096", capacity);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  g_graph_cap = capacity;
+  graph_evict_locked((size_t)capacity);
   clear_error();
   return HZD_OK;
 }

@@ -19,13 +19,12 @@ constexpr int kMaxRadius = 64;  // guided-filter radius supported by the 256-col
 struct FrameState {
   uint32_t hist[256];               // histogram of the dark channel D
   uint32_t ticket_select;           // last-block detection in the select kernel
-  uint32_t ticket_cb;               // last-block detection for colour-balance sums
-  uint32_t pad0[2];
+  uint32_t pad0[3];
   unsigned long long gt[4];         // sum of I^c over {D > vstar}, and its pixel count
   float A[4];                       // airlight A^c (0..255 scale)
   int32_t sel[4];                   // K, vstar, cutoff, consistency flag (0 = ok)
-  float gains[4];                   // gray-world gains
-  uint32_t pad1[48];
+  unsigned long long cb_sum[4];     // sum of J_gamma^c in 2^-23 fixed point (colour balance)
+  uint32_t pad1[40];
 };
 static_assert(sizeof(FrameState) <= 2048, "FrameState too large");
 
@@ -39,7 +38,6 @@ struct FrameDev {
   uint8_t* D;        // dark channel, pitch D_pitch
   uint8_t* E;        // per-channel erosions (packed RGB8), pitch E_pitch
   uint4* rowinfo;    // per row: {ties, sum R, sum G, sum B} over D == vstar
-  float4* cbpart;    // per block colour-balance partial sums
   uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
   int2* AB;          // offline: guided-filter a, b in fixed point (pitch W)
   void* tmap;        // offline + colour balance: refined t (float or half, pitch W)

@@ -72,15 +72,39 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Inclusive scan over the 64 lanes of a wave.
+// DPP move with zero for lanes whose source is outside the row or whose row
+// is masked off.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t v) { return v + dpp32<CTRL, ROW_MASK>(v); }
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_add(int32_t v) { return (int32_t)dpp_add<CTRL, ROW_MASK>((uint32_t)v); }
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_add(unsigned long long v) {
+  const uint32_t lo = dpp32<CTRL, ROW_MASK>((uint32_t)v), hi = dpp32<CTRL, ROW_MASK>((uint32_t)(v >> 32));
+  return v + (((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ long long dpp_add(long long v) {
+  return (long long)dpp_add<CTRL, ROW_MASK>((unsigned long long)v);
+}
+
+// Inclusive scan over the 64 lanes of a wave with DPP: Hillis-Steele inside
+// each row of 16 lanes (row_shr 1, 2, 4, 8), then row_bcast:15 carries row
+// totals into rows 1 and 3 and row_bcast:31 carries the first half's total
+// into rows 2 and 3.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    T u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
+  v = dpp_add<0x111, 0xF>(v);
+  v = dpp_add<0x112, 0xF>(v);
+  v = dpp_add<0x114, 0xF>(v);
+  v = dpp_add<0x118, 0xF>(v);
+  v = dpp_add<0x142, 0xA>(v);
+  v = dpp_add<0x143, 0xC>(v);
   return v;
 }
 
@@ -365,17 +389,39 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
     for (int base = 16 * lane; base < W; base += 1024) {
       const uint4 dv = *reinterpret_cast<const uint4*>(Drow + base);  // rows are padded to 16 bytes
       const uint32_t dw[4] = {dv.x, dv.y, dv.z, dv.w};
+      const int nx = min(16, W - base);
+      uint32_t cand = 0;  // pixels with D >= vstar
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const int x = base + k;
         const uint32_t d = (dw[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-        if (x < W && d >= vstar) {
-          const uint32_t r = Irow[3 * x], g = Irow[3 * x + 1], bl = Irow[3 * x + 2];
-          if (d > vstar) {
-            gR += r; gG += g; gB += bl; gN += 1;
-          } else {
-            tR += r; tG += g; tB += bl; tN += 1;
-          }
+        if (k < nx && d >= vstar) cand |= 1u << k;
+      }
+      if (!cand) continue;
+      // the lane's 16 pixels of I in one round trip when the rows are dword aligned
+      uint32_t iw[12];
+      const bool vec = fd.aligned && nx == 16;
+      if (vec) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(Irow + 3 * base);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) iw[j] = q[j];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (!((cand >> k) & 1u)) continue;
+        uint32_t r, g, bl;
+        if (vec) {
+          r = (iw[(3 * k) >> 2] >> (8 * ((3 * k) & 3))) & 0xFFu;
+          g = (iw[(3 * k + 1) >> 2] >> (8 * ((3 * k + 1) & 3))) & 0xFFu;
+          bl = (iw[(3 * k + 2) >> 2] >> (8 * ((3 * k + 2) & 3))) & 0xFFu;
+        } else {
+          const int x = base + k;
+          r = Irow[3 * x]; g = Irow[3 * x + 1]; bl = Irow[3 * x + 2];
+        }
+        const uint32_t d = (dw[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+        if (d > vstar) {
+          gR += r; gG += g; gB += bl; gN += 1;
+        } else {
+          tR += r; tG += g; tB += bl; tN += 1;
         }
       }
     }
@@ -620,8 +666,10 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
   t.H = fd.H;
   t.r = fd.radius;
   t.SW = kGfCols - 2 * t.r;
-  const int strips = (t.W + t.SW - 1) / t.SW;
-  const int sx = tile % strips, sy = tile / strips;
+  // column-major: consecutive tiles are vertical neighbours, which share
+  // 2r halo rows, and XCD-aware block mapping keeps runs of them in one L2
+  const int chunks = (t.H + fd.gf_rows - 1) / fd.gf_rows;
+  const int sx = tile / chunks, sy = tile - sx * chunks;
   t.x0 = sx * t.SW;
   t.y0 = sy * fd.gf_rows;
   t.y1 = min(t.H, t.y0 + fd.gf_rows);
@@ -630,8 +678,37 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
   return t;
 }
 
+constexpr int kPrimeBatch = 32;  // loads in flight per thread for the initial window
+constexpr int kRpi = 4;          // rows per barrier phase in the guided-filter strip kernels
+
 // Prefix sums over the 256 columns of one LDS row, 4 columns per lane (one
 // wave per row of the array).
+// NR rows of 256 values each, `stride` elements apart: independent scans
+// whose DPP steps interleave.
+template <typename T, int NR>
+__device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
+  const int lane = threadIdx.x & 63;
+  T v[NR][4];
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[j][k] = base[j * stride + 4 * lane + k];
+  T ex[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    v[j][1] += v[j][0];
+    v[j][2] += v[j][1];
+    v[j][3] += v[j][2];
+    ex[j] = v[j][3];
+  }
+#pragma unroll
+  for (int j = 0; j < NR; ++j) ex[j] = wave_incl_scan(ex[j]) - v[j][3];
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) base[j * stride + 4 * lane + k] = v[j][k] + ex[j];
+}
+
 template <typename T>
 __device__ __forceinline__ void wave_prefix256(T* row) {
   const int lane = threadIdx.x & 63;
@@ -648,14 +725,15 @@ __device__ __forceinline__ void wave_prefix256(T* row) {
 
 // Eq. (6), stage 1 (He et al. 2013 box form).  Each thread keeps exact u64
 // vertical window sums of L, L^2, P, L*P for its column, sliding down the
-// rows; per row the four column sums are prefix-summed across the strip in
-// LDS (one wave per quantity) and each output's clipped (2r+1)^2 box sum is a
-// difference of two prefixes.  The next row's operands are loaded one
-// iteration ahead, and the LDS rows are double-buffered (two barriers per
-// row).  Means, var and cov are formed in FP64; a and b leave as int32 fixed
-// point with the frame's scale.
+// rows.  Rows are handled kRpi at a time: the window sums of kRpi rows go to
+// LDS, one barrier, each wave prefix-sums one quantity of all kRpi rows
+// across the strip (independent DPP scans), another barrier, and each output
+// thread forms kRpi clipped (2r+1)^2 box sums as differences of two prefixes
+// (independent FP64 chains).  Operands of the next kRpi rows are loaded while
+// the current ones are processed.  Means, var and cov are formed in FP64; a
+// and b leave as int32 fixed point with the frame's scale.
 __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
-  __shared__ unsigned long long s_q[2][4][kGfCols];
+  __shared__ unsigned long long s_q[kRpi][4][kGfCols];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -673,9 +751,16 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     const unsigned long long L = v.x, P = v.y;
     sL -= L; sLL -= L * L; sP -= P; sLP -= L * P;
   };
-  if (g.colin) {
+  if (g.colin) {  // the initial window: many loads in flight per thread
     const int ya = max(0, g.y0 - r), yb = min(H - 1, g.y0 + r);
     int yy = ya;
+    for (; yy + kPrimeBatch <= yb + 1; yy += kPrimeBatch) {
+      uint2 v[kPrimeBatch];
+#pragma unroll
+      for (int k = 0; k < kPrimeBatch; ++k) v[k] = col[(int64_t)(yy + k) * W];
+#pragma unroll
+      for (int k = 0; k < kPrimeBatch; ++k) add(v[k]);
+    }
     for (; yy + 8 <= yb + 1; yy += 8) {
       uint2 v[8];
 #pragma unroll
@@ -685,16 +770,18 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     }
     for (; yy <= yb; ++yy) add(col[(int64_t)yy * W]);
   }
+  // entering/leaving rows of output row yn (zero where the window does not move)
   auto fetch = [&](int yn, uint2& vin, uint2& vout) {
     vin = make_uint2(0u, 0u);
     vout = make_uint2(0u, 0u);
-    if (g.colin && yn < g.y1) {
+    if (g.colin && yn > g.y0 && yn < g.y1) {
       if (yn + r < H) vin = col[(int64_t)(yn + r) * W];
       if (yn - r - 1 >= 0) vout = col[(int64_t)(yn - r - 1) * W];
     }
   };
-  uint2 pin, pout;
-  fetch(g.y0 + 1, pin, pout);
+  uint2 pin[kRpi], pout[kRpi];
+#pragma unroll
+  for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
 
   const int x = g.x0 + tid;
   const bool outcol = tid < g.SW && x < W;
@@ -703,82 +790,83 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
   const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
   const double eps = (double)fd.eps, s = (double)fd.ab_scale, lim = 2147483647.0;
-  int buf = 0;
-  for (int y = g.y0; y < g.y1; ++y) {
-    if (y > g.y0) {
-      add(pin);
-      sub(pout);
+  for (int yb = g.y0; yb < g.y1; yb += kRpi) {
+#pragma unroll
+    for (int u = 0; u < kRpi; ++u) {
+      add(pin[u]);
+      sub(pout[u]);
+      fetch(yb + kRpi + u, pin[u], pout[u]);
+      s_q[u][0][tid] = sL;
+      s_q[u][1][tid] = sLL;
+      s_q[u][2][tid] = sP;
+      s_q[u][3][tid] = sLP;
     }
-    fetch(y + 1, pin, pout);
-    s_q[buf][0][tid] = sL;
-    s_q[buf][1][tid] = sLL;
-    s_q[buf][2][tid] = sP;
-    s_q[buf][3][tid] = sLP;
     __syncthreads();
-    wave_prefix256(s_q[buf][wv]);
+    wave_prefix256_rows<unsigned long long, kRpi>(&s_q[0][wv][0], 4 * kGfCols);
     __syncthreads();
     if (outcol) {
-      double q[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        q[k] = (double)(s_q[buf][k][chi] - (clo > 0 ? s_q[buf][k][clo - 1] : 0ull));
-      const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
-      const double in = icw * rcp_nr((double)ch);
-      const double mG = q[0] * (in * kG);
-      const double mGG = q[1] * (in * (kG * kG));
-      const double mP = q[2] * (in * kP);
-      const double mGP = q[3] * (in * (kG * kP));
-      const double var = mGG - mG * mG;
-      const double cov = mGP - mG * mP;
-      const double a = cov * rcp_nr(var + eps);
-      const double bb = mP - a * mG;
-      const double ia = fmin(fmax(__builtin_rint(a * s), -lim), lim);
-      const double ib = fmin(fmax(__builtin_rint(bb * s), -lim), lim);
-      fd.AB[(int64_t)y * W + x] = make_int2((int)ia, (int)ib);
+      for (int u = 0; u < kRpi; ++u) {
+        const int y = yb + u;
+        if (y < g.y1) {
+          double q[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            q[k] = (double)(s_q[u][k][chi] - (clo > 0 ? s_q[u][k][clo - 1] : 0ull));
+          const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
+          const double in = icw * rcp_nr((double)ch);
+          const double mG = q[0] * (in * kG);
+          const double mGG = q[1] * (in * (kG * kG));
+          const double mP = q[2] * (in * kP);
+          const double mGP = q[3] * (in * (kG * kP));
+          const double var = mGG - mG * mG;
+          const double cov = mGP - mG * mP;
+          const double a = cov * rcp_nr(var + eps);
+          const double bb = mP - a * mG;
+          const double ia = fmin(fmax(__builtin_rint(a * s), -lim), lim);
+          const double ib = fmin(fmax(__builtin_rint(bb * s), -lim), lim);
+          fd.AB[(int64_t)y * W + x] = make_int2((int)ia, (int)ib);
+        }
+      }
     }
-    buf ^= 1;
+    __syncthreads();
   }
 }
 
-// Deterministic colour-balance partials: each block writes the sum of J_gamma
-// over its pixels; the last block of the frame (atomic ticket) adds the
-// partials in FP64 in block order and forms the gray-world gains.
-__device__ __forceinline__ void cb_finish(const FrameDev& fd, int tile, int nblk, const float acc[3],
-                                          float* s_red, double* s_d, int* s_last) {
-  const int tid = threadIdx.x;
-  const float s0 = block_sum(acc[0], s_red), s1 = block_sum(acc[1], s_red), s2 = block_sum(acc[2], s_red);
-  if (tid == 0) fd.cbpart[tile] = make_float4(s0, s1, s2, 0.f);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) *s_last = (atomicAdd(&fd.st->ticket_cb, 1u) == (uint32_t)(nblk - 1));
-  __syncthreads();
-  if (!*s_last) return;
-  __threadfence();
-  double m[3] = {0.0, 0.0, 0.0};
-  for (int i = tid; i < nblk; i += 256) {
-    const float4 pp = fd.cbpart[i];
-    m[0] += pp.x; m[1] += pp.y; m[2] += pp.z;
+// Colour-balance sums that do not depend on the tiling: J_gamma in fixed
+// point (2^-23 steps; exact for J_gamma >= 1), summed in u64 per block and
+// merged with integer atomics.  The consumer forms the gray-world gains.
+__device__ __forceinline__ uint32_t cb_fixed(float jg) { return (uint32_t)__builtin_rintf(jg * 8388608.0f); }
+
+__device__ __forceinline__ void cb_accumulate(const FrameDev& fd, const unsigned long long acc[3],
+                                              unsigned long long* s_tmp) {
+  const unsigned long long s0 = block_sum(acc[0], s_tmp), s1 = block_sum(acc[1], s_tmp),
+                           s2 = block_sum(acc[2], s_tmp);
+  if (threadIdx.x == 0) {
+    atomicAdd(&fd.st->cb_sum[0], s0);
+    atomicAdd(&fd.st->cb_sum[1], s1);
+    atomicAdd(&fd.st->cb_sum[2], s2);
   }
-  for (int c = 0; c < 3; ++c) m[c] = block_sum(m[c], s_d);
-  if (tid == 0) {
-    const double n = (double)fd.W * (double)fd.H;
-    const double mu[3] = {m[0] / n, m[1] / n, m[2] / n};
-    const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
-    for (int c = 0; c < 3; ++c) fd.st->gains[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
-  }
+}
+
+// Gray-world gains g_c = mean(mu) / mu_c (1 when mu_c = 0) from the sums.
+__device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3]) {
+  const double k = 1.0 / (8388608.0 * (double)fd.W * (double)fd.H);
+  double mu[3];
+  for (int c = 0; c < 3; ++c) mu[c] = (double)fd.st->cb_sum[c] * k;
+  const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
+  for (int c = 0; c < 3; ++c) g[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
 }
 
 // ------------------------------------------------------------------- k_gf_q
 // Eq. (6), stage 2: box means of a and b (exact i64 sums of the fixed-point
-// values, same strip scheme and prefetching), q = mean(a) G + mean(b),
-// clamped to [t0, 1].  PHASE 0: fuse Eqs. (7)-(8) and write the output.
-// PHASE 1: store the refined t and the colour-balance partial sums.
+// values, same strip scheme, kRpi rows per barrier phase), q = mean(a) G +
+// mean(b), clamped to [t0, 1].  PHASE 0: fuse Eqs. (7)-(8) and write the
+// output.  PHASE 1: store the refined t and the colour-balance sums.
 template <int PHASE, bool FP16>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
-  __shared__ long long s_q[2][2][kGfCols];
-  __shared__ float s_red[4];
-  __shared__ double s_d[4];
-  __shared__ int s_last;
+  __shared__ long long s_q[kRpi][2][kGfCols];
+  __shared__ unsigned long long s_red[4];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -793,12 +881,12 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   if (g.colin) {
     const int ya = max(0, g.y0 - r), yb = min(H - 1, g.y0 + r);
     int yy = ya;
-    for (; yy + 8 <= yb + 1; yy += 8) {
-      int2 v[8];
+    for (; yy + kPrimeBatch <= yb + 1; yy += kPrimeBatch) {
+      int2 v[kPrimeBatch];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = col[(int64_t)(yy + k) * W];
+      for (int k = 0; k < kPrimeBatch; ++k) v[k] = col[(int64_t)(yy + k) * W];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < kPrimeBatch; ++k) {
         sa += v[k].x;
         sb += v[k].y;
       }
@@ -812,14 +900,14 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   auto fetch = [&](int yn, int2& vin, int2& vout) {
     vin = make_int2(0, 0);
     vout = make_int2(0, 0);
-    if (g.colin && yn < g.y1) {
+    if (g.colin && yn > g.y0 && yn < g.y1) {
       if (yn + r < H) vin = col[(int64_t)(yn + r) * W];
       if (yn - r - 1 >= 0) vout = col[(int64_t)(yn - r - 1) * W];
     }
   };
   const int x = g.x0 + tid;
   const bool outcol = tid < g.SW && x < W;
-  // the output pixel's guide value and colour, one row ahead
+  // the output pixel's guide value and colour
   auto fetch_px = [&](int yn, uint32_t& L, uint32_t& rgb) {
     L = 0u;
     rgb = 0u;
@@ -829,76 +917,85 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
       rgb = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
     }
   };
-  int2 pin, pout;
-  fetch(g.y0 + 1, pin, pout);
-  uint32_t curL, curRGB;
-  fetch_px(g.y0, curL, curRGB);
+  int2 pin[kRpi], pout[kRpi];
+  uint32_t pL[kRpi], pRGB[kRpi];
+#pragma unroll
+  for (int u = 0; u < kRpi; ++u) {
+    fetch(g.y0 + u, pin[u], pout[u]);
+    fetch_px(g.y0 + u, pL[u], pRGB[u]);
+  }
 
   const int lo = max(x - r, 0), hi = min(x + r, W - 1);
   const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
   const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
   const double inv_s = (double)fd.ab_inv_scale;
   const double t0 = (double)fd.t0;
-  float acc[3] = {0.f, 0.f, 0.f};
-  int buf = 0;
-  for (int y = g.y0; y < g.y1; ++y) {
-    if (y > g.y0) {
-      sa += pin.x - pout.x;
-      sb += pin.y - pout.y;
+  unsigned long long acc[3] = {0ull, 0ull, 0ull};
+  for (int yb = g.y0; yb < g.y1; yb += kRpi) {
+    uint32_t curL[kRpi], curRGB[kRpi];
+#pragma unroll
+    for (int u = 0; u < kRpi; ++u) {
+      sa += pin[u].x - pout[u].x;
+      sb += pin[u].y - pout[u].y;
+      fetch(yb + kRpi + u, pin[u], pout[u]);
+      curL[u] = pL[u];
+      curRGB[u] = pRGB[u];
+      fetch_px(yb + kRpi + u, pL[u], pRGB[u]);
+      s_q[u][0][tid] = sa;
+      s_q[u][1][tid] = sb;
     }
-    fetch(y + 1, pin, pout);
-    uint32_t nL, nRGB;
-    fetch_px(y + 1, nL, nRGB);
-    s_q[buf][0][tid] = sa;
-    s_q[buf][1][tid] = sb;
     __syncthreads();
-    if (wv < 2) wave_prefix256(s_q[buf][wv]);
+    // 2 quantities x kRpi rows of scans over the 4 waves
+    wave_prefix256_rows<long long, kRpi / 2>(&s_q[wv >> 1][wv & 1][0], 2 * 2 * kGfCols);
     __syncthreads();
     if (outcol) {
-      const long long qa = s_q[buf][0][chi] - (clo > 0 ? s_q[buf][0][clo - 1] : 0ll);
-      const long long qb = s_q[buf][1][chi] - (clo > 0 ? s_q[buf][1][clo - 1] : 0ll);
-      const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
-      const double in = inv_s * icw * rcp_nr((double)ch);
-      const double G = (double)curL * (1.0 / 255000.0);
-      const double q = fma((double)qa * in, G, (double)qb * in);
-      float t = (float)fmin(fmax(q, t0), 1.0);
-      if (FP16) t = round_half(t);
-      const int64_t pi = (int64_t)y * W + x;
-      if (fd.t_out) fd.t_out[pi] = t;
-      float I[3] = {(float)(curRGB & 0xFFu), (float)((curRGB >> 8) & 0xFFu), (float)((curRGB >> 16) & 0xFFu)};
-      float J[3], Jg[3];
-      recon_pixel(rc, I, t, J, Jg);
-      if (fd.J_out) {
-        fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
-      }
-      if (PHASE == 0) {
-        uint8_t* o = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x;
-        o[0] = (uint8_t)rne_u8(Jg[0]);
-        o[1] = (uint8_t)rne_u8(Jg[1]);
-        o[2] = (uint8_t)rne_u8(Jg[2]);
-      } else {
-        if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
-        else reinterpret_cast<float*>(fd.tmap)[pi] = t;
-        acc[0] += Jg[0]; acc[1] += Jg[1]; acc[2] += Jg[2];
+#pragma unroll
+      for (int u = 0; u < kRpi; ++u) {
+        const int y = yb + u;
+        if (y < g.y1) {
+          const long long qa = s_q[u][0][chi] - (clo > 0 ? s_q[u][0][clo - 1] : 0ll);
+          const long long qb = s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ll);
+          const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
+          const double in = inv_s * icw * rcp_nr((double)ch);
+          const double G = (double)curL[u] * (1.0 / 255000.0);
+          const double q = fma((double)qa * in, G, (double)qb * in);
+          float t = (float)fmin(fmax(q, t0), 1.0);
+          if (FP16) t = round_half(t);
+          const int64_t pi = (int64_t)y * W + x;
+          if (fd.t_out) fd.t_out[pi] = t;
+          const uint32_t c = curRGB[u];
+          float I[3] = {(float)(c & 0xFFu), (float)((c >> 8) & 0xFFu), (float)((c >> 16) & 0xFFu)};
+          float J[3], Jg[3];
+          recon_pixel(rc, I, t, J, Jg);
+          if (fd.J_out) {
+            fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
+          }
+          if (PHASE == 0) {
+            uint8_t* o = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x;
+            o[0] = (uint8_t)rne_u8(Jg[0]);
+            o[1] = (uint8_t)rne_u8(Jg[1]);
+            o[2] = (uint8_t)rne_u8(Jg[2]);
+          } else {
+            if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
+            else reinterpret_cast<float*>(fd.tmap)[pi] = t;
+            acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+          }
+        }
       }
     }
-    curL = nL;
-    curRGB = nRGB;
-    buf ^= 1;
+    __syncthreads();
   }
-  if (PHASE == 1) cb_finish(fd, tile, b.tile0[f + 1] - b.tile0[f], acc, s_red, s_d, &s_last);
+  if (PHASE == 1) cb_accumulate(fd, acc, s_red);
 }
 
 // ------------------------------------------------------------------ k_recon
 // Pointwise Eqs. (4)-(5) (or the refined t), Eq. (7), Eq. (8) and the colour
 // balance.  A block covers kReconPx pixels of one row, 4 per thread.
-// PHASE 0: write the output.  PHASE 1: colour-balance partial sums only (the
-// last block forms the gains).  PHASE 2: apply the gains and write.
+// PHASE 0: write the output.  PHASE 1: colour-balance sums only.  PHASE 2:
+// form the gray-world gains from the sums, apply them and write.
 template <int TSRC, int PHASE, bool FP16>
 __global__ __launch_bounds__(256) void k_recon(Batch b) {
-  __shared__ float s_red[4];
-  __shared__ double s_d[4];
-  __shared__ int s_last;
+  __shared__ unsigned long long s_red[4];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -911,10 +1008,8 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   const TxConsts k = tx_consts(fd);
   const ReconConsts rc = recon_consts(fd);
   float gain[3] = {1.f, 1.f, 1.f};
-  if (PHASE == 2) {
-    gain[0] = fd.st->gains[0]; gain[1] = fd.st->gains[1]; gain[2] = fd.st->gains[2];
-  }
-  float acc[3] = {0.f, 0.f, 0.f};
+  if (PHASE == 2) cb_gains(fd, gain);
+  unsigned long long acc[3] = {0ull, 0ull, 0ull};
   if (x0 < W) {
     const int nx = min(4, W - x0);
     const uint8_t* Ip = fd.src + (int64_t)y * fd.src_pitch + 3 * x0;
@@ -972,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
         if (FP16) t = round_half(t);
         recon_pixel(rc, I, t, J, Jg);
         if (PHASE == 1) {
-          acc[0] += Jg[0]; acc[1] += Jg[1]; acc[2] += Jg[2];
+          acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
         } else {
           const int64_t pi = (int64_t)y * W + x0 + i;
           if (fd.t_out) fd.t_out[pi] = t;
@@ -998,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       }
     }
   }
-  if (PHASE == 1) cb_finish(fd, tile, b.tile0[f + 1] - b.tile0[f], acc, s_red, s_d, &s_last);
+  if (PHASE == 1) cb_accumulate(fd, acc, s_red);
 }
 
 // ----------------------------------------------------------------- launches

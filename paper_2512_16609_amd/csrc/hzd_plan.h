@@ -18,6 +18,7 @@ bool operator<(const GroupKey& a, const GroupKey& b);
 size_t frame_ws_bytes(const hzd_params& p, int W, int H);
 FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws);
 int run_group(const GroupKey& g, const Batch& b, hipStream_t s);
+int launch_group(const GroupKey& g, const Batch& b, hipStream_t s);
 int check(hipError_t e, const char* what);
 
 }  // namespace hzd

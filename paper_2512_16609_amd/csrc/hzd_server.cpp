@@ -210,7 +210,7 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     b.f[i] = make_frame_dev(st->p, j.fr, &aux, ws);
   }
   (void)hipSetDevice(s->cfg.device);
-  int rc = run_group(key, b, s->hstreams[hs]);
+  int rc = launch_group(key, b, s->hstreams[hs]);
   if (rc == HZD_OK) rc = check(hipEventRecord(s->events[hs], s->hstreams[hs]), "event record");
   s->stats.launches++;
   if (rc != HZD_OK) {

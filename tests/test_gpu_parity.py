@@ -159,3 +159,53 @@ def test_same_shape_batch_of_eight_720p_fp16():
         assert d.max() <= 1
     for i, I in enumerate(frames):
         assert np.array_equal(dsts[i].cpu().numpy(), run_gpu(I, p, with_J=False)["out"])
+
+
+def test_results_do_not_depend_on_tile_rows():
+    # exact integer box sums and integer colour-balance sums: every tile shape gives the same bits
+    I = _frame(640, 480, 31)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
+    outs = []
+    try:
+        for rows in (8, 16, 24, 32, 64, 128, 256):
+            hzd.tile_config_set(640, 480, rows)
+            outs.append(run_gpu(I, p))
+    finally:
+        hzd.tile_config_set(640, 480, None)
+    for o in outs[1:]:
+        for k in o:
+            assert np.array_equal(o[k], outs[0][k]), k
+    compare(I, p, outs[0], label="tile rows")
+
+
+def test_autotune_picks_a_candidate():
+    I = _frame(640, 480, 32)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
+    src = to_dev(I)
+    dst = torch.zeros_like(src)
+    try:
+        rows = hzd.autotune(src, dst, p, reps=3)
+        assert rows in (8, 16, 24, 32, 48, 64, 96, 128)
+        assert hzd.tile_config_get(640, 480) == rows
+        compare(I, p, run_gpu(I, p), label="autotuned")
+    finally:
+        hzd.tile_config_set(640, 480, None)
+
+
+def test_graph_replay_matches_direct_launch():
+    I1, I2 = _frame(640, 480, 41), _frame(640, 480, 42)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
+    ref1, ref2 = run_gpu(I1, p, with_J=False)["out"], run_gpu(I2, p, with_J=False)["out"]
+    src, dst = to_dev(I1), torch.zeros((480, 640, 3), dtype=torch.uint8, device="cuda")
+    ws = hzd.alloc_workspace(hzd.workspace_size(p, [(480, 640)]))
+    stream = torch.cuda.Stream()
+    try:
+        hzd.graph_cache(8)
+        with torch.cuda.stream(stream):
+            for rep in range(4):      # capture once, then replays; new content in the same buffers
+                src.copy_(to_dev(I1 if rep % 2 == 0 else I2))
+                hzd.dehaze_frame(src, dst, p, workspace=ws, stream=stream)
+                stream.synchronize()
+                assert np.array_equal(dst.cpu().numpy(), ref1 if rep % 2 == 0 else ref2), rep
+    finally:
+        hzd.graph_cache(0)
