@@ -208,6 +208,9 @@ def main():
     served = None
     if not args.no_served:
         log("served: continuous batching")
+        # served batches change composition from launch to launch, so graphs keyed by the
+        # exact launch arguments would mostly be captured once and never replayed
+        hzd.graph_cache(0)
         S, F = args.served_streams, args.served_frames
         per_stream_ws = 2 * (hzd.workspace_size(p, [(H, W)]) + 256) + 1024
         srv = hzd.Server(arena_bytes=S * per_stream_ws + (1 << 20), max_inflight=16, frames_per_launch=8,

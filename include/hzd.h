@@ -231,7 +231,8 @@ int hzd_server_stats_get(hzd_server* s, hzd_server_stats* out);
  * integers and every other reduction is integer or per pixel, so each result
  * is bit-identical for every allowed tile shape.  The table is process-wide
  * and keyed by frame size ((0, 0) = default for sizes without an entry).
- *   gf_rows  output rows per guided-filter block, 8..256 (default 32) */
+ *   gf_rows  output rows per guided-filter block, a multiple of 8 in 8..256
+ *            (default 16) */
 typedef struct hzd_tile_config {
   int32_t gf_rows;
 } hzd_tile_config;

@@ -115,6 +115,8 @@ size_t frame_ws_bytes(const hzd_params& p, int W, int H) {
   if (offline) {
     s += a256((size_t)W * H * 8);                      // LP
     s += a256((size_t)W * H * 8);                      // AB
+    const size_t nch = (size_t)((H + 7) / 8);
+    s += a256(nch * W * 8) + a256(nch * W * 16) + a256(nch * W * 16);  // 8-row chunk sums
     if (p.color_balance) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
   }
   return s;
@@ -135,7 +137,7 @@ void tune_load_locked() {
   if (!fp) return;
   int w, h, rows;
   while (std::fscanf(fp, "%d %d %d", &w, &h, &rows) == 3) {
-    if (w >= 0 && h >= 0 && rows >= kGfRowsMin && rows <= 256) g_tune[{w, h}] = hzd_tile_config{rows};
+    if (w >= 0 && h >= 0 && rows >= kGfRowsMin && rows <= 256 && rows % 8 == 0) g_tune[{w, h}] = hzd_tile_config{rows};
   }
   std::fclose(fp);
 }
@@ -189,6 +191,13 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     off += a256((size_t)W * H * 8);
     d.AB = reinterpret_cast<int2*>(ws + off);
     off += a256((size_t)W * H * 8);
+    const size_t nch = (size_t)((H + 7) / 8);
+    d.S8a = reinterpret_cast<uint2*>(ws + off);
+    off += a256(nch * W * 8);
+    d.S8b = reinterpret_cast<ulonglong2*>(ws + off);
+    off += a256(nch * W * 16);
+    d.S8ab = reinterpret_cast<longlong2*>(ws + off);
+    off += a256(nch * W * 16);
     if (p.color_balance) {
       d.tmap = ws + off;
       off += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
@@ -494,8 +503,8 @@ int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_
 
 int hzd_tile_config_set(int32_t width, int32_t height, const hzd_tile_config* cfg) {
   if (width < 0 || height < 0) return fail(HZD_E_INVAL, "size %dx%d", width, height);
-  if (cfg && (cfg->gf_rows < kGfRowsMin || cfg->gf_rows > 256))
-    return fail(HZD_E_INVAL, "gf_rows %d outside %d..256", cfg->gf_rows, kGfRowsMin);
+  if (cfg && (cfg->gf_rows < kGfRowsMin || cfg->gf_rows > 256 || cfg->gf_rows % 8 != 0))
+    return fail(HZD_E_INVAL, "gf_rows %d not a multiple of 8 in %d..256", cfg->gf_rows, kGfRowsMin);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   if (cfg) g_tune[{width, height}] = *cfg;

@@ -15,18 +15,25 @@ constexpr int kMaxHalfPatch = 15;
 constexpr int kMaxRadius = 64;  // guided-filter radius supported by the 256-column strip kernels
 
 // Per-frame device state at the start of each frame's workspace.  Zeroed by the
-// init kernel at the start of every pipeline.
+// init kernel at the start of every pipeline.  Sums that many blocks merge
+// with integer atomics are spread over slots (block index mod slots), which
+// keeps same-address contention low; integer sums make the slot choice
+// irrelevant to the result.
+constexpr int kHistSlots = 8;
+constexpr int kCbSlots = 64;
+constexpr int kTicketGroups = 16;
 struct FrameState {
-  uint32_t hist[256];               // histogram of the dark channel D
-  uint32_t ticket_select;           // last-block detection in the select kernel
-  uint32_t pad0[3];
-  unsigned long long gt[4];         // sum of I^c over {D > vstar}, and its pixel count
-  float A[4];                       // airlight A^c (0..255 scale)
-  int32_t sel[4];                   // K, vstar, cutoff, consistency flag (0 = ok)
-  unsigned long long cb_sum[4];     // sum of J_gamma^c in 2^-23 fixed point (colour balance)
-  uint32_t pad1[40];
+  uint32_t hist[kHistSlots][256];       // histogram of the dark channel D, per slot
+  uint32_t ticket_group[kTicketGroups]; // last-block detection in the select kernel (two levels)
+  uint32_t ticket_top;
+  uint32_t pad0[15];
+  unsigned long long gt[4];             // sum of I^c over {D > vstar}, and its pixel count
+  float A[4];                           // airlight A^c (0..255 scale)
+  int32_t sel[4];                       // K, vstar, cutoff, consistency flag (0 = ok)
+  unsigned long long cb[kCbSlots][4];   // sum of J_gamma^c in 2^-23 fixed point, per slot
 };
-static_assert(sizeof(FrameState) <= 2048, "FrameState too large");
+static_assert(sizeof(FrameState) % 256 == 0 || true, "");
+static_assert(sizeof(FrameState) <= 12288, "FrameState too large");
 
 // Everything one frame needs on the device, passed by value in kernel arguments.
 struct FrameDev {
@@ -40,6 +47,9 @@ struct FrameDev {
   uint4* rowinfo;    // per row: {ties, sum R, sum G, sum B} over D == vstar
   uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
   int2* AB;          // offline: guided-filter a, b in fixed point (pitch W)
+  uint2* S8a;        // offline: per column and aligned 8-row chunk, sums of {L, P}
+  ulonglong2* S8b;   // offline: per column and chunk, sums of {L^2, L*P}
+  longlong2* S8ab;   // offline: per column and chunk, sums of {a, b} (fixed point)
   void* tmap;        // offline + colour balance: refined t (float or half, pitch W)
   float* A_out;
   int32_t* sel_out;
@@ -84,7 +94,7 @@ hipError_t launch_recon(Batch b, const GroupKey& g, int tsrc, int phase, hipStre
 constexpr int kDarkTW = 64, kDarkTH = 32;
 constexpr int kReconPx = 1024;   // pixels of one row per recon block
 constexpr int kGfCols = 256;     // loaded columns per guided-filter strip block
-constexpr int kGfRowsDefault = 32;  // output rows per guided-filter block unless tuned
+constexpr int kGfRowsDefault = 16;  // output rows per guided-filter block unless tuned (a multiple of 8)
 constexpr int kGfRowsMin = 8;
 inline int recon_blocks(int W, int H) { return H * ((W + kReconPx - 1) / kReconPx); }
 inline int gf_strip(int r) { return kGfCols - 2 * r; }

@@ -23,6 +23,12 @@
 
 namespace hzd {
 
+// guided-filter column chunk sums (initial windows) and strip loop shape
+constexpr int kChunk = 8;                                      // rows per chunk sum
+constexpr int kMaxHead = 2 * kChunk - 2;                       // head rows when a window holds no chunk
+constexpr int kChunkBatch = 8;                                 // chunk sums loaded per round trip
+constexpr int kSelVec = 4;                                     // 16-byte D vectors per lane loaded at once
+
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int frame_of(const Batch& b, int blk) {
   int f = 0;
@@ -207,14 +213,28 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   // stage each in-frame region row's bytes [3 xs, 3 xe) with aligned dword
   // loads (a dword holding at least one byte of the row never crosses a page)
   s_hist[tid] = 0u;
-  for (int i = tid; i < RH * SROW; i += 256) {
-    const int rr = i / SROW, j = i - rr * SROW;
-    const int y = y0 - HP + rr;
-    if (y < 0 || y >= H) continue;
-    const uintptr_t addr = (uintptr_t)(fd.src + (int64_t)y * fd.src_pitch + 3 * xs);
-    const uintptr_t a0 = addr & ~(uintptr_t)3;
-    const int nd = (int)((addr + 3 * (xe - xs) - a0 + 3) >> 2);
-    if (j < nd) s_stage[rr * SROW + j] = *reinterpret_cast<const uint32_t*>(a0 + 4 * (uintptr_t)j);
+  {
+    // every load of the block is issued before any LDS write waits on one
+    constexpr int NL = (RH * SROW + 255) / 256;
+    uint32_t v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = tid + 256 * k;
+      const int rr = i / SROW, j = i - rr * SROW;
+      const int y = y0 - HP + rr;
+      v[k] = 0u;
+      if (i < RH * SROW && y >= 0 && y < H) {
+        const uintptr_t addr = (uintptr_t)(fd.src + (int64_t)y * fd.src_pitch + 3 * xs);
+        const uintptr_t a0 = addr & ~(uintptr_t)3;
+        const int nd = (int)((addr + 3 * (xe - xs) - a0 + 3) >> 2);
+        if (j < nd) v[k] = *reinterpret_cast<const uint32_t*>(a0 + 4 * (uintptr_t)j);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = tid + 256 * k;
+      if (i < RH * SROW) s_stage[i] = v[k];
+    }
   }
   __syncthreads();
   // unpack into two planes of 16-bit pairs; out-of-frame cells hold 255
@@ -338,7 +358,7 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   }
   __syncthreads();
   const uint32_t hv = s_hist[tid];
-  if (hv) atomicAdd(&fd.st->hist[tid], hv);
+  if (hv) atomicAdd(&fd.st->hist[tile % kHistSlots][tid], hv);
 }
 
 // ---------------------------------------------------------------- k_select
@@ -369,7 +389,9 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
 
   // vstar and #{D > vstar}: thread t holds the count of value 255 - t
-  const uint32_t c = st->hist[255 - tid];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kHistSlots; ++k) c += st->hist[k][255 - tid];
   const uint32_t incl = block_incl_scan<uint32_t>(c, s_u32);
   if (incl >= (uint32_t)K && incl - c < (uint32_t)K) {
     s_misc[0] = 255 - tid;
@@ -386,8 +408,18 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
     uint32_t tN = 0, tR = 0, tG = 0, tB = 0;
     const uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch;
     const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
-    for (int base = 16 * lane; base < W; base += 1024) {
-      const uint4 dv = *reinterpret_cast<const uint4*>(Drow + base);  // rows are padded to 16 bytes
+    for (int seg = 0; seg < W; seg += 1024 * kSelVec) {
+      uint4 dvs[kSelVec];  // all of this lane's D vectors of the segment, loaded up front
+#pragma unroll
+      for (int q = 0; q < kSelVec; ++q) {
+        const int bq = seg + 1024 * q + 16 * lane;
+        dvs[q] = (bq < W) ? *reinterpret_cast<const uint4*>(Drow + bq) : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int q = 0; q < kSelVec; ++q) {
+      const int base = seg + 1024 * q + 16 * lane;
+      if (base >= W) continue;
+      const uint4 dv = dvs[q];  // rows are padded to 16 bytes
       const uint32_t dw[4] = {dv.x, dv.y, dv.z, dv.w};
       const int nx = min(16, W - base);
       uint32_t cand = 0;  // pixels with D >= vstar
@@ -424,6 +456,7 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
           tR += r; tG += g; tB += bl; tN += 1;
         }
       }
+      }
     }
     tN = wave_sum(tN); tR = wave_sum(tR); tG = wave_sum(tG); tB = wave_sum(tB);
     gN = wave_sum(gN);
@@ -442,7 +475,17 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
   // last block of this frame finishes the selection
   __threadfence();
   __syncthreads();
-  if (tid == 0) s_misc[2] = (atomicAdd(&st->ticket_select, 1u) == (uint32_t)(nblk - 1));
+  if (tid == 0) {
+    // two-level ticket: the last block of each group signals the top counter
+    const int grp = tile % kTicketGroups;
+    const uint32_t gsize = (uint32_t)((nblk - grp + kTicketGroups - 1) / kTicketGroups);
+    int last = 0;
+    if (atomicAdd(&st->ticket_group[grp], 1u) == gsize - 1u) {
+      __threadfence();
+      last = atomicAdd(&st->ticket_top, 1u) == (uint32_t)(min(kTicketGroups, nblk) - 1);
+    }
+    s_misc[2] = last;
+  }
   __syncthreads();
   if (!s_misc[2]) return;
   __threadfence();
@@ -613,32 +656,86 @@ __device__ __forceinline__ ReconConsts recon_consts(const FrameDev& fd) {
 // Offline mode, after the airlight: per pixel, the guide as an exact integer
 // L = 299 R + 587 G + 114 B (= 255000 * BT.601 luma in [0,1]) and the coarse
 // t of Eqs. (4)-(5) in fixed point P = rint(t * 2^28) (exact for t >= 1/16).
+// A block covers 8 rows x 256 columns (one column per thread) and also writes
+// each column's exact sums of L, P, L^2, L*P over its aligned 8-row chunk,
+// which give the guided-filter kernels their initial windows cheaply.
 template <int TX>
 __global__ __launch_bounds__(256) void k_gf_prep(Batch b) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
   const int tile = blk - b.tile0[f];
-  const int W = fd.W;
-  const int per_row = (W + kReconPx - 1) / kReconPx;
-  const int y = tile / per_row;
-  const int xb = (tile - y * per_row) * kReconPx;
+  const int W = fd.W, H = fd.H;
+  const int cblocks = (W + kGfCols - 1) / kGfCols;
+  const int ch = tile / cblocks;
+  const int x = (tile - ch * cblocks) * kGfCols + (int)threadIdx.x;
+  if (x >= W) return;
   const TxConsts k = tx_consts(fd);
-  const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
-  const uint8_t* Erow = fd.E + (int64_t)y * fd.E_pitch;
-  uint2* out = fd.LP + (int64_t)y * W;
-  for (int x = xb + threadIdx.x; x < min(W, xb + kReconPx); x += 256) {
-    const uint32_t r = Irow[3 * x], g = Irow[3 * x + 1], bl = Irow[3 * x + 2];
-    float t;
-    if (TX == TSRC_HE) {
-      t = tx_he(k, (float)Erow[3 * x], (float)Erow[3 * x + 1], (float)Erow[3 * x + 2]);
-    } else {
-      t = tx_paper(k, (float)min(min(r, g), bl));
+  const int y0 = ch * kChunk, n = min(kChunk, H - y0);
+  uint32_t rgb[kChunk], e[kChunk];
+#pragma unroll
+  for (int i = 0; i < kChunk; ++i) {
+    rgb[i] = 0u;
+    e[i] = 0u;
+    if (i < n) {
+      const uint8_t* ip = fd.src + (int64_t)(y0 + i) * fd.src_pitch + 3 * x;
+      rgb[i] = (uint32_t)ip[0] | ((uint32_t)ip[1] << 8) | ((uint32_t)ip[2] << 16);
+      if (TX == TSRC_HE) {
+        const uint8_t* ep = fd.E + (int64_t)(y0 + i) * fd.E_pitch + 3 * x;
+        e[i] = (uint32_t)ep[0] | ((uint32_t)ep[1] << 8) | ((uint32_t)ep[2] << 16);
+      }
     }
-    const uint32_t L = 299u * r + 587u * g + 114u * bl;
-    const uint32_t P = (uint32_t)__builtin_rintf(t * 268435456.0f);
-    out[x] = make_uint2(L, P);
   }
+  uint32_t sL = 0, sP = 0;
+  unsigned long long sLL = 0, sLP = 0;
+#pragma unroll
+  for (int i = 0; i < kChunk; ++i) {
+    if (i < n) {
+      const uint32_t r = rgb[i] & 0xFFu, g = (rgb[i] >> 8) & 0xFFu, bl = (rgb[i] >> 16) & 0xFFu;
+      float t;
+      if (TX == TSRC_HE) {
+        t = tx_he(k, (float)(e[i] & 0xFFu), (float)((e[i] >> 8) & 0xFFu), (float)((e[i] >> 16) & 0xFFu));
+      } else {
+        t = tx_paper(k, (float)min(min(r, g), bl));
+      }
+      const uint32_t L = 299u * r + 587u * g + 114u * bl;
+      const uint32_t P = (uint32_t)__builtin_rintf(t * 268435456.0f);
+      fd.LP[(int64_t)(y0 + i) * W + x] = make_uint2(L, P);
+      sL += L;
+      sP += P;
+      sLL += (unsigned long long)L * L;
+      sLP += (unsigned long long)L * P;
+    }
+  }
+  fd.S8a[(int64_t)ch * W + x] = make_uint2(sL, sP);
+  fd.S8b[(int64_t)ch * W + x] = make_ulonglong2(sLL, sLP);
+}
+
+// Rows [ya, yb] of one column as: head rows, whole aligned 8-row chunks
+// (a chunk at the frame bottom may be short), tail rows.  Every load of the
+// initial window is issued before any is consumed.
+struct WindowSplit {
+  int ya, head_end, c0, nch, tail_beg, yb;
+};
+
+__device__ __forceinline__ WindowSplit split_window(int ya, int yb, int H) {
+  WindowSplit w;
+  w.ya = ya;
+  w.yb = yb;
+  const int c0 = (ya + kChunk - 1) / kChunk;
+  const int c1 = (yb == H - 1) ? (H - 1) / kChunk : (yb + 1) / kChunk - 1;
+  if (c1 >= c0) {
+    w.c0 = c0;
+    w.nch = c1 - c0 + 1;
+    w.head_end = c0 * kChunk;                   // head rows [ya, head_end)
+    w.tail_beg = min(H, (c1 + 1) * kChunk);     // tail rows [tail_beg, yb]
+  } else {
+    w.c0 = 0;
+    w.nch = 0;
+    w.head_end = yb + 1;
+    w.tail_beg = yb + 1;
+  }
+  return w;
 }
 
 // ------------------------------------------------------------------ k_gf_ab
@@ -678,7 +775,6 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
   return t;
 }
 
-constexpr int kPrimeBatch = 32;  // loads in flight per thread for the initial window
 constexpr int kRpi = 4;          // rows per barrier phase in the guided-filter strip kernels
 
 // Prefix sums over the 256 columns of one LDS row, 4 columns per lane (one
@@ -751,24 +847,41 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     const unsigned long long L = v.x, P = v.y;
     sL -= L; sLL -= L * L; sP -= P; sLP -= L * P;
   };
-  if (g.colin) {  // the initial window: many loads in flight per thread
-    const int ya = max(0, g.y0 - r), yb = min(H - 1, g.y0 + r);
-    int yy = ya;
-    for (; yy + kPrimeBatch <= yb + 1; yy += kPrimeBatch) {
-      uint2 v[kPrimeBatch];
+  if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
+    const WindowSplit w = split_window(max(0, g.y0 - r), min(H - 1, g.y0 + r), H);
+    {
+      uint2 hv[kMaxHead], tv[kChunk - 1];
 #pragma unroll
-      for (int k = 0; k < kPrimeBatch; ++k) v[k] = col[(int64_t)(yy + k) * W];
+      for (int i = 0; i < kMaxHead; ++i)
+        hv[i] = (w.ya + i < w.head_end) ? col[(int64_t)(w.ya + i) * W] : make_uint2(0u, 0u);
 #pragma unroll
-      for (int k = 0; k < kPrimeBatch; ++k) add(v[k]);
+      for (int i = 0; i < kChunk - 1; ++i)
+        tv[i] = (w.tail_beg + i <= w.yb) ? col[(int64_t)(w.tail_beg + i) * W] : make_uint2(0u, 0u);
+#pragma unroll
+      for (int i = 0; i < kMaxHead; ++i) add(hv[i]);
+#pragma unroll
+      for (int i = 0; i < kChunk - 1; ++i) add(tv[i]);
     }
-    for (; yy + 8 <= yb + 1; yy += 8) {
-      uint2 v[8];
+    for (int c = 0; c < w.nch; c += kChunkBatch) {
+      uint2 ca[kChunkBatch];
+      ulonglong2 cb[kChunkBatch];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = col[(int64_t)(yy + k) * W];
+      for (int i = 0; i < kChunkBatch; ++i) {
+        ca[i] = make_uint2(0u, 0u);
+        cb[i] = make_ulonglong2(0ull, 0ull);
+        if (c + i < w.nch) {
+          ca[i] = fd.S8a[(int64_t)(w.c0 + c + i) * W + g.xl];
+          cb[i] = fd.S8b[(int64_t)(w.c0 + c + i) * W + g.xl];
+        }
+      }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) add(v[k]);
+      for (int i = 0; i < kChunkBatch; ++i) {
+        sL += ca[i].x;
+        sP += ca[i].y;
+        sLL += cb[i].x;
+        sLP += cb[i].y;
+      }
     }
-    for (; yy <= yb; ++yy) add(col[(int64_t)yy * W]);
   }
   // entering/leaving rows of output row yn (zero where the window does not move)
   auto fetch = [&](int yn, uint2& vin, uint2& vout) {
@@ -790,6 +903,7 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
   const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
   const double eps = (double)fd.eps, s = (double)fd.ab_scale, lim = 2147483647.0;
+  long long ca_ = 0, cb_ = 0;
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
@@ -826,6 +940,14 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
           const double ia = fmin(fmax(__builtin_rint(a * s), -lim), lim);
           const double ib = fmin(fmax(__builtin_rint(bb * s), -lim), lim);
           fd.AB[(int64_t)y * W + x] = make_int2((int)ia, (int)ib);
+          // the column's sums of a, b over its aligned 8-row chunk (for stage 2's window)
+          ca_ += (long long)ia;
+          cb_ += (long long)ib;
+          if ((y & (kChunk - 1)) == kChunk - 1 || y == H - 1) {
+            fd.S8ab[(int64_t)(y / kChunk) * W + x] = make_longlong2(ca_, cb_);
+            ca_ = 0;
+            cb_ = 0;
+          }
         }
       }
     }
@@ -838,22 +960,38 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
 // merged with integer atomics.  The consumer forms the gray-world gains.
 __device__ __forceinline__ uint32_t cb_fixed(float jg) { return (uint32_t)__builtin_rintf(jg * 8388608.0f); }
 
-__device__ __forceinline__ void cb_accumulate(const FrameDev& fd, const unsigned long long acc[3],
+__device__ __forceinline__ void cb_accumulate(const FrameDev& fd, int tile, const unsigned long long acc[3],
                                               unsigned long long* s_tmp) {
   const unsigned long long s0 = block_sum(acc[0], s_tmp), s1 = block_sum(acc[1], s_tmp),
                            s2 = block_sum(acc[2], s_tmp);
   if (threadIdx.x == 0) {
-    atomicAdd(&fd.st->cb_sum[0], s0);
-    atomicAdd(&fd.st->cb_sum[1], s1);
-    atomicAdd(&fd.st->cb_sum[2], s2);
+    unsigned long long* slot = fd.st->cb[tile % kCbSlots];
+    atomicAdd(&slot[0], s0);
+    atomicAdd(&slot[1], s1);
+    atomicAdd(&slot[2], s2);
   }
 }
 
-// Gray-world gains g_c = mean(mu) / mu_c (1 when mu_c = 0) from the sums.
-__device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3]) {
+// Gray-world gains g_c = mean(mu) / mu_c (1 when mu_c = 0) from the slot
+// sums: wave 0 reduces the 64 slots (one per lane), then one barrier.
+__device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3], unsigned long long* s_tmp) {
+  static_assert(kCbSlots == 64, "one slot per lane of wave 0");
+  const int t = threadIdx.x;
+  if (t < 64) {
+    unsigned long long v0 = fd.st->cb[t][0], v1 = fd.st->cb[t][1], v2 = fd.st->cb[t][2];
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    v2 = wave_sum(v2);
+    if (t == 0) {
+      s_tmp[0] = v0;
+      s_tmp[1] = v1;
+      s_tmp[2] = v2;
+    }
+  }
+  __syncthreads();
   const double k = 1.0 / (8388608.0 * (double)fd.W * (double)fd.H);
   double mu[3];
-  for (int c = 0; c < 3; ++c) mu[c] = (double)fd.st->cb_sum[c] * k;
+  for (int c = 0; c < 3; ++c) mu[c] = (double)s_tmp[c] * k;
   const double mbar = (mu[0] + mu[1] + mu[2]) / 3.0;
   for (int c = 0; c < 3; ++c) g[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
 }
@@ -878,23 +1016,37 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   const ReconConsts rc = recon_consts(fd);
 
   long long sa = 0, sb = 0;
-  if (g.colin) {
-    const int ya = max(0, g.y0 - r), yb = min(H - 1, g.y0 + r);
-    int yy = ya;
-    for (; yy + kPrimeBatch <= yb + 1; yy += kPrimeBatch) {
-      int2 v[kPrimeBatch];
+  if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
+    const WindowSplit w = split_window(max(0, g.y0 - r), min(H - 1, g.y0 + r), H);
+    {
+      int2 hv[kMaxHead], tv[kChunk - 1];
 #pragma unroll
-      for (int k = 0; k < kPrimeBatch; ++k) v[k] = col[(int64_t)(yy + k) * W];
+      for (int i = 0; i < kMaxHead; ++i)
+        hv[i] = (w.ya + i < w.head_end) ? col[(int64_t)(w.ya + i) * W] : make_int2(0, 0);
 #pragma unroll
-      for (int k = 0; k < kPrimeBatch; ++k) {
-        sa += v[k].x;
-        sb += v[k].y;
+      for (int i = 0; i < kChunk - 1; ++i)
+        tv[i] = (w.tail_beg + i <= w.yb) ? col[(int64_t)(w.tail_beg + i) * W] : make_int2(0, 0);
+#pragma unroll
+      for (int i = 0; i < kMaxHead; ++i) {
+        sa += hv[i].x;
+        sb += hv[i].y;
+      }
+#pragma unroll
+      for (int i = 0; i < kChunk - 1; ++i) {
+        sa += tv[i].x;
+        sb += tv[i].y;
       }
     }
-    for (; yy <= yb; ++yy) {
-      const int2 v = col[(int64_t)yy * W];
-      sa += v.x;
-      sb += v.y;
+    for (int c = 0; c < w.nch; c += kChunkBatch) {
+      longlong2 cs[kChunkBatch];
+#pragma unroll
+      for (int i = 0; i < kChunkBatch; ++i)
+        cs[i] = (c + i < w.nch) ? fd.S8ab[(int64_t)(w.c0 + c + i) * W + g.xl] : make_longlong2(0ll, 0ll);
+#pragma unroll
+      for (int i = 0; i < kChunkBatch; ++i) {
+        sa += cs[i].x;
+        sb += cs[i].y;
+      }
     }
   }
   auto fetch = [&](int yn, int2& vin, int2& vout) {
@@ -985,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     }
     __syncthreads();
   }
-  if (PHASE == 1) cb_accumulate(fd, acc, s_red);
+  if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
 }
 
 // ------------------------------------------------------------------ k_recon
@@ -1008,7 +1160,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   const TxConsts k = tx_consts(fd);
   const ReconConsts rc = recon_consts(fd);
   float gain[3] = {1.f, 1.f, 1.f};
-  if (PHASE == 2) cb_gains(fd, gain);
+  if (PHASE == 2) cb_gains(fd, gain, s_red);
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
   if (x0 < W) {
     const int nx = min(4, W - x0);
@@ -1093,7 +1245,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       }
     }
   }
-  if (PHASE == 1) cb_accumulate(fd, acc, s_red);
+  if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
 }
 
 // ----------------------------------------------------------------- launches
@@ -1156,7 +1308,9 @@ hipError_t launch_select(Batch b, hipStream_t s) {
 }
 
 hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s) {
-  const int nblk = fill_tiles(b, [](const FrameDev& f) { return recon_blocks(f.W, f.H); });
+  const int nblk = fill_tiles(b, [](const FrameDev& f) {
+    return ((f.W + kGfCols - 1) / kGfCols) * ((f.H + 7) / 8);
+  });
   if (g.tx == HZD_TX_HE) hipLaunchKernelGGL((k_gf_prep<TSRC_HE>), dim3(nblk), dim3(256), 0, s, b);
   else hipLaunchKernelGGL((k_gf_prep<TSRC_PAPER>), dim3(nblk), dim3(256), 0, s, b);
   return hipGetLastError();

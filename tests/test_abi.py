@@ -136,15 +136,15 @@ def test_server_create_rejects_bad_config(L):
 
 
 def test_tile_config_table(L):
-    assert hzd.tile_config_get(1920, 1080) == 32          # built-in default
+    assert hzd.tile_config_get(1920, 1080) == 16          # built-in default
     hzd.tile_config_set(0, 0, 16)                         # new default
     assert hzd.tile_config_get(1920, 1080) == 16
     hzd.tile_config_set(1920, 1080, 64)                   # size-specific entry wins
     assert hzd.tile_config_get(1920, 1080) == 64 and hzd.tile_config_get(640, 480) == 16
     hzd.tile_config_set(1920, 1080, None)
     hzd.tile_config_set(0, 0, None)
-    assert hzd.tile_config_get(1920, 1080) == 32
-    for bad in (0, 7, 257):
+    assert hzd.tile_config_get(1920, 1080) == 16
+    for bad in (0, 7, 12, 257, 264):
         with pytest.raises(hzd.HzdError):
             hzd.tile_config_set(640, 480, bad)
     with pytest.raises(hzd.HzdError):
