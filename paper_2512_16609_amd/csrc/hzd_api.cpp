@@ -287,6 +287,8 @@ int stage(const char* name, hipStream_t s, F&& launch) {
 // The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames.
 int run_group(const GroupKey& g, const Batch& b, hipStream_t s) {
   int rc;
+  // with profiling on, an empty event pair measures what bracketing itself costs
+  if (g_prof_on.load(std::memory_order_relaxed)) (void)stage("event_pair", s, [] { return hipSuccess; });
   if ((rc = stage("init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
   const bool he = g.tx == HZD_TX_HE;
   if ((rc = stage("dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
