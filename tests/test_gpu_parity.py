@@ -209,3 +209,35 @@ def test_graph_replay_matches_direct_launch():
                 assert np.array_equal(dst.cpu().numpy(), ref1 if rep % 2 == 0 else ref2), rep
     finally:
         hzd.graph_cache(0)
+
+
+def test_uneven_batch_each_size_matches_oracle():
+    # the 64-frame configuration's four sizes in one batch call (offline r=60, no colour balance);
+    # every frame is checked element by element against the FP64 oracle
+    shapes = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, gf_eps=1e-3, color_balance=0)
+    frames = [make_frame(w, h, 4000 + 16 * i).I for i, (w, h) in enumerate(shapes)]
+    srcs = [to_dev(I) for I in frames]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    auxs = [hzd.make_aux(h, w, J=False) for (w, h) in shapes]
+    hzd.dehaze_batch(srcs, dsts, p, auxs=auxs)
+    torch.cuda.synchronize()
+    for i, I in enumerate(frames):
+        g = {k: v.cpu().numpy() for k, v in auxs[i].items()}
+        g["out"] = dsts[i].cpu().numpy()
+        s = compare(I, p, g, label=f"batch {shapes[i]}")
+        print(shapes[i], s)
+
+
+def test_batch_larger_than_one_launch_group():
+    # 21 frames, two parameter groups, more than 16 frames in one group: several launches
+    rng = np.random.default_rng(77)
+    shapes = [(int(rng.integers(20, 90)), int(rng.integers(20, 130))) for _ in range(21)]
+    params = [P() if i % 3 else P(mode=hzd.MODE_OFFLINE, gf_radius=9, color_balance=1) for i in range(21)]
+    frames = [rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8) for (h, w) in shapes]
+    srcs = [to_dev(I) for I in frames]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    hzd.dehaze_batch(srcs, dsts, P(), per_frame_params=params)
+    torch.cuda.synchronize()
+    for i, I in enumerate(frames):
+        assert np.array_equal(dsts[i].cpu().numpy(), run_gpu(I, params[i], with_J=False)["out"]), i
