@@ -111,7 +111,7 @@ size_t frame_ws_bytes(const hzd_params& p, int W, int H) {
   size_t s = a256(sizeof(FrameState));
   s += a256((size_t)H * a16(W));                       // D
   if (needE) s += a256((size_t)H * a16(3 * W));        // E
-  s += a256((size_t)H * 16);                           // rowinfo
+  s += a256((size_t)H * sizeof(RowSel));               // per-row selection records
   if (offline) {
     s += a256((size_t)W * H * 8);                      // LP
     s += a256((size_t)W * H * 8);                      // AB
@@ -184,8 +184,8 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     d.E = ws + off;
     off += a256((size_t)H * d.E_pitch);
   }
-  d.rowinfo = reinterpret_cast<uint4*>(ws + off);
-  off += a256((size_t)H * 16);
+  d.rowsel = reinterpret_cast<RowSel*>(ws + off);
+  off += a256((size_t)H * sizeof(RowSel));
   if (offline) {
     d.LP = reinterpret_cast<uint2*>(ws + off);
     off += a256((size_t)W * H * 8);

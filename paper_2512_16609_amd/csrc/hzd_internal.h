@@ -21,19 +21,22 @@ constexpr int kMaxRadius = 64;  // guided-filter radius supported by the 256-col
 // irrelevant to the result.
 constexpr int kHistSlots = 8;
 constexpr int kCbSlots = 64;
-constexpr int kTicketGroups = 16;
 struct FrameState {
   uint32_t hist[kHistSlots][256];       // histogram of the dark channel D, per slot
-  uint32_t ticket_group[kTicketGroups]; // last-block detection in the select kernel (two levels)
-  uint32_t ticket_top;
-  uint32_t pad0[15];
-  unsigned long long gt[4];             // sum of I^c over {D > vstar}, and its pixel count
   float A[4];                           // airlight A^c (0..255 scale)
   int32_t sel[4];                       // K, vstar, cutoff, consistency flag (0 = ok)
   unsigned long long cb[kCbSlots][4];   // sum of J_gamma^c in 2^-23 fixed point, per slot
 };
-static_assert(sizeof(FrameState) % 256 == 0 || true, "");
 static_assert(sizeof(FrameState) <= 12288, "FrameState too large");
+
+// Per-row record of the airlight selection pass: the row's pixels with
+// D == vstar (ties) and D > vstar, counted and summed per channel.
+struct RowSel {
+  uint32_t ties, above, pad0, pad1;
+  unsigned long long tsum[3];
+  unsigned long long gsum[3];
+};
+static_assert(sizeof(RowSel) == 64, "RowSel layout");
 
 // Everything one frame needs on the device, passed by value in kernel arguments.
 struct FrameDev {
@@ -44,7 +47,7 @@ struct FrameDev {
   FrameState* st;
   uint8_t* D;        // dark channel, pitch D_pitch
   uint8_t* E;        // per-channel erosions (packed RGB8), pitch E_pitch
-  uint4* rowinfo;    // per row: {ties, sum R, sum G, sum B} over D == vstar
+  RowSel* rowsel;    // per row: selection counts and sums (one record per row)
   uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
   int2* AB;          // offline: guided-filter a, b in fixed point (pitch W)
   uint2* S8a;        // offline: per column and aligned 8-row chunk, sums of {L, P}
@@ -83,7 +86,7 @@ struct GroupKey {
 // Launches (hzd_kernels.hip).  Each fills b.tile0 for its own tiling.
 hipError_t launch_init(Batch b, hipStream_t s);
 hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s);
-hipError_t launch_select(Batch b, hipStream_t s);
+hipError_t launch_select(Batch b, hipStream_t s);        // two kernels: rows, then one block per frame
 hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s);
 hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s);
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s);

@@ -3,12 +3,13 @@
 //
 // Stage map (every kernel processes a batch of frames; a block finds its
 // frame from the per-launch block prefix in the kernel arguments):
-//   k_init     zero each frame's state (histogram, tickets, sums)
+//   k_init     zero each frame's state (histogram, colour-balance sums)
 //   k_dark     Eq. (2): channel minimum + patch erosion on LDS tiles with halo;
 //              writes D (u8), optionally the per-channel erosions E, and a
 //              256-bin histogram of D
-//   k_select   Eq. (3): vstar from the histogram, per-row tie counts, the tie
-//              cut in raster order by the last block, exact integer sums, A
+//   k_select_rows   Eq. (3): vstar from the histogram, per-row counts and
+//              exact sums of the ties and of the pixels above vstar
+//   k_select_final  Eq. (3): the tie cut in raster order, A from exact sums
 //   k_gf_prep  offline: per-pixel luma and coarse t (Eqs. (4)-(5)) in fixed point
 //   k_gf_ab    Eq. (6) stage 1: exact integer box sums -> a, b
 //   k_gf_q     Eq. (6) stage 2: box means of a, b -> refined t (+ fused Eq. (7))
@@ -364,59 +365,94 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
 // ---------------------------------------------------------------- k_select
 // Eq. (3) with a unique top-K set: order pixels by (D descending, raster
 // index ascending) and take the first K.
-//   vstar  = largest v with #{D >= v} >= K (from the histogram; every block
-//            recomputes it from the 256 counts)
+//   vstar  = largest v with #{D >= v} >= K (from the histogram)
 //   need   = K - #{D > vstar} >= 1 pixels with D == vstar are taken, the
 //            first `need` of them in raster order.
-// Each wave handles one row: it sums I over D > vstar (exact u64, atomically
-// merged) and counts and sums the ties D == vstar of its row.  The last block
-// of the frame (atomic ticket) scans the per-row tie counts, finds the cut
-// row and, inside it, the cutoff pixel with ballot/popcount, and forms
-// A^c = alpha * S^c / K from exact integer sums.
-__global__ __launch_bounds__(256) void k_select(Batch b) {
+// Two kernels with no atomics between them.  k_select_rows: each wave reads
+// one row of D, gathers I where D >= vstar and writes the row's record
+// (counts and exact sums of the ties D == vstar and of D > vstar).
+// k_select_final: one block per frame scans the row records, finds the row
+// holding the cut, finds the cutoff pixel inside it with a block-wide scan of
+// per-lane tie counts, and forms A^c = alpha * S^c / K from exact integer sums.
+
+// vstar and #{D > vstar} from the slotted histogram; thread t < 256 holds the
+// count of value 255 - t, so an inclusive scan gives #{D >= 255 - t}.
+template <int NW>
+__device__ __forceinline__ uint32_t hist_count(const FrameState* st) {
+  uint32_t c = 0;
+  const int tid = threadIdx.x;
+  if (NW * 64 <= 256 || tid < 256) {
+#pragma unroll
+    for (int k = 0; k < kHistSlots; ++k) c += st->hist[k][255 - tid];
+  }
+  return c;
+}
+
+// Inclusive scan over a block of NW waves; also returns the block total.
+template <int NW, typename T>
+__device__ __forceinline__ T block_scan_total(T v, T* s_tmp, T& total) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T x = wave_incl_scan(v);
+  if (lane == 63) s_tmp[w] = x;
+  __syncthreads();
+  T add = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const T t = s_tmp[i];
+    if (i < w) add += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return x + add;
+}
+
+// From the per-thread histogram counts: vstar and #{D > vstar} (block-uniform).
+template <int NW>
+__device__ __forceinline__ void find_vstar(uint32_t c, uint32_t K, uint32_t* s_tmp, int* s_out,
+                                           uint32_t& vstar, uint32_t& cnt_gt) {
+  uint32_t tot;
+  const uint32_t incl = block_scan_total<NW>(c, s_tmp, tot);
+  if (incl >= K && incl - c < K) {  // exactly one thread: counts are >= 0 and K <= W*H
+    s_out[0] = 255 - (int)threadIdx.x;
+    s_out[1] = (int)(incl - c);
+  }
+  __syncthreads();
+  vstar = (uint32_t)s_out[0];
+  cnt_gt = (uint32_t)s_out[1];
+}
+
+__global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   __shared__ uint32_t s_u32[4];
-  __shared__ unsigned long long s_u64[4];
-  __shared__ int s_misc[4];
-  __shared__ unsigned long long s_sum[3];
+  __shared__ int s_misc[2];
 
   const int blk = blockIdx.x;
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
   const int tile = blk - b.tile0[f];
-  const int nblk = b.tile0[f + 1] - b.tile0[f];
-  const int W = fd.W, H = fd.H, K = fd.K;
-  FrameState* st = fd.st;
+  const int W = fd.W, H = fd.H;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
 
-  // vstar and #{D > vstar}: thread t holds the count of value 255 - t
-  uint32_t c = 0;
-#pragma unroll
-  for (int k = 0; k < kHistSlots; ++k) c += st->hist[k][255 - tid];
-  const uint32_t incl = block_incl_scan<uint32_t>(c, s_u32);
-  if (incl >= (uint32_t)K && incl - c < (uint32_t)K) {
-    s_misc[0] = 255 - tid;
-    s_misc[1] = (int)(incl - c);
-  }
-  __syncthreads();
-  const uint32_t vstar = (uint32_t)s_misc[0];
-  const uint32_t cnt_gt = (uint32_t)s_misc[1];
+  uint32_t vstar, cnt_gt;
+  find_vstar<4>(hist_count<4>(fd.st), (uint32_t)fd.K, s_u32, s_misc, vstar, cnt_gt);
+  (void)cnt_gt;
 
   // one row per wave; each lane reads 16 consecutive bytes of D per step
   const int y = tile * 4 + wv;
-  if (y < H) {
-    unsigned long long gR = 0, gG = 0, gB = 0, gN = 0;
-    uint32_t tN = 0, tR = 0, tG = 0, tB = 0;
-    const uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch;
-    const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
-    for (int seg = 0; seg < W; seg += 1024 * kSelVec) {
-      uint4 dvs[kSelVec];  // all of this lane's D vectors of the segment, loaded up front
+  if (y >= H) return;
+  unsigned long long gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;
+  uint32_t gN = 0, tN = 0;
+  const uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch;
+  const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
+  for (int seg = 0; seg < W; seg += 1024 * kSelVec) {
+    uint4 dvs[kSelVec];  // all of this lane's D vectors of the segment, loaded up front
 #pragma unroll
-      for (int q = 0; q < kSelVec; ++q) {
-        const int bq = seg + 1024 * q + 16 * lane;
-        dvs[q] = (bq < W) ? *reinterpret_cast<const uint4*>(Drow + bq) : make_uint4(0u, 0u, 0u, 0u);
-      }
+    for (int q = 0; q < kSelVec; ++q) {
+      const int bq = seg + 1024 * q + 16 * lane;
+      dvs[q] = (bq < W) ? *reinterpret_cast<const uint4*>(Drow + bq) : make_uint4(0u, 0u, 0u, 0u);
+    }
 #pragma unroll
-      for (int q = 0; q < kSelVec; ++q) {
+    for (int q = 0; q < kSelVec; ++q) {
       const int base = seg + 1024 * q + 16 * lane;
       if (base >= W) continue;
       const uint4 dv = dvs[q];  // rows are padded to 16 bytes
@@ -433,9 +469,9 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
       uint32_t iw[12];
       const bool vec = fd.aligned && nx == 16;
       if (vec) {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(Irow + 3 * base);
+        const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow + 3 * base);
 #pragma unroll
-        for (int j = 0; j < 12; ++j) iw[j] = q[j];
+        for (int j = 0; j < 12; ++j) iw[j] = q4[j];
       }
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
@@ -456,153 +492,189 @@ __global__ __launch_bounds__(256) void k_select(Batch b) {
           tR += r; tG += g; tB += bl; tN += 1;
         }
       }
-      }
-    }
-    tN = wave_sum(tN); tR = wave_sum(tR); tG = wave_sum(tG); tB = wave_sum(tB);
-    gN = wave_sum(gN);
-    if (gN) { gR = wave_sum(gR); gG = wave_sum(gG); gB = wave_sum(gB); }
-    if (lane == 0) {
-      fd.rowinfo[y] = make_uint4(tN, tR, tG, tB);
-      if (gN) {
-        atomicAdd(&st->gt[0], gR);
-        atomicAdd(&st->gt[1], gG);
-        atomicAdd(&st->gt[2], gB);
-        atomicAdd(&st->gt[3], gN);
-      }
     }
   }
+  tN = wave_sum(tN);
+  gN = wave_sum(gN);
+  if (tN) { tR = wave_sum(tR); tG = wave_sum(tG); tB = wave_sum(tB); }
+  if (gN) { gR = wave_sum(gR); gG = wave_sum(gG); gB = wave_sum(gB); }
+  if (lane == 0) {
+    RowSel r;
+    r.ties = tN; r.above = gN; r.pad0 = 0; r.pad1 = 0;
+    r.tsum[0] = tR; r.tsum[1] = tG; r.tsum[2] = tB;
+    r.gsum[0] = gR; r.gsum[1] = gG; r.gsum[2] = gB;
+    fd.rowsel[y] = r;
+  }
+}
 
-  // last block of this frame finishes the selection
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    // two-level ticket: the last block of each group signals the top counter
-    const int grp = tile % kTicketGroups;
-    const uint32_t gsize = (uint32_t)((nblk - grp + kTicketGroups - 1) / kTicketGroups);
-    int last = 0;
-    if (atomicAdd(&st->ticket_group[grp], 1u) == gsize - 1u) {
-      __threadfence();
-      last = atomicAdd(&st->ticket_top, 1u) == (uint32_t)(min(kTicketGroups, nblk) - 1);
-    }
-    s_misc[2] = last;
-  }
-  __syncthreads();
-  if (!s_misc[2]) return;
-  __threadfence();
+constexpr int kFinT = 512;             // threads of the final selection block
+constexpr int kFinW = kFinT / 64;
+constexpr int kFinRows = 4;            // row records loaded per round trip per thread
 
-  const uint32_t need = (uint32_t)K - cnt_gt;  // >= 1
-  if (tid == 0) {
-    s_misc[0] = -1;
-    s_misc[1] = 0;
-  }
-  __syncthreads();
-  const int per = (H + 255) / 256;
+__global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
+  __shared__ uint32_t s_u32[kFinW];
+  __shared__ unsigned long long s_red[kFinW][5];
+  __shared__ int s_misc[4];
+
+  const FrameDev& fd = b.f[blockIdx.x];  // one block per frame
+  FrameState* st = fd.st;
+  const int W = fd.W, H = fd.H;
+  const uint32_t K = (uint32_t)fd.K;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+
+  // this thread's rows [ra, rb): counts and sums of the records, loaded kFinRows at a time
+  const int per = (H + kFinT - 1) / kFinT;
   const int ra = min(H, tid * per), rb = min(H, ra + per);
-  uint32_t mine = 0;
-  for (int yy = ra; yy < rb; ++yy) mine += fd.rowinfo[yy].x;
-  const uint32_t rincl = block_incl_scan<uint32_t>(mine, s_u32);
-  const uint32_t rexcl = rincl - mine;
+  const uint32_t hc = hist_count<kFinW>(st);
+  uint32_t ties = 0, above = 0;
+  unsigned long long ts[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
+  for (int y0 = ra; y0 < rb; y0 += kFinRows) {
+    RowSel r[kFinRows];
+#pragma unroll
+    for (int u = 0; u < kFinRows; ++u)
+      if (y0 + u < rb) r[u] = fd.rowsel[y0 + u];
+#pragma unroll
+    for (int u = 0; u < kFinRows; ++u) {
+      if (y0 + u >= rb) continue;
+      ties += r[u].ties;
+      above += r[u].above;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { ts[c] += r[u].tsum[c]; gs[c] += r[u].gsum[c]; }
+    }
+  }
+  uint32_t vstar, cnt_gt;
+  find_vstar<kFinW>(hc, K, s_u32, s_misc, vstar, cnt_gt);
+  const uint32_t need = K - cnt_gt;  // >= 1
+
+  // the row holding the need-th tie in raster order
+  if (tid == 0) {
+    s_misc[2] = -1;
+    s_misc[3] = 0;
+  }
+  uint32_t ttot;
+  const uint32_t rincl = block_scan_total<kFinW>(ties, s_u32, ttot);
+  const uint32_t rexcl = rincl - ties;
+  unsigned long long part[3] = {0, 0, 0};  // this thread's tie sums over rows before the cut row
   if (rexcl < need && need <= rincl) {
     uint32_t cum = rexcl;
     for (int yy = ra; yy < rb; ++yy) {
-      const uint32_t tc = fd.rowinfo[yy].x;
-      if (cum + tc >= need) {
-        s_misc[0] = yy;
-        s_misc[1] = (int)cum;
+      const RowSel r = fd.rowsel[yy];
+      if (cum + r.ties >= need) {
+        s_misc[2] = yy;
+        s_misc[3] = (int)cum;
         break;
       }
-      cum += tc;
+      cum += r.ties;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) part[c] += r.tsum[c];
     }
   }
   __syncthreads();
-  const int rstar = s_misc[0];
-  const uint32_t before = (uint32_t)s_misc[1];
+  const int rstar = s_misc[2];
+  const uint32_t before = (uint32_t)s_misc[3];
   if (rstar < 0) {  // inconsistent counts: report instead of reading a row that is not there
     if (tid == 0) {
-      st->sel[0] = K;
+      st->sel[0] = (int32_t)K;
       st->sel[1] = (int32_t)vstar;
       st->sel[2] = -1;
       st->sel[3] = 2;
     }
     return;
   }
-
-  // ties in rows above the cut row are all in the set
-  unsigned long long sR = 0, sG = 0, sB = 0;
-  for (int yy = ra; yy < min(rb, rstar); ++yy) {
-    const uint4 ri = fd.rowinfo[yy];
-    sR += ri.y; sG += ri.z; sB += ri.w;
-  }
-  sR = block_sum(sR, s_u64);
-  sG = block_sum(sG, s_u64);
-  sB = block_sum(sB, s_u64);
-
-  // the cut row: the first (need - before) ties in raster order.  Lane l
-  // owns bytes [16 l, 16 l + 16) of each 1024-pixel segment, so lane order is
-  // raster order inside a segment; an exclusive scan of the per-lane tie
-  // counts tells each lane how many of its ties are taken.
-  if (wv == 0) {
-    const uint32_t k = need - before;
-    const uint8_t* Drow = fd.D + (int64_t)rstar * fd.D_pitch;
-    const uint8_t* Irow = fd.src + (int64_t)rstar * fd.src_pitch;
-    uint32_t run = 0;
-    unsigned long long cR = 0, cG = 0, cB = 0;
-    int cut_x = -1;
-    for (int base = 0; base < W && run < k; base += 1024) {
-      const int x0 = base + 16 * lane;
-      uint32_t dw[4] = {0u, 0u, 0u, 0u};
-      if (x0 < W) {
-        const uint4 dv = *reinterpret_cast<const uint4*>(Drow + x0);
-        dw[0] = dv.x; dw[1] = dv.y; dw[2] = dv.z; dw[3] = dv.w;
-      }
-      uint32_t mask = 0;
+  if (rb <= rstar) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const uint32_t d = (dw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        if (x0 + j < W && d == vstar) mask |= 1u << j;
+    for (int c = 0; c < 3; ++c) part[c] = ts[c];
+  }
+
+  // the cut row: the first (need - before) ties in raster order.  Thread t
+  // owns bytes [16 t, 16 t + 16) of each kFinT*16-pixel segment, so thread
+  // order is raster order inside a segment; an exclusive block scan of the
+  // per-thread tie counts says how many of its ties each thread takes.
+  const uint32_t k = need - before;
+  const uint8_t* Drow = fd.D + (int64_t)rstar * fd.D_pitch;
+  const uint8_t* Irow = fd.src + (int64_t)rstar * fd.src_pitch;
+  uint32_t run = 0;  // ties in earlier segments (block-uniform)
+  unsigned long long cs[3] = {0, 0, 0};
+  int cut_x = -1;
+  for (int seg = 0; seg < W && run < k; seg += 16 * kFinT) {
+    const int x0 = seg + 16 * tid;
+    uint32_t dw[4] = {0u, 0u, 0u, 0u};
+    if (x0 < W) {
+      const uint4 dv = *reinterpret_cast<const uint4*>(Drow + x0);  // rows are padded to 16 bytes
+      dw[0] = dv.x; dw[1] = dv.y; dw[2] = dv.z; dw[3] = dv.w;
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t d = (dw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+      if (x0 + j < W && d == vstar) mask |= 1u << j;
+    }
+    const uint32_t cnt = (uint32_t)__popc(mask);
+    uint32_t seg_total;
+    const uint32_t ex = block_scan_total<kFinW>(cnt, s_u32, seg_total) - cnt;
+    const uint32_t avail = (run + ex < k) ? min(cnt, k - run - ex) : 0u;
+    if (avail) {
+      uint32_t iw[12];
+      const bool vec = fd.aligned && x0 + 16 <= W;
+      if (vec) {
+        const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow + 3 * x0);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) iw[j] = q4[j];
       }
-      const uint32_t cnt = (uint32_t)__popc(mask);
-      const uint32_t ex = wave_incl_scan(cnt) - cnt;   // ties before this lane in the segment
-      const uint32_t seg_total = __shfl(ex + cnt, 63, 64);
-      // ties this lane takes: those with (run + ex + rank) < k
-      const uint32_t avail = (run + ex < k) ? min(cnt, k - run - ex) : 0u;
       uint32_t m = mask;
       for (uint32_t i = 0; i < avail; ++i) {
         const int j = __ffs(m) - 1;
         m &= m - 1;
-        const int x = x0 + j;
-        cR += Irow[3 * x]; cG += Irow[3 * x + 1]; cB += Irow[3 * x + 2];
-        if (run + ex + i + 1 == k) cut_x = x;
-      }
-      run += seg_total;
-    }
-    cR = wave_sum(cR); cG = wave_sum(cG); cB = wave_sum(cB);
-    int cx = cut_x;
+        uint32_t px[3];
+        if (vec) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cx = max(cx, __shfl_xor(cx, o, 64));
-    if (lane == 0) {
-      s_sum[0] = cR; s_sum[1] = cG; s_sum[2] = cB;
-      s_misc[3] = cx;
+          for (int c = 0; c < 3; ++c) {
+            const int byte = 3 * j + c;
+            px[c] = (iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) px[c] = Irow[3 * (x0 + j) + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cs[c] += px[c];
+        if (run + ex + i + 1 == k) cut_x = x0 + j;
+      }
     }
+    run += seg_total;
+  }
+
+  // S^c = sum over D > vstar (all rows) + ties of rows before the cut row + the cut row's share
+  unsigned long long v[5];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = gs[c] + part[c] + cs[c];
+  v[3] = above;
+  v[4] = (unsigned long long)(cut_x + 1);  // 0 = none; at most one thread holds the cut
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const unsigned long long x = wave_sum(v[i]);
+    if (lane == 0) s_red[wv][i] = x;
   }
   __syncthreads();
   if (tid == 0) {
-    const unsigned long long S[3] = {st->gt[0] + sR + s_sum[0], st->gt[1] + sG + s_sum[1],
-                                     st->gt[2] + sB + s_sum[2]};
-    const int32_t cutoff = rstar * W + s_misc[3];
+    unsigned long long S[5] = {0, 0, 0, 0, 0};
+    for (int w = 0; w < kFinW; ++w)
+      for (int i = 0; i < 5; ++i) S[i] += s_red[w][i];
+    const int cx = (int)S[4] - 1;
+    const int32_t cutoff = rstar * W + cx;
     const double a = (double)fd.alpha;
     for (int ch = 0; ch < 3; ++ch) {
       const float A = (float)(a * (double)S[ch] / (double)K);
       st->A[ch] = A;
       if (fd.A_out) fd.A_out[ch] = A;
     }
-    st->sel[0] = K;
+    st->sel[0] = (int32_t)K;
     st->sel[1] = (int32_t)vstar;
     st->sel[2] = cutoff;
-    // consistency: the atomically merged count over D > vstar must equal the histogram's
-    st->sel[3] = (st->gt[3] == (unsigned long long)cnt_gt && s_misc[3] >= 0) ? 0 : 1;
+    // consistency: the rows' count over D > vstar must equal the histogram's
+    st->sel[3] = (S[3] == (unsigned long long)cnt_gt && cx >= 0) ? 0 : 1;
     if (fd.sel_out) {
-      fd.sel_out[0] = K;
+      fd.sel_out[0] = (int32_t)K;
       fd.sel_out[1] = (int32_t)vstar;
       fd.sel_out[2] = cutoff;
     }
@@ -1303,7 +1375,10 @@ hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s) 
 
 hipError_t launch_select(Batch b, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return (f.H + 3) / 4; });
-  hipLaunchKernelGGL(k_select, dim3(nblk), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_select_rows, dim3(nblk), dim3(256), 0, s, b);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_select_final, dim3(b.n), dim3(kFinT), 0, s, b);
   return hipGetLastError();
 }
 
