@@ -137,7 +137,7 @@ void tune_load_locked() {
   if (!fp) return;
   int w, h, rows;
   while (std::fscanf(fp, "%d %d %d", &w, &h, &rows) == 3) {
-    if (w >= 0 && h >= 0 && rows >= kGfRowsMin && rows <= 256 && rows % 8 == 0) g_tune[{w, h}] = hzd_tile_config{rows};
+    if (w >= 0 && h >= 0 && rows >= kGfRowsMin && rows <= kGfRowsMax && rows % 8 == 0) g_tune[{w, h}] = hzd_tile_config{rows};
   }
   std::fclose(fp);
 }
@@ -505,8 +505,8 @@ int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_
 
 int hzd_tile_config_set(int32_t width, int32_t height, const hzd_tile_config* cfg) {
   if (width < 0 || height < 0) return fail(HZD_E_INVAL, "size %dx%d", width, height);
-  if (cfg && (cfg->gf_rows < kGfRowsMin || cfg->gf_rows > 256 || cfg->gf_rows % 8 != 0))
-    return fail(HZD_E_INVAL, "gf_rows %d not a multiple of 8 in %d..256", cfg->gf_rows, kGfRowsMin);
+  if (cfg && (cfg->gf_rows < kGfRowsMin || cfg->gf_rows > kGfRowsMax || cfg->gf_rows % 8 != 0))
+    return fail(HZD_E_INVAL, "gf_rows %d not a multiple of 8 in %d..%d", cfg->gf_rows, kGfRowsMin, kGfRowsMax);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   if (cfg) g_tune[{width, height}] = *cfg;

@@ -99,6 +99,7 @@ constexpr int kReconPx = 1024;   // pixels of one row per recon block
 constexpr int kGfCols = 256;     // loaded columns per guided-filter strip block
 constexpr int kGfRowsDefault = 16;  // output rows per guided-filter block unless tuned (a multiple of 8)
 constexpr int kGfRowsMin = 8;
+constexpr int kGfRowsMax = 256;    // one per-row table entry per thread of a 256-thread block
 inline int recon_blocks(int W, int H) { return H * ((W + kReconPx - 1) / kReconPx); }
 inline int gf_strip(int r) { return kGfCols - 2 * r; }
 inline int gf_blocks(int W, int H, int r, int rows) {

@@ -820,6 +820,14 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return fma(r, e, r);
 }
 
+// 64-bit integers to double with one rounding: hi * 2^32 + lo in one FMA.
+__device__ __forceinline__ double u64_to_f64(unsigned long long x) {
+  return fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+}
+__device__ __forceinline__ double i64_to_f64(long long x) {
+  return fma((double)(int32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+}
+
 // Geometry of one guided-filter strip block: 256 loaded columns (one per
 // thread) starting at x0 - r, output columns [x0, x0 + 256 - 2r), output rows
 // [y0, y1) with y1 - y0 = fd.gf_rows (the tile height is a tuning knob; the
@@ -848,6 +856,83 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
 }
 
 constexpr int kRpi = 4;          // rows per barrier phase in the guided-filter strip kernels
+static_assert(kGfRowsMax <= 256, "per-row table filled by one pass of the block's threads");
+
+// Per output row of the block: the clipped window height ch and 1/ch (one
+// table per block, filled before the first barrier of the row loop).
+__device__ __forceinline__ void gf_row_table(const GfTile& g, double2* s_rows) {
+  const int i = threadIdx.x;
+  if (i < g.y1 - g.y0) {
+    const int y = g.y0 + i;
+    const int ch = min(y + g.r, g.H - 1) - max(y - g.r, 0) + 1;
+    s_rows[i] = make_double2((double)ch, rcp_nr((double)ch));
+  }
+}
+static_assert(kChunk % kRpi == 0, "phases must not straddle 8-row chunks");
+
+// One step of an inclusive wave scan on NR 64-bit values at once: v += the
+// DPP-routed v, as a VOP2 DPP add on the low halves and a DPP add-with-carry
+// on the high halves (two VALU ops per value instead of two DPP moves and a
+// 64-bit add).  Rows of a step are interleaved, so every DPP read is at least
+// two VALU ops after the write of its source; s_nop 1 covers values written
+// just before the block.  Lanes whose source is outside the row read 0
+// (bound_ctrl); rows masked off by row_mask keep their value.
+#define HZD_DPP64_2(mod)                                                                   \
+  asm("s_nop 1\n\t"                                                                        \
+      "v_add_co_u32_dpp %0, vcc, %0, %0 " mod "\n\t"                                       \
+      "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " mod "\n\t"                                 \
+      "v_add_co_u32_dpp %2, vcc, %2, %2 " mod "\n\t"                                       \
+      "v_addc_co_u32_dpp %3, vcc, %3, %3, vcc " mod                                       \
+      : "+v"(lo[0]), "+v"(hi[0]), "+v"(lo[1]), "+v"(hi[1])                                \
+      :                                                                                  \
+      : "vcc")
+#define HZD_DPP64_4(mod)                                                                   \
+  asm("s_nop 1\n\t"                                                                        \
+      "v_add_co_u32_dpp %0, vcc, %0, %0 " mod "\n\t"                                       \
+      "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " mod "\n\t"                                 \
+      "v_add_co_u32_dpp %2, vcc, %2, %2 " mod "\n\t"                                       \
+      "v_addc_co_u32_dpp %3, vcc, %3, %3, vcc " mod "\n\t"                                 \
+      "v_add_co_u32_dpp %4, vcc, %4, %4 " mod "\n\t"                                       \
+      "v_addc_co_u32_dpp %5, vcc, %5, %5, vcc " mod "\n\t"                                 \
+      "v_add_co_u32_dpp %6, vcc, %6, %6 " mod "\n\t"                                       \
+      "v_addc_co_u32_dpp %7, vcc, %7, %7, vcc " mod                                       \
+      : "+v"(lo[0]), "+v"(hi[0]), "+v"(lo[1]), "+v"(hi[1]), "+v"(lo[2]), "+v"(hi[2]),     \
+        "+v"(lo[3]), "+v"(hi[3])                                                          \
+      :                                                                                  \
+      : "vcc")
+
+// Inclusive scans over the 64 lanes of NR (2 or 4) independent 64-bit values
+// (two's complement, so signed and unsigned alike), the same lane pattern as
+// wave_incl_scan.
+template <int NR>
+__device__ __forceinline__ void wave_incl_scan64(unsigned long long (&v)[NR]) {
+  static_assert(NR == 2 || NR == 4, "2 or 4 rows per scan");
+  uint32_t lo[NR], hi[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    lo[j] = (uint32_t)v[j];
+    hi[j] = (uint32_t)(v[j] >> 32);
+  }
+  if constexpr (NR == 2) {
+    HZD_DPP64_2("row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_2("row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_2("row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_2("row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_2("row_bcast:15 row_mask:0xa bank_mask:0xf");
+    HZD_DPP64_2("row_bcast:31 row_mask:0xc bank_mask:0xf");
+  } else {
+    HZD_DPP64_4("row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_4("row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_4("row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_4("row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    HZD_DPP64_4("row_bcast:15 row_mask:0xa bank_mask:0xf");
+    HZD_DPP64_4("row_bcast:31 row_mask:0xc bank_mask:0xf");
+  }
+#pragma unroll
+  for (int j = 0; j < NR; ++j) v[j] = ((unsigned long long)hi[j] << 32) | lo[j];
+}
+#undef HZD_DPP64_2
+#undef HZD_DPP64_4
 
 // Prefix sums over the 256 columns of one LDS row, 4 columns per lane (one
 // wave per row of the array).
@@ -855,26 +940,28 @@ constexpr int kRpi = 4;          // rows per barrier phase in the guided-filter 
 // whose DPP steps interleave.
 template <typename T, int NR>
 __device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
+  static_assert(sizeof(T) == 8, "64-bit sums");
   const int lane = threadIdx.x & 63;
   T v[NR][4];
 #pragma unroll
   for (int j = 0; j < NR; ++j)
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[j][k] = base[j * stride + 4 * lane + k];
-  T ex[NR];
+  unsigned long long ex[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     v[j][1] += v[j][0];
     v[j][2] += v[j][1];
     v[j][3] += v[j][2];
-    ex[j] = v[j][3];
+    ex[j] = (unsigned long long)v[j][3];
   }
+  wave_incl_scan64<NR>(ex);
 #pragma unroll
-  for (int j = 0; j < NR; ++j) ex[j] = wave_incl_scan(ex[j]) - v[j][3];
+  for (int j = 0; j < NR; ++j) {
+    const T e = (T)(ex[j] - (unsigned long long)v[j][3]);
 #pragma unroll
-  for (int j = 0; j < NR; ++j)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) base[j * stride + 4 * lane + k] = v[j][k] + ex[j];
+    for (int k = 0; k < 4; ++k) base[j * stride + 4 * lane + k] = v[j][k] + e;
+  }
 }
 
 template <typename T>
@@ -902,6 +989,7 @@ __device__ __forceinline__ void wave_prefix256(T* row) {
 // and b leave as int32 fixed point with the frame's scale.
 __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   __shared__ unsigned long long s_q[kRpi][4][kGfCols];
+  __shared__ double2 s_rows[kGfRowsMax];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -909,6 +997,7 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   const int W = g.W, H = g.H, r = g.r;
   const int tid = threadIdx.x, wv = tid >> 6;
   const uint2* col = fd.LP + (g.colin ? g.xl : 0);
+  gf_row_table(g, s_rows);
 
   unsigned long long sL = 0, sLL = 0, sP = 0, sLP = 0;
   auto add = [&](uint2 v) {
@@ -925,10 +1014,10 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
       uint2 hv[kMaxHead], tv[kChunk - 1];
 #pragma unroll
       for (int i = 0; i < kMaxHead; ++i)
-        hv[i] = (w.ya + i < w.head_end) ? col[(int64_t)(w.ya + i) * W] : make_uint2(0u, 0u);
+        hv[i] = (w.ya + i < w.head_end) ? col[(w.ya + i) * W] : make_uint2(0u, 0u);
 #pragma unroll
       for (int i = 0; i < kChunk - 1; ++i)
-        tv[i] = (w.tail_beg + i <= w.yb) ? col[(int64_t)(w.tail_beg + i) * W] : make_uint2(0u, 0u);
+        tv[i] = (w.tail_beg + i <= w.yb) ? col[(w.tail_beg + i) * W] : make_uint2(0u, 0u);
 #pragma unroll
       for (int i = 0; i < kMaxHead; ++i) add(hv[i]);
 #pragma unroll
@@ -942,8 +1031,8 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
         ca[i] = make_uint2(0u, 0u);
         cb[i] = make_ulonglong2(0ull, 0ull);
         if (c + i < w.nch) {
-          ca[i] = fd.S8a[(int64_t)(w.c0 + c + i) * W + g.xl];
-          cb[i] = fd.S8b[(int64_t)(w.c0 + c + i) * W + g.xl];
+          ca[i] = fd.S8a[(w.c0 + c + i) * W + g.xl];
+          cb[i] = fd.S8b[(w.c0 + c + i) * W + g.xl];
         }
       }
 #pragma unroll
@@ -960,8 +1049,8 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     vin = make_uint2(0u, 0u);
     vout = make_uint2(0u, 0u);
     if (g.colin && yn > g.y0 && yn < g.y1) {
-      if (yn + r < H) vin = col[(int64_t)(yn + r) * W];
-      if (yn - r - 1 >= 0) vout = col[(int64_t)(yn - r - 1) * W];
+      if (yn + r < H) vin = col[(yn + r) * W];  // offsets < W*H < 2^31
+      if (yn - r - 1 >= 0) vout = col[(yn - r - 1) * W];
     }
   };
   uint2 pin[kRpi], pout[kRpi];
@@ -972,9 +1061,16 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   const bool outcol = tid < g.SW && x < W;
   const int lo = max(x - r, 0), hi = min(x + r, W - 1);
   const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
-  const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
+  // Eq. (6) from the exact box sums S over n = cw * ch pixels (L = G / kG, P = t / kP):
+  //   var = kG^2 / n (S_LL - S_L^2 / n),  cov = kG kP / n (S_LP - S_L S_P / n)
+  //   a = cov / (var + eps) = (kP / kG) C / (V + n eps / kG^2)   with V, C the brackets
+  //   b = mean(t) - a mean(G) = (kP / n) (S_P - (a kG / kP) S_L)
+  const double cw = (double)(hi - lo + 1);
+  const double icw = outcol ? rcp_nr(cw) : 0.0;
   const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
-  const double eps = (double)fd.eps, s = (double)fd.ab_scale, lim = 2147483647.0;
+  const double eps_n = (double)fd.eps / (kG * kG);
+  const double s = (double)fd.ab_scale, lim = 2147483647.0;
+  const double sa_k = s * kP / kG, sb_k = s * kP;
   long long ca_ = 0, cb_ = 0;
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
 #pragma unroll
@@ -991,34 +1087,55 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     wave_prefix256_rows<unsigned long long, kRpi>(&s_q[0][wv][0], 4 * kGfCols);
     __syncthreads();
     if (outcol) {
+      // a, b of row u (output row y) in fixed point
+      auto row_ab = [&](int u, int y) -> int2 {
+        // box sums as differences of two prefixes; S_L < 2^32, so 32-bit wrap-around is exact
+        const uint32_t sl = (uint32_t)s_q[u][0][chi] - (clo > 0 ? (uint32_t)s_q[u][0][clo - 1] : 0u);
+        const double SL = (double)sl;
+        const double SLL = u64_to_f64(s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ull));
+        const double SP = u64_to_f64(s_q[u][2][chi] - (clo > 0 ? s_q[u][2][clo - 1] : 0ull));
+        const double SLP = u64_to_f64(s_q[u][3][chi] - (clo > 0 ? s_q[u][3][clo - 1] : 0ull));
+        const double2 rw = s_rows[y - g.y0];  // {ch, 1 / ch}
+        const double inv_n = icw * rw.y;
+        const double t1 = SL * inv_n;
+        const double V = fma(-t1, SL, SLL);
+        const double C = fma(-t1, SP, SLP);
+        const double a2 = C * rcp_nr(fma(cw * rw.x, eps_n, V));  // a kG / kP
+        const double ia = fmin(fmax(__builtin_rint(a2 * sa_k), -lim), lim);
+        const double ib = fmin(fmax(__builtin_rint(fma(-a2, SL, SP) * (inv_n * sb_k)), -lim), lim);
+        return make_int2((int)ia, (int)ib);
+      };
+      // the column's sums of a, b over its aligned 8-row chunk (for stage 2's window)
+      auto chunk_end = [&](int y) {
+        if ((y & (kChunk - 1)) == kChunk - 1 || y == H - 1) {
+          fd.S8ab[(y / kChunk) * W + x] = make_longlong2(ca_, cb_);
+          ca_ = 0;
+          cb_ = 0;
+        }
+      };
+      if (yb + kRpi <= g.y1) {
+        // a whole phase: no per-row branches, so the kRpi FP64 chains interleave.
+        // Phases start at multiples of kRpi (a divisor of kChunk), so only the
+        // phase's last row can end a chunk or the frame.
+        int2 v[kRpi];
 #pragma unroll
-      for (int u = 0; u < kRpi; ++u) {
-        const int y = yb + u;
-        if (y < g.y1) {
-          double q[4];
+        for (int u = 0; u < kRpi; ++u) v[u] = row_ab(u, yb + u);
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            q[k] = (double)(s_q[u][k][chi] - (clo > 0 ? s_q[u][k][clo - 1] : 0ull));
-          const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
-          const double in = icw * rcp_nr((double)ch);
-          const double mG = q[0] * (in * kG);
-          const double mGG = q[1] * (in * (kG * kG));
-          const double mP = q[2] * (in * kP);
-          const double mGP = q[3] * (in * (kG * kP));
-          const double var = mGG - mG * mG;
-          const double cov = mGP - mG * mP;
-          const double a = cov * rcp_nr(var + eps);
-          const double bb = mP - a * mG;
-          const double ia = fmin(fmax(__builtin_rint(a * s), -lim), lim);
-          const double ib = fmin(fmax(__builtin_rint(bb * s), -lim), lim);
-          fd.AB[(int64_t)y * W + x] = make_int2((int)ia, (int)ib);
-          // the column's sums of a, b over its aligned 8-row chunk (for stage 2's window)
-          ca_ += (long long)ia;
-          cb_ += (long long)ib;
-          if ((y & (kChunk - 1)) == kChunk - 1 || y == H - 1) {
-            fd.S8ab[(int64_t)(y / kChunk) * W + x] = make_longlong2(ca_, cb_);
-            ca_ = 0;
-            cb_ = 0;
+        for (int u = 0; u < kRpi; ++u) {
+          fd.AB[(yb + u) * W + x] = v[u];
+          ca_ += v[u].x;
+          cb_ += v[u].y;
+        }
+        chunk_end(yb + kRpi - 1);
+      } else {
+        for (int u = 0; u < kRpi; ++u) {
+          const int y = yb + u;
+          if (y < g.y1) {
+            const int2 v = row_ab(u, y);
+            fd.AB[y * W + x] = v;
+            ca_ += v.x;
+            cb_ += v.y;
+            chunk_end(y);
           }
         }
       }
@@ -1072,10 +1189,12 @@ __device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3], unsigne
 // Eq. (6), stage 2: box means of a and b (exact i64 sums of the fixed-point
 // values, same strip scheme, kRpi rows per barrier phase), q = mean(a) G +
 // mean(b), clamped to [t0, 1].  PHASE 0: fuse Eqs. (7)-(8) and write the
-// output.  PHASE 1: store the refined t and the colour-balance sums.
-template <int PHASE, bool FP16>
+// output.  PHASE 1: store the refined t and the colour-balance sums.  AUX:
+// some frame of the launch asks for its t or J maps.
+template <int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   __shared__ long long s_q[kRpi][2][kGfCols];
+  __shared__ double2 s_rows[kGfRowsMax];
   __shared__ unsigned long long s_red[4];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
@@ -1085,6 +1204,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   const int W = g.W, H = g.H, r = g.r;
   const int tid = threadIdx.x, wv = tid >> 6;
   const int2* col = fd.AB + (g.colin ? g.xl : 0);
+  gf_row_table(g, s_rows);
   const ReconConsts rc = recon_consts(fd);
 
   long long sa = 0, sb = 0;
@@ -1094,10 +1214,10 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
       int2 hv[kMaxHead], tv[kChunk - 1];
 #pragma unroll
       for (int i = 0; i < kMaxHead; ++i)
-        hv[i] = (w.ya + i < w.head_end) ? col[(int64_t)(w.ya + i) * W] : make_int2(0, 0);
+        hv[i] = (w.ya + i < w.head_end) ? col[(w.ya + i) * W] : make_int2(0, 0);
 #pragma unroll
       for (int i = 0; i < kChunk - 1; ++i)
-        tv[i] = (w.tail_beg + i <= w.yb) ? col[(int64_t)(w.tail_beg + i) * W] : make_int2(0, 0);
+        tv[i] = (w.tail_beg + i <= w.yb) ? col[(w.tail_beg + i) * W] : make_int2(0, 0);
 #pragma unroll
       for (int i = 0; i < kMaxHead; ++i) {
         sa += hv[i].x;
@@ -1113,7 +1233,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
       longlong2 cs[kChunkBatch];
 #pragma unroll
       for (int i = 0; i < kChunkBatch; ++i)
-        cs[i] = (c + i < w.nch) ? fd.S8ab[(int64_t)(w.c0 + c + i) * W + g.xl] : make_longlong2(0ll, 0ll);
+        cs[i] = (c + i < w.nch) ? fd.S8ab[(w.c0 + c + i) * W + g.xl] : make_longlong2(0ll, 0ll);
 #pragma unroll
       for (int i = 0; i < kChunkBatch; ++i) {
         sa += cs[i].x;
@@ -1125,8 +1245,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     vin = make_int2(0, 0);
     vout = make_int2(0, 0);
     if (g.colin && yn > g.y0 && yn < g.y1) {
-      if (yn + r < H) vin = col[(int64_t)(yn + r) * W];
-      if (yn - r - 1 >= 0) vout = col[(int64_t)(yn - r - 1) * W];
+      if (yn + r < H) vin = col[(yn + r) * W];  // offsets < W*H < 2^31
+      if (yn - r - 1 >= 0) vout = col[(yn - r - 1) * W];
     }
   };
   const int x = g.x0 + tid;
@@ -1136,7 +1256,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     L = 0u;
     rgb = 0u;
     if (outcol && yn < g.y1) {
-      L = fd.LP[(int64_t)yn * W + x].x;
+      L = fd.LP[yn * W + x].x;
       const uint8_t* p = fd.src + (int64_t)yn * fd.src_pitch + 3 * x;
       rgb = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
     }
@@ -1151,8 +1271,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 
   const int lo = max(x - r, 0), hi = min(x + r, W - 1);
   const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
-  const double icw = outcol ? rcp_nr((double)(hi - lo + 1)) : 0.0;
-  const double inv_s = (double)fd.ab_inv_scale;
+  const double icw_s = outcol ? (double)fd.ab_inv_scale * rcp_nr((double)(hi - lo + 1)) : 0.0;
   const double t0 = (double)fd.t0;
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
@@ -1173,38 +1292,40 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     wave_prefix256_rows<long long, kRpi / 2>(&s_q[wv >> 1][wv & 1][0], 2 * 2 * kGfCols);
     __syncthreads();
     if (outcol) {
-#pragma unroll
-      for (int u = 0; u < kRpi; ++u) {
-        const int y = yb + u;
-        if (y < g.y1) {
-          const long long qa = s_q[u][0][chi] - (clo > 0 ? s_q[u][0][clo - 1] : 0ll);
-          const long long qb = s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ll);
-          const int ch = min(y + r, H - 1) - max(y - r, 0) + 1;
-          const double in = inv_s * icw * rcp_nr((double)ch);
-          const double G = (double)curL[u] * (1.0 / 255000.0);
-          const double q = fma((double)qa * in, G, (double)qb * in);
-          float t = (float)fmin(fmax(q, t0), 1.0);
-          if (FP16) t = round_half(t);
-          const int64_t pi = (int64_t)y * W + x;
-          if (fd.t_out) fd.t_out[pi] = t;
-          const uint32_t c = curRGB[u];
-          float I[3] = {(float)(c & 0xFFu), (float)((c >> 8) & 0xFFu), (float)((c >> 16) & 0xFFu)};
-          float J[3], Jg[3];
-          recon_pixel(rc, I, t, J, Jg);
-          if (fd.J_out) {
-            fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
-          }
-          if (PHASE == 0) {
-            uint8_t* o = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x;
-            o[0] = (uint8_t)rne_u8(Jg[0]);
-            o[1] = (uint8_t)rne_u8(Jg[1]);
-            o[2] = (uint8_t)rne_u8(Jg[2]);
-          } else {
-            if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
-            else reinterpret_cast<float*>(fd.tmap)[pi] = t;
-            acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
-          }
+      auto row_q = [&](int u, int y) {
+        const double qa = i64_to_f64(s_q[u][0][chi] - (clo > 0 ? s_q[u][0][clo - 1] : 0ll));
+        const double qb = i64_to_f64(s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ll));
+        const double in = icw_s * s_rows[y - g.y0].y;
+        const double G = (double)curL[u] * (1.0 / 255000.0);
+        const double q = fma(qa * in, G, qb * in);
+        float t = (float)fmin(fmax(q, t0), 1.0);
+        if (FP16) t = round_half(t);
+        const int64_t pi = (int64_t)y * W + x;
+        if (AUX && fd.t_out) fd.t_out[pi] = t;
+        const uint32_t c = curRGB[u];
+        float I[3] = {(float)(c & 0xFFu), (float)((c >> 8) & 0xFFu), (float)((c >> 16) & 0xFFu)};
+        float J[3], Jg[3];
+        recon_pixel(rc, I, t, J, Jg);
+        if (AUX && fd.J_out) {
+          fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
         }
+        if (PHASE == 0) {
+          uint8_t* o = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x;
+          o[0] = (uint8_t)rne_u8(Jg[0]);
+          o[1] = (uint8_t)rne_u8(Jg[1]);
+          o[2] = (uint8_t)rne_u8(Jg[2]);
+        } else {
+          if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
+          else reinterpret_cast<float*>(fd.tmap)[pi] = t;
+          acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+        }
+      };
+      if (yb + kRpi <= g.y1) {  // a whole phase: no per-row branches, the rows' chains interleave
+#pragma unroll
+        for (int u = 0; u < kRpi; ++u) row_q(u, yb + u);
+      } else {
+        for (int u = 0; u < kRpi; ++u)
+          if (yb + u < g.y1) row_q(u, yb + u);
       }
     }
     __syncthreads();
@@ -1216,8 +1337,9 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 // Pointwise Eqs. (4)-(5) (or the refined t), Eq. (7), Eq. (8) and the colour
 // balance.  A block covers kReconPx pixels of one row, 4 per thread.
 // PHASE 0: write the output.  PHASE 1: colour-balance sums only.  PHASE 2:
-// form the gray-world gains from the sums, apply them and write.
-template <int TSRC, int PHASE, bool FP16>
+// form the gray-world gains from the sums, apply them and write.  AUX: some
+// frame of the launch asks for its t or J maps.
+template <int TSRC, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_recon(Batch b) {
   __shared__ unsigned long long s_red[4];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -1263,49 +1385,54 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       }
     }
     uint32_t ow[3] = {0, 0, 0};
+    auto px = [&](int i) {
+      float I[3], J[3], Jg[3];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (i < nx) {
-        float I[3], J[3], Jg[3];
+      for (int c = 0; c < 3; ++c) {
+        const int byte = 3 * i + c;
+        I[c] = (float)((iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
+      }
+      float t;
+      if (TSRC == TSRC_HE) {
+        float e[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int byte = 3 * i + c;
-          I[c] = (float)((iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
+          e[c] = (float)((ew[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
         }
-        float t;
-        if (TSRC == TSRC_HE) {
-          float e[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int byte = 3 * i + c;
-            e[c] = (float)((ew[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
-          }
-          t = tx_he(k, e[0], e[1], e[2]);
-        } else if (TSRC == TSRC_PAPER) {
-          t = tx_paper(k, fminf(fminf(I[0], I[1]), I[2]));
-        } else {
-          const int64_t pi = (int64_t)y * W + x0 + i;
-          t = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi])
-                   : reinterpret_cast<const float*>(fd.tmap)[pi];
+        t = tx_he(k, e[0], e[1], e[2]);
+      } else if (TSRC == TSRC_PAPER) {
+        t = tx_paper(k, fminf(fminf(I[0], I[1]), I[2]));
+      } else {
+        const int64_t pi = (int64_t)y * W + x0 + i;
+        t = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi])
+                 : reinterpret_cast<const float*>(fd.tmap)[pi];
+      }
+      if (FP16) t = round_half(t);
+      recon_pixel(rc, I, t, J, Jg);
+      if (PHASE == 1) {
+        acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+      } else {
+        const int64_t pi = (int64_t)y * W + x0 + i;
+        if (AUX && fd.t_out) fd.t_out[pi] = t;
+        if (AUX && fd.J_out) {
+          fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
         }
-        if (FP16) t = round_half(t);
-        recon_pixel(rc, I, t, J, Jg);
-        if (PHASE == 1) {
-          acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
-        } else {
-          const int64_t pi = (int64_t)y * W + x0 + i;
-          if (fd.t_out) fd.t_out[pi] = t;
-          if (fd.J_out) {
-            fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
-          }
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const float v = (PHASE == 2) ? fminf(255.0f, gain[c] * Jg[c]) : Jg[c];
-            const int byte = 3 * i + c;
-            ow[byte >> 2] |= rne_u8(v) << (8 * (byte & 3));
-          }
+        for (int c = 0; c < 3; ++c) {
+          const float v = (PHASE == 2) ? fminf(255.0f, gain[c] * Jg[c]) : Jg[c];
+          const int byte = 3 * i + c;
+          ow[byte >> 2] |= rne_u8(v) << (8 * (byte & 3));
         }
       }
+    };
+    if (nx == 4) {  // no per-pixel branches: the four pixels' chains interleave
+#pragma unroll
+      for (int i = 0; i < 4; ++i) px(i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < nx) px(i);
     }
     if (PHASE != 1) {
       uint8_t* Op = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x0;
@@ -1338,6 +1465,26 @@ template <int HP>
 hipError_t dark_hp(const Batch& b, int nblk, bool write_E, hipStream_t s) {
   if (write_E) hipLaunchKernelGGL((k_dark<HP, true>), dim3(nblk), dim3(256), 0, s, b);
   else hipLaunchKernelGGL((k_dark<HP, false>), dim3(nblk), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+// Whether any frame of the launch wants its t or J map (the kernels then keep
+// the per-pixel branches for those stores).
+bool any_aux_maps(const Batch& b) {
+  for (int i = 0; i < b.n; ++i)
+    if (b.f[i].t_out || b.f[i].J_out) return true;
+  return false;
+}
+
+template <int PHASE>
+hipError_t gf_q_p(const Batch& b, int nblk, bool fp16, bool aux, hipStream_t s) {
+  if (fp16) {
+    if (aux) hipLaunchKernelGGL((k_gf_q<PHASE, true, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<PHASE, true, false>), dim3(nblk), dim3(256), 0, s, b);
+  } else {
+    if (aux) hipLaunchKernelGGL((k_gf_q<PHASE, false, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<PHASE, false, false>), dim3(nblk), dim3(256), 0, s, b);
+  }
   return hipGetLastError();
 }
 
@@ -1400,29 +1547,29 @@ hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s) {
 
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
-  if (g.cb) {
-    if (g.fp16) hipLaunchKernelGGL((k_gf_q<1, true>), dim3(nblk), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_gf_q<1, false>), dim3(nblk), dim3(256), 0, s, b);
-  } else {
-    if (g.fp16) hipLaunchKernelGGL((k_gf_q<0, true>), dim3(nblk), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_gf_q<0, false>), dim3(nblk), dim3(256), 0, s, b);
-  }
-  return hipGetLastError();
+  const bool aux = any_aux_maps(b);
+  if (g.cb) return gf_q_p<1>(b, nblk, g.fp16, aux, s);
+  return gf_q_p<0>(b, nblk, g.fp16, aux, s);
 }
 
 namespace {
 template <int TSRC, int PHASE>
-hipError_t recon_tp(const Batch& b, int nblk, bool fp16, hipStream_t s) {
-  if (fp16) hipLaunchKernelGGL((k_recon<TSRC, PHASE, true>), dim3(nblk), dim3(256), 0, s, b);
-  else hipLaunchKernelGGL((k_recon<TSRC, PHASE, false>), dim3(nblk), dim3(256), 0, s, b);
+hipError_t recon_tp(const Batch& b, int nblk, bool fp16, bool aux, hipStream_t s) {
+  if (fp16) {
+    if (aux) hipLaunchKernelGGL((k_recon<TSRC, PHASE, true, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_recon<TSRC, PHASE, true, false>), dim3(nblk), dim3(256), 0, s, b);
+  } else {
+    if (aux) hipLaunchKernelGGL((k_recon<TSRC, PHASE, false, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_recon<TSRC, PHASE, false, false>), dim3(nblk), dim3(256), 0, s, b);
+  }
   return hipGetLastError();
 }
 template <int TSRC>
-hipError_t recon_t(const Batch& b, int nblk, int phase, bool fp16, hipStream_t s) {
+hipError_t recon_t(const Batch& b, int nblk, int phase, bool fp16, bool aux, hipStream_t s) {
   switch (phase) {
-    case 0: return recon_tp<TSRC, 0>(b, nblk, fp16, s);
-    case 1: return recon_tp<TSRC, 1>(b, nblk, fp16, s);
-    case 2: return recon_tp<TSRC, 2>(b, nblk, fp16, s);
+    case 0: return recon_tp<TSRC, 0>(b, nblk, fp16, aux, s);
+    case 1: return recon_tp<TSRC, 1>(b, nblk, fp16, false, s);   // sums only: no maps written
+    case 2: return recon_tp<TSRC, 2>(b, nblk, fp16, aux, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1430,10 +1577,11 @@ hipError_t recon_t(const Batch& b, int nblk, int phase, bool fp16, hipStream_t s
 
 hipError_t launch_recon(Batch b, const GroupKey& g, int tsrc, int phase, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return recon_blocks(f.W, f.H); });
+  const bool aux = any_aux_maps(b);
   switch (tsrc) {
-    case TSRC_HE: return recon_t<TSRC_HE>(b, nblk, phase, g.fp16, s);
-    case TSRC_PAPER: return recon_t<TSRC_PAPER>(b, nblk, phase, g.fp16, s);
-    case TSRC_TMAP: return recon_t<TSRC_TMAP>(b, nblk, phase, g.fp16, s);
+    case TSRC_HE: return recon_t<TSRC_HE>(b, nblk, phase, g.fp16, aux, s);
+    case TSRC_PAPER: return recon_t<TSRC_PAPER>(b, nblk, phase, g.fp16, aux, s);
+    case TSRC_TMAP: return recon_t<TSRC_TMAP>(b, nblk, phase, g.fp16, aux, s);
     default: return hipErrorInvalidValue;
   }
 }
