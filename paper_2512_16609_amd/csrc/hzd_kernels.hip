@@ -996,7 +996,9 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   const GfTile g = gf_tile(fd, blk - b.tile0[f]);
   const int W = g.W, H = g.H, r = g.r;
   const int tid = threadIdx.x, wv = tid >> 6;
-  const uint2* col = fd.LP + (g.colin ? g.xl : 0);
+  // this thread's column; threads outside the frame read the nearest edge
+  // column, whose sums land in prefix entries no in-frame box uses
+  const uint2* col = fd.LP + min(max(g.xl, 0), W - 1);
   gf_row_table(g, s_rows);
 
   unsigned long long sL = 0, sLL = 0, sP = 0, sLP = 0;
@@ -1044,15 +1046,16 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
       }
     }
   }
-  // entering/leaving rows of output row yn (zero where the window does not move)
+  // entering/leaving rows of output row yn.  The loads are unconditional
+  // (rows clamped into the frame) so that the number of loads in flight is
+  // static and a prefetch is waited for only where it is used; rows that do
+  // not enter or leave the window are skipped at the use (uniform branches).
   auto fetch = [&](int yn, uint2& vin, uint2& vout) {
-    vin = make_uint2(0u, 0u);
-    vout = make_uint2(0u, 0u);
-    if (g.colin && yn > g.y0 && yn < g.y1) {
-      if (yn + r < H) vin = col[(yn + r) * W];  // offsets < W*H < 2^31
-      if (yn - r - 1 >= 0) vout = col[(yn - r - 1) * W];
-    }
+    vin = col[min(yn + r, H - 1) * W];  // offsets < W*H < 2^31
+    vout = col[min(max(yn - r - 1, 0), H - 1) * W];
   };
+  auto enters = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn + r < H; };
+  auto leaves = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn - r - 1 >= 0; };
   uint2 pin[kRpi], pout[kRpi];
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
@@ -1075,8 +1078,8 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
-      add(pin[u]);
-      sub(pout[u]);
+      if (enters(yb + u)) add(pin[u]);
+      if (leaves(yb + u)) sub(pout[u]);
       fetch(yb + kRpi + u, pin[u], pout[u]);
       s_q[u][0][tid] = sL;
       s_q[u][1][tid] = sLL;
@@ -1203,7 +1206,9 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   const GfTile g = gf_tile(fd, tile);
   const int W = g.W, H = g.H, r = g.r;
   const int tid = threadIdx.x, wv = tid >> 6;
-  const int2* col = fd.AB + (g.colin ? g.xl : 0);
+  // this thread's column; threads outside the frame read the nearest edge
+  // column, whose sums land in prefix entries no in-frame box uses
+  const int2* col = fd.AB + min(max(g.xl, 0), W - 1);
   gf_row_table(g, s_rows);
   const ReconConsts rc = recon_consts(fd);
 
@@ -1241,32 +1246,33 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
       }
     }
   }
+  // unconditional loads (rows and columns clamped into the frame): the number
+  // of loads in flight is static, so a prefetch is waited for only at its use
   auto fetch = [&](int yn, int2& vin, int2& vout) {
-    vin = make_int2(0, 0);
-    vout = make_int2(0, 0);
-    if (g.colin && yn > g.y0 && yn < g.y1) {
-      if (yn + r < H) vin = col[(yn + r) * W];  // offsets < W*H < 2^31
-      if (yn - r - 1 >= 0) vout = col[(yn - r - 1) * W];
-    }
+    vin = col[min(yn + r, H - 1) * W];  // offsets < W*H < 2^31
+    vout = col[min(max(yn - r - 1, 0), H - 1) * W];
   };
+  auto enters = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn + r < H; };
+  auto leaves = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn - r - 1 >= 0; };
   const int x = g.x0 + tid;
   const bool outcol = tid < g.SW && x < W;
-  // the output pixel's guide value and colour
-  auto fetch_px = [&](int yn, uint32_t& L, uint32_t& rgb) {
-    L = 0u;
-    rgb = 0u;
-    if (outcol && yn < g.y1) {
-      L = fd.LP[yn * W + x].x;
-      const uint8_t* p = fd.src + (int64_t)yn * fd.src_pitch + 3 * x;
-      rgb = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
-    }
+  const int xc = min(x, W - 1);
+  // the output pixel's guide value and colour (R, G in one 16-bit load, B)
+  auto fetch_px = [&](int yn, uint32_t& L, uint32_t& rg, uint32_t& bl) {
+    const int yc = min(yn, H - 1);
+    L = fd.LP[yc * W + xc].x;
+    const uint8_t* p = fd.src + (int64_t)yc * fd.src_pitch + 3 * xc;
+    uint16_t v;
+    __builtin_memcpy(&v, p, 2);
+    rg = v;
+    bl = p[2];
   };
   int2 pin[kRpi], pout[kRpi];
-  uint32_t pL[kRpi], pRGB[kRpi];
+  uint32_t pL[kRpi], pRG[kRpi], pB[kRpi];
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) {
     fetch(g.y0 + u, pin[u], pout[u]);
-    fetch_px(g.y0 + u, pL[u], pRGB[u]);
+    fetch_px(g.y0 + u, pL[u], pRG[u], pB[u]);
   }
 
   const int lo = max(x - r, 0), hi = min(x + r, W - 1);
@@ -1275,15 +1281,22 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   const double t0 = (double)fd.t0;
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
-    uint32_t curL[kRpi], curRGB[kRpi];
+    uint32_t curL[kRpi], curRG[kRpi], curB[kRpi];
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
-      sa += pin[u].x - pout[u].x;
-      sb += pin[u].y - pout[u].y;
+      if (enters(yb + u)) {
+        sa += pin[u].x;
+        sb += pin[u].y;
+      }
+      if (leaves(yb + u)) {
+        sa -= pout[u].x;
+        sb -= pout[u].y;
+      }
       fetch(yb + kRpi + u, pin[u], pout[u]);
       curL[u] = pL[u];
-      curRGB[u] = pRGB[u];
-      fetch_px(yb + kRpi + u, pL[u], pRGB[u]);
+      curRG[u] = pRG[u];
+      curB[u] = pB[u];
+      fetch_px(yb + kRpi + u, pL[u], pRG[u], pB[u]);
       s_q[u][0][tid] = sa;
       s_q[u][1][tid] = sb;
     }
@@ -1302,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         if (FP16) t = round_half(t);
         const int64_t pi = (int64_t)y * W + x;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
-        const uint32_t c = curRGB[u];
+        const uint32_t c = curRG[u] | (curB[u] << 16);
         float I[3] = {(float)(c & 0xFFu), (float)((c >> 8) & 0xFFu), (float)((c >> 16) & 0xFFu)};
         float J[3], Jg[3];
         recon_pixel(rc, I, t, J, Jg);
