@@ -95,7 +95,7 @@ hipError_t launch_recon(Batch b, const GroupKey& g, int tsrc, int phase, hipStre
 
 // Tiling shared by the workspace planner and the launches.
 constexpr int kDarkTW = 64, kDarkTH = 32;
-constexpr int kReconPx = 1024;   // pixels of one row per recon block
+constexpr int kReconPx = 2048;   // pixels of one row per recon block (two groups of 4 per thread)
 constexpr int kGfCols = 256;     // loaded columns per guided-filter strip block
 constexpr int kGfRowsDefault = 16;  // output rows per guided-filter block unless tuned (a multiple of 8)
 constexpr int kGfRowsMin = 8;

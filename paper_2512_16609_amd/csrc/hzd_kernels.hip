@@ -186,20 +186,21 @@ __global__ __launch_bounds__(256) void k_init(Batch b) {
 // LDS as two planes of packed 16-bit pairs: (R | B << 16) and (G | 255 << 16),
 // so each v_pk_min_u16 handles two channels.  Out-of-frame cells hold 255 (a
 // clipped window).  Vertical van Herk per column segment, then horizontal van
-// Herk per row segment, both in registers.
+// Herk per row segment, both in registers.  One LDS buffer serves as the byte
+// stage, the two planes and, in place, the vertical-pass output (each step
+// reads into registers, then a barrier, then writes), so that 5 blocks fit
+// on a CU at h = 7 and a 1080p frame's tiles run in one round.
 template <int HP, bool WRITE_E>
 __global__ __launch_bounds__(256) void k_dark(Batch b) {
   constexpr int TW = kDarkTW, TH = kDarkTH;
   constexpr int RW = TW + 2 * HP, RH = TH + 2 * HP, WIN = 2 * HP + 1;
   constexpr int SROW = (3 * RW + 3) / 4 + 2;   // dwords of one staged region row (+ slack)
-  __shared__ uint32_t s_rb[RH][RW];
-  __shared__ uint32_t s_g[RH][RW];
-  __shared__ uint32_t s_v[2][TH][RW];           // vertical-pass output; first used as the byte stage
+  __shared__ uint32_t s_pl[2][RH][RW];
   __shared__ uint32_t s_hist[256];
-  static_assert(RH * SROW <= 2 * TH * RW, "byte stage does not fit");
-  uint32_t(&s_vrb)[TH][RW] = s_v[0];
-  uint32_t(&s_vg)[TH][RW] = s_v[1];
-  uint32_t* s_stage = &s_v[0][0][0];
+  static_assert(RH * SROW <= 2 * RH * RW, "byte stage does not fit");
+  uint32_t(&s_rb)[RH][RW] = s_pl[0];
+  uint32_t(&s_g)[RH][RW] = s_pl[1];
+  uint32_t* s_stage = &s_pl[0][0][0];
 
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
@@ -258,6 +259,7 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
       }
     }
   }
+  __syncthreads();  // the planes overwrite the byte stage
 #pragma unroll
   for (int k = 0; k < (RH * RW + 255) / 256; ++k) {
     const int i = tid + 256 * k;
@@ -269,12 +271,16 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   }
   __syncthreads();
 
-  // vertical pass: RW columns x 2 segments of 16 output rows
+  // vertical pass: RW columns x 2 segments of 16 output rows, one per
+  // thread; the outputs replace rows [0, TH) of the planes in place
   {
     constexpr int SEG = 16, NSEG = TH / SEG, L = SEG + WIN - 1;
-    for (int w = tid; w < RW * NSEG; w += 256) {
-      const int sg = w / RW, cc = w - sg * RW, r0 = sg * SEG;
-      uint32_t vrb[L], vg[L], orb[SEG], og[SEG];
+    static_assert(RW * NSEG <= 256, "one column segment per thread");
+    const bool act = tid < RW * NSEG;
+    const int sg = tid / RW, cc = tid - sg * RW, r0 = sg * SEG;
+    uint32_t orb[SEG], og[SEG];
+    if (act) {
+      uint32_t vrb[L], vg[L];
 #pragma unroll
       for (int i = 0; i < L; ++i) {
         vrb[i] = s_rb[r0 + i][cc];
@@ -282,10 +288,13 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
       }
       sliding_min<L, WIN, SEG>(vrb, orb);
       sliding_min<L, WIN, SEG>(vg, og);
+    }
+    __syncthreads();  // every segment has read its rows before any is overwritten
+    if (act) {
 #pragma unroll
       for (int i = 0; i < SEG; ++i) {
-        s_vrb[r0 + i][cc] = orb[i];
-        s_vg[r0 + i][cc] = og[i];
+        s_rb[r0 + i][cc] = orb[i];
+        s_g[r0 + i][cc] = og[i];
       }
     }
   }
@@ -298,8 +307,8 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
     uint32_t vrb[L], vg[L], orb[HS], og[HS];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      vrb[i] = s_vrb[r][c0 + i];
-      vg[i] = s_vg[r][c0 + i];
+      vrb[i] = s_rb[r][c0 + i];
+      vg[i] = s_g[r][c0 + i];
     }
     sliding_min<L, WIN, HS>(vrb, orb);
     sliding_min<L, WIN, HS>(vg, og);
@@ -1348,12 +1357,27 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 
 // ------------------------------------------------------------------ k_recon
 // Pointwise Eqs. (4)-(5) (or the refined t), Eq. (7), Eq. (8) and the colour
-// balance.  A block covers kReconPx pixels of one row, 4 per thread.
-// PHASE 0: write the output.  PHASE 1: colour-balance sums only.  PHASE 2:
-// form the gray-world gains from the sums, apply them and write.  AUX: some
-// frame of the launch asks for its t or J maps.
+// balance.  A block covers kReconPx pixels of one row: each thread takes two
+// groups of 4 pixels, kReconPx / 2 apart, and issues the loads of both groups
+// before any arithmetic.  PHASE 0: write the output.  PHASE 1: colour-balance
+// sums only.  PHASE 2: form the gray-world gains from the sums, apply them and
+// write.  AUX: some frame of the launch asks for its t or J maps.
+__device__ __forceinline__ void load_rgb12(const uint8_t* p, int nx, bool aligned, uint32_t w[3]) {
+  if (aligned && nx == 4) {
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+    w[0] = q[0]; w[1] = q[1]; w[2] = q[2];
+  } else {
+    uint8_t tmp[12] = {0};
+    for (int i = 0; i < 3 * nx; ++i) tmp[i] = p[i];
+    w[0] = tmp[0] | (tmp[1] << 8) | (tmp[2] << 16) | ((uint32_t)tmp[3] << 24);
+    w[1] = tmp[4] | (tmp[5] << 8) | (tmp[6] << 16) | ((uint32_t)tmp[7] << 24);
+    w[2] = tmp[8] | (tmp[9] << 8) | (tmp[10] << 16) | ((uint32_t)tmp[11] << 24);
+  }
+}
+
 template <int TSRC, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_recon(Batch b) {
+  static_assert(kReconPx == 2 * 4 * 256, "two groups of 4 pixels per thread");
   __shared__ unsigned long long s_red[4];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
@@ -1362,48 +1386,48 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   const int W = fd.W;
   const int per_row = (W + kReconPx - 1) / kReconPx;
   const int y = tile / per_row;
-  const int x0 = (tile - y * per_row) * kReconPx + 4 * threadIdx.x;
-  const int tid = threadIdx.x;
+  const int xb = (tile - y * per_row) * kReconPx + 4 * (int)threadIdx.x;
   const TxConsts k = tx_consts(fd);
   const ReconConsts rc = recon_consts(fd);
   float gain[3] = {1.f, 1.f, 1.f};
   if (PHASE == 2) cb_gains(fd, gain, s_red);
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
-  if (x0 < W) {
-    const int nx = min(4, W - x0);
-    const uint8_t* Ip = fd.src + (int64_t)y * fd.src_pitch + 3 * x0;
-    uint32_t iw[3];
-    if (fd.aligned && nx == 4) {
-      const uint32_t* q = reinterpret_cast<const uint32_t*>(Ip);
-      iw[0] = q[0]; iw[1] = q[1]; iw[2] = q[2];
-    } else {
-      uint8_t tmp[12] = {0};
-      for (int i = 0; i < 3 * nx; ++i) tmp[i] = Ip[i];
-      iw[0] = tmp[0] | (tmp[1] << 8) | (tmp[2] << 16) | ((uint32_t)tmp[3] << 24);
-      iw[1] = tmp[4] | (tmp[5] << 8) | (tmp[6] << 16) | ((uint32_t)tmp[7] << 24);
-      iw[2] = tmp[8] | (tmp[9] << 8) | (tmp[10] << 16) | ((uint32_t)tmp[11] << 24);
-    }
-    uint32_t ew[3] = {0, 0, 0};
-    if (TSRC == TSRC_HE) {
-      const uint8_t* Ep = fd.E + (int64_t)y * fd.E_pitch + 3 * x0;
-      if (nx == 4) {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(Ep);
-        ew[0] = q[0]; ew[1] = q[1]; ew[2] = q[2];
-      } else {
-        uint8_t tmp[12] = {0};
-        for (int i = 0; i < 3 * nx; ++i) tmp[i] = Ep[i];
-        ew[0] = tmp[0] | (tmp[1] << 8) | (tmp[2] << 16) | ((uint32_t)tmp[3] << 24);
-        ew[1] = tmp[4] | (tmp[5] << 8) | (tmp[6] << 16) | ((uint32_t)tmp[7] << 24);
-        ew[2] = tmp[8] | (tmp[9] << 8) | (tmp[10] << 16) | ((uint32_t)tmp[11] << 24);
+
+  constexpr int NG = 2;
+  int x0[NG], nx[NG];
+  uint32_t iw[NG][3], ew[NG][3];
+  float tm[NG][4];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    x0[q] = xb + q * (kReconPx / 2);
+    nx[q] = max(0, min(4, W - x0[q]));
+    iw[q][0] = iw[q][1] = iw[q][2] = 0u;
+    ew[q][0] = ew[q][1] = ew[q][2] = 0u;
+    tm[q][0] = tm[q][1] = tm[q][2] = tm[q][3] = 1.0f;
+    if (nx[q] > 0) {
+      load_rgb12(fd.src + (int64_t)y * fd.src_pitch + 3 * x0[q], nx[q], fd.aligned, iw[q]);
+      if (TSRC == TSRC_HE) load_rgb12(fd.E + (int64_t)y * fd.E_pitch + 3 * x0[q], nx[q], true, ew[q]);
+      if (TSRC == TSRC_TMAP) {
+        const int64_t pi = (int64_t)y * W + x0[q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < nx[q])
+            tm[q][i] = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi + i])
+                            : reinterpret_cast<const float*>(fd.tmap)[pi + i];
       }
     }
+  }
+
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    if (nx[q] == 0) continue;
     uint32_t ow[3] = {0, 0, 0};
     auto px = [&](int i) {
       float I[3], J[3], Jg[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int byte = 3 * i + c;
-        I[c] = (float)((iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
+        I[c] = (float)((iw[q][byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
       }
       float t;
       if (TSRC == TSRC_HE) {
@@ -1411,22 +1435,20 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int byte = 3 * i + c;
-          e[c] = (float)((ew[byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
+          e[c] = (float)((ew[q][byte >> 2] >> (8 * (byte & 3))) & 0xFFu);
         }
         t = tx_he(k, e[0], e[1], e[2]);
       } else if (TSRC == TSRC_PAPER) {
         t = tx_paper(k, fminf(fminf(I[0], I[1]), I[2]));
       } else {
-        const int64_t pi = (int64_t)y * W + x0 + i;
-        t = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi])
-                 : reinterpret_cast<const float*>(fd.tmap)[pi];
+        t = tm[q][i];
       }
       if (FP16) t = round_half(t);
       recon_pixel(rc, I, t, J, Jg);
       if (PHASE == 1) {
         acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
       } else {
-        const int64_t pi = (int64_t)y * W + x0 + i;
+        const int64_t pi = (int64_t)y * W + x0[q] + i;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
         if (AUX && fd.J_out) {
           fd.J_out[3 * pi] = J[0]; fd.J_out[3 * pi + 1] = J[1]; fd.J_out[3 * pi + 2] = J[2];
@@ -1439,21 +1461,21 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
         }
       }
     };
-    if (nx == 4) {  // no per-pixel branches: the four pixels' chains interleave
+    if (nx[q] == 4) {  // no per-pixel branches: the four pixels' chains interleave
 #pragma unroll
       for (int i = 0; i < 4; ++i) px(i);
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (i < nx) px(i);
+        if (i < nx[q]) px(i);
     }
     if (PHASE != 1) {
-      uint8_t* Op = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x0;
-      if (fd.aligned && nx == 4) {
-        uint32_t* q = reinterpret_cast<uint32_t*>(Op);
-        q[0] = ow[0]; q[1] = ow[1]; q[2] = ow[2];
+      uint8_t* Op = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x0[q];
+      if (fd.aligned && nx[q] == 4) {
+        uint32_t* o = reinterpret_cast<uint32_t*>(Op);
+        o[0] = ow[0]; o[1] = ow[1]; o[2] = ow[2];
       } else {
-        for (int i = 0; i < 3 * nx; ++i) Op[i] = (uint8_t)(ow[i >> 2] >> (8 * (i & 3)));
+        for (int i = 0; i < 3 * nx[q]; ++i) Op[i] = (uint8_t)(ow[i >> 2] >> (8 * (i & 3)));
       }
     }
   }
