@@ -101,7 +101,10 @@ constexpr int kGfRowsDefault = 16;  // output rows per guided-filter block unles
 constexpr int kGfRowsMin = 8;
 constexpr int kGfRowsMax = 256;    // one per-row table entry per thread of a 256-thread block
 inline int recon_blocks(int W, int H) { return H * ((W + kReconPx - 1) / kReconPx); }
-inline int gf_strip(int r) { return kGfCols - 2 * r; }
+// Output columns of a guided-filter strip: the largest multiple of 64 that
+// leaves room for the 2r halo columns in kGfCols (128 or 192 for r <= 64), so
+// the 4 x gf_strip outputs of a 4-row phase split evenly over the 256 threads.
+inline int gf_strip(int r) { return ((kGfCols - 2 * r) / 64) * 64; }
 inline int gf_blocks(int W, int H, int r, int rows) {
   return ((W + gf_strip(r) - 1) / gf_strip(r)) * ((H + rows - 1) / rows);
 }

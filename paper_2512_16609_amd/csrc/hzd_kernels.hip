@@ -837,10 +837,10 @@ __device__ __forceinline__ double i64_to_f64(long long x) {
   return fma((double)(int32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
 }
 
-// Geometry of one guided-filter strip block: 256 loaded columns (one per
-// thread) starting at x0 - r, output columns [x0, x0 + 256 - 2r), output rows
-// [y0, y1) with y1 - y0 = fd.gf_rows (the tile height is a tuning knob; the
-// integer sums make results independent of it).
+// Geometry of one guided-filter strip block: SW + 2r loaded columns (one per
+// thread) starting at x0 - r, output columns [x0, x0 + SW) with SW = 128 or
+// 192 (gf_strip), output rows [y0, y1) with y1 - y0 = fd.gf_rows (the tile
+// height is a tuning knob; the integer sums make results independent of it).
 struct GfTile {
   int W, H, r, SW, x0, y0, y1, xl;
   bool colin;
@@ -851,7 +851,7 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
   t.W = fd.W;
   t.H = fd.H;
   t.r = fd.radius;
-  t.SW = kGfCols - 2 * t.r;
+  t.SW = ((kGfCols - 2 * t.r) / 64) * 64;
   // column-major: consecutive tiles are vertical neighbours, which share
   // 2r halo rows, and XCD-aware block mapping keeps runs of them in one L2
   const int chunks = (t.H + fd.gf_rows - 1) / fd.gf_rows;
@@ -860,7 +860,7 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
   t.y0 = sy * fd.gf_rows;
   t.y1 = min(t.H, t.y0 + fd.gf_rows);
   t.xl = t.x0 - t.r + (int)threadIdx.x;
-  t.colin = t.xl >= 0 && t.xl < t.W;
+  t.colin = (int)threadIdx.x < t.SW + 2 * t.r && t.xl >= 0 && t.xl < t.W;
   return t;
 }
 
@@ -996,9 +996,11 @@ __device__ __forceinline__ void wave_prefix256(T* row) {
 // (independent FP64 chains).  Operands of the next kRpi rows are loaded while
 // the current ones are processed.  Means, var and cov are formed in FP64; a
 // and b leave as int32 fixed point with the frame's scale.
+template <int NI>
 __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   __shared__ unsigned long long s_q[kRpi][4][kGfCols];
   __shared__ double2 s_rows[kGfRowsMax];
+  __shared__ unsigned long long s_ch[2][64 * NI];  // a, b sums of each output column's current 8-row chunk
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -1069,21 +1071,35 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
 
-  const int x = g.x0 + tid;
-  const bool outcol = tid < g.SW && x < W;
-  const int lo = max(x - r, 0), hi = min(x + r, W - 1);
-  const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
+  // output items of this thread in a phase: item i = tid + 256 j is row
+  // i / SW, column i % SW of the phase (SW = 64 NI), so every wave gets the
+  // same share of the FP64 work
+  constexpr int SWc = 64 * NI;
+  int iu[NI], ic[NI], iclo[NI], ichi[NI];
+  double icw[NI], cwd[NI];
+  bool iok[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int i = tid + 256 * j;
+    iu[j] = i / SWc;
+    ic[j] = i - iu[j] * SWc;
+    const int x = g.x0 + ic[j];
+    iok[j] = x < W;
+    const int lo = max(x - r, 0), hi = min(x + r, W - 1);
+    iclo[j] = lo - (g.x0 - r);
+    ichi[j] = hi - (g.x0 - r);
+    cwd[j] = (double)(hi - lo + 1);
+    icw[j] = rcp_nr(cwd[j]);
+  }
+  for (int i = tid; i < 2 * SWc; i += 256) (&s_ch[0][0])[i] = 0ull;
   // Eq. (6) from the exact box sums S over n = cw * ch pixels (L = G / kG, P = t / kP):
   //   var = kG^2 / n (S_LL - S_L^2 / n),  cov = kG kP / n (S_LP - S_L S_P / n)
   //   a = cov / (var + eps) = (kP / kG) C / (V + n eps / kG^2)   with V, C the brackets
   //   b = mean(t) - a mean(G) = (kP / n) (S_P - (a kG / kP) S_L)
-  const double cw = (double)(hi - lo + 1);
-  const double icw = outcol ? rcp_nr(cw) : 0.0;
   const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
   const double eps_n = (double)fd.eps / (kG * kG);
   const double s = (double)fd.ab_scale, lim = 2147483647.0;
   const double sa_k = s * kP / kG, sb_k = s * kP;
-  long long ca_ = 0, cb_ = 0;
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
@@ -1098,9 +1114,11 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     __syncthreads();
     wave_prefix256_rows<unsigned long long, kRpi>(&s_q[0][wv][0], 4 * kGfCols);
     __syncthreads();
-    if (outcol) {
-      // a, b of row u (output row y) in fixed point
-      auto row_ab = [&](int u, int y) -> int2 {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int u = iu[j], y = yb + u;
+      if (iok[j] && y < g.y1) {
+        const int clo = iclo[j], chi = ichi[j];
         // box sums as differences of two prefixes; S_L < 2^32, so 32-bit wrap-around is exact
         const uint32_t sl = (uint32_t)s_q[u][0][chi] - (clo > 0 ? (uint32_t)s_q[u][0][clo - 1] : 0u);
         const double SL = (double)sl;
@@ -1108,51 +1126,32 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
         const double SP = u64_to_f64(s_q[u][2][chi] - (clo > 0 ? s_q[u][2][clo - 1] : 0ull));
         const double SLP = u64_to_f64(s_q[u][3][chi] - (clo > 0 ? s_q[u][3][clo - 1] : 0ull));
         const double2 rw = s_rows[y - g.y0];  // {ch, 1 / ch}
-        const double inv_n = icw * rw.y;
+        const double inv_n = icw[j] * rw.y;
         const double t1 = SL * inv_n;
         const double V = fma(-t1, SL, SLL);
         const double C = fma(-t1, SP, SLP);
-        const double a2 = C * rcp_nr(fma(cw * rw.x, eps_n, V));  // a kG / kP
+        const double a2 = C * rcp_nr(fma(cwd[j] * rw.x, eps_n, V));  // a kG / kP
         const double ia = fmin(fmax(__builtin_rint(a2 * sa_k), -lim), lim);
         const double ib = fmin(fmax(__builtin_rint(fma(-a2, SL, SP) * (inv_n * sb_k)), -lim), lim);
-        return make_int2((int)ia, (int)ib);
-      };
-      // the column's sums of a, b over its aligned 8-row chunk (for stage 2's window)
-      auto chunk_end = [&](int y) {
-        if ((y & (kChunk - 1)) == kChunk - 1 || y == H - 1) {
-          fd.S8ab[(y / kChunk) * W + x] = make_longlong2(ca_, cb_);
-          ca_ = 0;
-          cb_ = 0;
-        }
-      };
-      if (yb + kRpi <= g.y1) {
-        // a whole phase: no per-row branches, so the kRpi FP64 chains interleave.
-        // Phases start at multiples of kRpi (a divisor of kChunk), so only the
-        // phase's last row can end a chunk or the frame.
-        int2 v[kRpi];
-#pragma unroll
-        for (int u = 0; u < kRpi; ++u) v[u] = row_ab(u, yb + u);
-#pragma unroll
-        for (int u = 0; u < kRpi; ++u) {
-          fd.AB[(yb + u) * W + x] = v[u];
-          ca_ += v[u].x;
-          cb_ += v[u].y;
-        }
-        chunk_end(yb + kRpi - 1);
-      } else {
-        for (int u = 0; u < kRpi; ++u) {
-          const int y = yb + u;
-          if (y < g.y1) {
-            const int2 v = row_ab(u, y);
-            fd.AB[y * W + x] = v;
-            ca_ += v.x;
-            cb_ += v.y;
-            chunk_end(y);
-          }
-        }
+        const int x = g.x0 + ic[j];
+        fd.AB[y * W + x] = make_int2((int)ia, (int)ib);
+        // the column's sums of a, b over its aligned 8-row chunk (for stage 2's window)
+        atomicAdd(&s_ch[0][ic[j]], (unsigned long long)(long long)(int)ia);
+        atomicAdd(&s_ch[1][ic[j]], (unsigned long long)(long long)(int)ib);
       }
     }
     __syncthreads();
+    // the phase's last row ends an 8-row chunk (phases start at multiples of
+    // kRpi, a divisor of kChunk): store the chunk sums and start the next
+    const int yl = min(yb + kRpi, g.y1) - 1;
+    if ((yl & (kChunk - 1)) == kChunk - 1 || yl == H - 1) {
+      for (int c = tid; c < SWc; c += 256) {
+        const int x = g.x0 + c;
+        if (x < W) fd.S8ab[(yl / kChunk) * W + x] = make_longlong2((long long)s_ch[0][c], (long long)s_ch[1][c]);
+        s_ch[0][c] = 0ull;
+        s_ch[1][c] = 0ull;
+      }
+    }
   }
 }
 
@@ -1203,7 +1202,7 @@ __device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3], unsigne
 // mean(b), clamped to [t0, 1].  PHASE 0: fuse Eqs. (7)-(8) and write the
 // output.  PHASE 1: store the refined t and the colour-balance sums.  AUX:
 // some frame of the launch asks for its t or J maps.
-template <int PHASE, bool FP16, bool AUX>
+template <int NI, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   __shared__ long long s_q[kRpi][2][kGfCols];
   __shared__ double2 s_rows[kGfRowsMax];
@@ -1263,11 +1262,29 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   };
   auto enters = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn + r < H; };
   auto leaves = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn - r - 1 >= 0; };
-  const int x = g.x0 + tid;
-  const bool outcol = tid < g.SW && x < W;
-  const int xc = min(x, W - 1);
-  // the output pixel's guide value and colour (R, G in one 16-bit load, B)
-  auto fetch_px = [&](int yn, uint32_t& L, uint32_t& rg, uint32_t& bl) {
+  // output items of this thread in a phase: item i = tid + 256 j is row
+  // i / SW, column i % SW of the phase (SW = 64 NI)
+  constexpr int SWc = 64 * NI;
+  int iu[NI], ic[NI], iclo[NI], ichi[NI], ixc[NI];
+  double icw_s[NI];
+  bool iok[NI];
+  const double inv_s = (double)fd.ab_inv_scale;
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int i = tid + 256 * j;
+    iu[j] = i / SWc;
+    ic[j] = i - iu[j] * SWc;
+    const int x = g.x0 + ic[j];
+    iok[j] = x < W;
+    ixc[j] = min(x, W - 1);
+    const int lo = max(x - r, 0), hi = min(x + r, W - 1);
+    iclo[j] = lo - (g.x0 - r);
+    ichi[j] = hi - (g.x0 - r);
+    icw_s[j] = inv_s * rcp_nr((double)(hi - lo + 1));
+  }
+  // an output pixel's guide value and colour (R, G in one 16-bit load, B),
+  // loaded one phase ahead (row clamped into the frame: unconditional loads)
+  auto fetch_px = [&](int yn, int xc, uint32_t& L, uint32_t& rg, uint32_t& bl) {
     const int yc = min(yn, H - 1);
     L = fd.LP[yc * W + xc].x;
     const uint8_t* p = fd.src + (int64_t)yc * fd.src_pitch + 3 * xc;
@@ -1277,20 +1294,16 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     bl = p[2];
   };
   int2 pin[kRpi], pout[kRpi];
-  uint32_t pL[kRpi], pRG[kRpi], pB[kRpi];
+  uint32_t pL[NI], pRG[NI], pB[NI];
 #pragma unroll
-  for (int u = 0; u < kRpi; ++u) {
-    fetch(g.y0 + u, pin[u], pout[u]);
-    fetch_px(g.y0 + u, pL[u], pRG[u], pB[u]);
-  }
+  for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
+#pragma unroll
+  for (int j = 0; j < NI; ++j) fetch_px(g.y0 + iu[j], ixc[j], pL[j], pRG[j], pB[j]);
 
-  const int lo = max(x - r, 0), hi = min(x + r, W - 1);
-  const int clo = lo - (g.x0 - r), chi = hi - (g.x0 - r);
-  const double icw_s = outcol ? (double)fd.ab_inv_scale * rcp_nr((double)(hi - lo + 1)) : 0.0;
   const double t0 = (double)fd.t0;
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
-    uint32_t curL[kRpi], curRG[kRpi], curB[kRpi];
+    uint32_t curL[NI], curRG[NI], curB[NI];
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
       if (enters(yb + u)) {
@@ -1302,29 +1315,35 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         sb -= pout[u].y;
       }
       fetch(yb + kRpi + u, pin[u], pout[u]);
-      curL[u] = pL[u];
-      curRG[u] = pRG[u];
-      curB[u] = pB[u];
-      fetch_px(yb + kRpi + u, pL[u], pRG[u], pB[u]);
       s_q[u][0][tid] = sa;
       s_q[u][1][tid] = sb;
+    }
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      curL[j] = pL[j];
+      curRG[j] = pRG[j];
+      curB[j] = pB[j];
+      fetch_px(yb + kRpi + iu[j], ixc[j], pL[j], pRG[j], pB[j]);
     }
     __syncthreads();
     // 2 quantities x kRpi rows of scans over the 4 waves
     wave_prefix256_rows<long long, kRpi / 2>(&s_q[wv >> 1][wv & 1][0], 2 * 2 * kGfCols);
     __syncthreads();
-    if (outcol) {
-      auto row_q = [&](int u, int y) {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int u = iu[j], y = yb + u;
+      if (iok[j] && y < g.y1) {
+        const int clo = iclo[j], chi = ichi[j], x = g.x0 + ic[j];
         const double qa = i64_to_f64(s_q[u][0][chi] - (clo > 0 ? s_q[u][0][clo - 1] : 0ll));
         const double qb = i64_to_f64(s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ll));
-        const double in = icw_s * s_rows[y - g.y0].y;
-        const double G = (double)curL[u] * (1.0 / 255000.0);
+        const double in = icw_s[j] * s_rows[y - g.y0].y;
+        const double G = (double)curL[j] * (1.0 / 255000.0);
         const double q = fma(qa * in, G, qb * in);
         float t = (float)fmin(fmax(q, t0), 1.0);
         if (FP16) t = round_half(t);
         const int64_t pi = (int64_t)y * W + x;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
-        const uint32_t c = curRG[u] | (curB[u] << 16);
+        const uint32_t c = curRG[j] | (curB[j] << 16);
         float I[3] = {(float)(c & 0xFFu), (float)((c >> 8) & 0xFFu), (float)((c >> 16) & 0xFFu)};
         float J[3], Jg[3];
         recon_pixel(rc, I, t, J, Jg);
@@ -1341,13 +1360,6 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
           else reinterpret_cast<float*>(fd.tmap)[pi] = t;
           acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
         }
-      };
-      if (yb + kRpi <= g.y1) {  // a whole phase: no per-row branches, the rows' chains interleave
-#pragma unroll
-        for (int u = 0; u < kRpi; ++u) row_q(u, yb + u);
-      } else {
-        for (int u = 0; u < kRpi; ++u)
-          if (yb + u < g.y1) row_q(u, yb + u);
       }
     }
     __syncthreads();
@@ -1511,16 +1523,22 @@ bool any_aux_maps(const Batch& b) {
   return false;
 }
 
-template <int PHASE>
-hipError_t gf_q_p(const Batch& b, int nblk, bool fp16, bool aux, hipStream_t s) {
+template <int NI, int PHASE>
+hipError_t gf_q_n(const Batch& b, int nblk, bool fp16, bool aux, hipStream_t s) {
   if (fp16) {
-    if (aux) hipLaunchKernelGGL((k_gf_q<PHASE, true, true>), dim3(nblk), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_gf_q<PHASE, true, false>), dim3(nblk), dim3(256), 0, s, b);
+    if (aux) hipLaunchKernelGGL((k_gf_q<NI, PHASE, true, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<NI, PHASE, true, false>), dim3(nblk), dim3(256), 0, s, b);
   } else {
-    if (aux) hipLaunchKernelGGL((k_gf_q<PHASE, false, true>), dim3(nblk), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_gf_q<PHASE, false, false>), dim3(nblk), dim3(256), 0, s, b);
+    if (aux) hipLaunchKernelGGL((k_gf_q<NI, PHASE, false, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<NI, PHASE, false, false>), dim3(nblk), dim3(256), 0, s, b);
   }
   return hipGetLastError();
+}
+
+template <int PHASE>
+hipError_t gf_q_p(const Batch& b, int nblk, int radius, bool fp16, bool aux, hipStream_t s) {
+  if (gf_strip(radius) == 192) return gf_q_n<3, PHASE>(b, nblk, fp16, aux, s);
+  return gf_q_n<2, PHASE>(b, nblk, fp16, aux, s);
 }
 
 }  // namespace
@@ -1574,17 +1592,17 @@ hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s) {
 }
 
 hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s) {
-  (void)g;
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
-  hipLaunchKernelGGL(k_gf_ab, dim3(nblk), dim3(256), 0, s, b);
+  if (gf_strip(g.radius) == 192) hipLaunchKernelGGL(k_gf_ab<3>, dim3(nblk), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL(k_gf_ab<2>, dim3(nblk), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
   const bool aux = any_aux_maps(b);
-  if (g.cb) return gf_q_p<1>(b, nblk, g.fp16, aux, s);
-  return gf_q_p<0>(b, nblk, g.fp16, aux, s);
+  if (g.cb) return gf_q_p<1>(b, nblk, g.radius, g.fp16, aux, s);
+  return gf_q_p<0>(b, nblk, g.radius, g.fp16, aux, s);
 }
 
 namespace {
