@@ -26,7 +26,7 @@ namespace hzd {
 
 // guided-filter column chunk sums (initial windows) and strip loop shape
 constexpr int kChunk = 8;                                      // rows per chunk sum
-constexpr int kMaxHead = 2 * kChunk - 2;                       // head rows when a window holds no chunk
+constexpr int kEdgeBatch = 12;                                 // head/tail rows of a window loaded per round trip
 constexpr int kChunkBatch = 8;                                 // chunk sums loaded per round trip
 constexpr int kSelVec = 4;                                     // 16-byte D vectors per lane loaded at once
 
@@ -1023,18 +1023,18 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   };
   if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
     const WindowSplit w = split_window(max(0, g.y0 - r), min(H - 1, g.y0 + r), H);
-    {
-      uint2 hv[kMaxHead], tv[kChunk - 1];
+    // the rows outside whole chunks, head then tail, kEdgeBatch per round trip
+    const int nhead = w.head_end - w.ya, nedge = nhead + (w.yb + 1 - w.tail_beg);
+    for (int e0 = 0; e0 < nedge; e0 += kEdgeBatch) {
+      uint2 ev[kEdgeBatch];
 #pragma unroll
-      for (int i = 0; i < kMaxHead; ++i)
-        hv[i] = (w.ya + i < w.head_end) ? col[(w.ya + i) * W] : make_uint2(0u, 0u);
+      for (int i = 0; i < kEdgeBatch; ++i) {
+        const int e = e0 + i;
+        const int yr = e < nhead ? w.ya + e : w.tail_beg + (e - nhead);
+        ev[i] = (e < nedge) ? col[yr * W] : make_uint2(0u, 0u);
+      }
 #pragma unroll
-      for (int i = 0; i < kChunk - 1; ++i)
-        tv[i] = (w.tail_beg + i <= w.yb) ? col[(w.tail_beg + i) * W] : make_uint2(0u, 0u);
-#pragma unroll
-      for (int i = 0; i < kMaxHead; ++i) add(hv[i]);
-#pragma unroll
-      for (int i = 0; i < kChunk - 1; ++i) add(tv[i]);
+      for (int i = 0; i < kEdgeBatch; ++i) add(ev[i]);
     }
     for (int c = 0; c < w.nch; c += kChunkBatch) {
       uint2 ca[kChunkBatch];
@@ -1223,23 +1223,20 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   long long sa = 0, sb = 0;
   if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
     const WindowSplit w = split_window(max(0, g.y0 - r), min(H - 1, g.y0 + r), H);
-    {
-      int2 hv[kMaxHead], tv[kChunk - 1];
+    // the rows outside whole chunks, head then tail, kEdgeBatch per round trip
+    const int nhead = w.head_end - w.ya, nedge = nhead + (w.yb + 1 - w.tail_beg);
+    for (int e0 = 0; e0 < nedge; e0 += kEdgeBatch) {
+      int2 ev[kEdgeBatch];
 #pragma unroll
-      for (int i = 0; i < kMaxHead; ++i)
-        hv[i] = (w.ya + i < w.head_end) ? col[(w.ya + i) * W] : make_int2(0, 0);
-#pragma unroll
-      for (int i = 0; i < kChunk - 1; ++i)
-        tv[i] = (w.tail_beg + i <= w.yb) ? col[(w.tail_beg + i) * W] : make_int2(0, 0);
-#pragma unroll
-      for (int i = 0; i < kMaxHead; ++i) {
-        sa += hv[i].x;
-        sb += hv[i].y;
+      for (int i = 0; i < kEdgeBatch; ++i) {
+        const int e = e0 + i;
+        const int yr = e < nhead ? w.ya + e : w.tail_beg + (e - nhead);
+        ev[i] = (e < nedge) ? col[yr * W] : make_int2(0, 0);
       }
 #pragma unroll
-      for (int i = 0; i < kChunk - 1; ++i) {
-        sa += tv[i].x;
-        sb += tv[i].y;
+      for (int i = 0; i < kEdgeBatch; ++i) {
+        sa += ev[i].x;
+        sb += ev[i].y;
       }
     }
     for (int c = 0; c < w.nch; c += kChunkBatch) {

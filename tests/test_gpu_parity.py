@@ -42,6 +42,26 @@ def test_ragged_shapes_realtime(shape, patch):
     compare(I, p, run_gpu(I, p), label=f"{shape} p{patch}")
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (29, 1), (5, 7), (9, 130), (130, 9), (97, 130), (33, 300)])
+@pytest.mark.parametrize("radius", [1, 32, 33, 64])
+def test_ragged_shapes_offline(shape, radius):
+    # guided-filter strips (128 output columns for r > 32, 192 for r <= 32), 8-row chunks and
+    # clipped windows at every edge, against the oracle element by element
+    h, w = shape
+    rng = np.random.default_rng(h * 7919 + w * 31 + radius)
+    I = rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=radius, color_balance=1, top_frac=0.01)
+    compare(I, p, run_gpu(I, p), label=f"off {shape} r{radius}")
+
+
+@pytest.mark.parametrize("radius", [31, 32, 33, 34])
+def test_strip_width_boundary(radius):
+    # both strip widths on a frame wider than several strips, with the window clipped
+    I = _frame(448, 72, 13)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=radius)
+    compare(I, p, run_gpu(I, p), label=f"strip r{radius}")
+
+
 def test_pitch_larger_than_row():
     I = _frame(130, 97, 9)
     for pad in (1, 5, 64):
