@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
 
 constexpr int kFinT = 512;             // threads of the final selection block
 constexpr int kFinW = kFinT / 64;
-constexpr int kFinRows = 4;            // row records loaded per round trip per thread
+constexpr int kFinRows = 4;            // row records per round trip per thread; kept in registers when H <= kFinT * kFinRows
 
 __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
   __shared__ uint32_t s_u32[kFinW];
@@ -537,6 +537,8 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
   const uint32_t hc = hist_count<kFinW>(st);
   uint32_t ties = 0, above = 0;
   unsigned long long ts[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
+  uint32_t rt[kFinRows] = {0u, 0u, 0u, 0u};  // the first kFinRows rows' tie counts and sums
+  unsigned long long rsum[kFinRows][3];
   for (int y0 = ra; y0 < rb; y0 += kFinRows) {
     RowSel r[kFinRows];
 #pragma unroll
@@ -545,6 +547,11 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
 #pragma unroll
     for (int u = 0; u < kFinRows; ++u) {
       if (y0 + u >= rb) continue;
+      if (y0 == ra) {
+        rt[u] = r[u].ties;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rsum[u][c] = r[u].tsum[c];
+      }
       ties += r[u].ties;
       above += r[u].above;
 #pragma unroll
@@ -566,16 +573,31 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
   unsigned long long part[3] = {0, 0, 0};  // this thread's tie sums over rows before the cut row
   if (rexcl < need && need <= rincl) {
     uint32_t cum = rexcl;
-    for (int yy = ra; yy < rb; ++yy) {
-      const RowSel r = fd.rowsel[yy];
-      if (cum + r.ties >= need) {
-        s_misc[2] = yy;
-        s_misc[3] = (int)cum;
-        break;
-      }
-      cum += r.ties;
+    if (rb - ra <= kFinRows) {  // from registers
 #pragma unroll
-      for (int c = 0; c < 3; ++c) part[c] += r.tsum[c];
+      for (int u = 0; u < kFinRows; ++u) {
+        if (ra + u >= rb) break;
+        if (cum + rt[u] >= need) {
+          s_misc[2] = ra + u;
+          s_misc[3] = (int)cum;
+          break;
+        }
+        cum += rt[u];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[c] += rsum[u][c];
+      }
+    } else {
+      for (int yy = ra; yy < rb; ++yy) {
+        const RowSel r = fd.rowsel[yy];
+        if (cum + r.ties >= need) {
+          s_misc[2] = yy;
+          s_misc[3] = (int)cum;
+          break;
+        }
+        cum += r.ties;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[c] += r.tsum[c];
+      }
     }
   }
   __syncthreads();
@@ -1204,7 +1226,11 @@ __device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3], unsigne
 // some frame of the launch asks for its t or J maps.
 template <int NI, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
-  __shared__ long long s_q[kRpi][2][kGfCols];
+  // two buffers, alternating by phase: a phase's scan and output read one
+  // while the next phase's column sums go to the other, so a phase needs no
+  // closing barrier (a buffer is rewritten two phases later, after every wave
+  // has passed the next phase's first barrier and so finished this output)
+  __shared__ long long s_q[2][kRpi][2][kGfCols];
   __shared__ double2 s_rows[kGfRowsMax];
   __shared__ unsigned long long s_red[4];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -1299,7 +1325,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 
   const double t0 = (double)fd.t0;
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
-  for (int yb = g.y0; yb < g.y1; yb += kRpi) {
+  for (int yb = g.y0, buf = 0; yb < g.y1; yb += kRpi, buf ^= 1) {
+    long long(&q)[kRpi][2][kGfCols] = s_q[buf];
     uint32_t curL[NI], curRG[NI], curB[NI];
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
@@ -1312,8 +1339,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         sb -= pout[u].y;
       }
       fetch(yb + kRpi + u, pin[u], pout[u]);
-      s_q[u][0][tid] = sa;
-      s_q[u][1][tid] = sb;
+      q[u][0][tid] = sa;
+      q[u][1][tid] = sb;
     }
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
@@ -1324,19 +1351,19 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     }
     __syncthreads();
     // 2 quantities x kRpi rows of scans over the 4 waves
-    wave_prefix256_rows<long long, kRpi / 2>(&s_q[wv >> 1][wv & 1][0], 2 * 2 * kGfCols);
+    wave_prefix256_rows<long long, kRpi / 2>(&q[wv >> 1][wv & 1][0], 2 * 2 * kGfCols);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int u = iu[j], y = yb + u;
       if (iok[j] && y < g.y1) {
         const int clo = iclo[j], chi = ichi[j], x = g.x0 + ic[j];
-        const double qa = i64_to_f64(s_q[u][0][chi] - (clo > 0 ? s_q[u][0][clo - 1] : 0ll));
-        const double qb = i64_to_f64(s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ll));
+        const double qa = i64_to_f64(q[u][0][chi] - (clo > 0 ? q[u][0][clo - 1] : 0ll));
+        const double qb = i64_to_f64(q[u][1][chi] - (clo > 0 ? q[u][1][clo - 1] : 0ll));
         const double in = icw_s[j] * s_rows[y - g.y0].y;
         const double G = (double)curL[j] * (1.0 / 255000.0);
-        const double q = fma(qa * in, G, qb * in);
-        float t = (float)fmin(fmax(q, t0), 1.0);
+        const double qt = fma(qa * in, G, qb * in);
+        float t = (float)fmin(fmax(qt, t0), 1.0);
         if (FP16) t = round_half(t);
         const int64_t pi = (int64_t)y * W + x;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
@@ -1359,7 +1386,6 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         }
       }
     }
-    __syncthreads();
   }
   if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
 }
