@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   if (hv) atomicAdd(&fd.st->hist[tile % kHistSlots][tid], hv);
 }
 
-// ---------------------------------------------------------------- k_select
+// ------------------------------------------------ k_select_rows, k_select_final
 // Eq. (3) with a unique top-K set: order pixels by (D descending, raster
 // index ascending) and take the first K.
 //   vstar  = largest v with #{D >= v} >= K (from the histogram)
@@ -995,29 +995,17 @@ __device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void wave_prefix256(T* row) {
-  const int lane = threadIdx.x & 63;
-  T v0 = row[4 * lane], v1 = row[4 * lane + 1], v2 = row[4 * lane + 2], v3 = row[4 * lane + 3];
-  v1 += v0;
-  v2 += v1;
-  v3 += v2;
-  const T ex = wave_incl_scan(v3) - v3;
-  row[4 * lane] = v0 + ex;
-  row[4 * lane + 1] = v1 + ex;
-  row[4 * lane + 2] = v2 + ex;
-  row[4 * lane + 3] = v3 + ex;
-}
-
 // Eq. (6), stage 1 (He et al. 2013 box form).  Each thread keeps exact u64
 // vertical window sums of L, L^2, P, L*P for its column, sliding down the
 // rows.  Rows are handled kRpi at a time: the window sums of kRpi rows go to
 // LDS, one barrier, each wave prefix-sums one quantity of all kRpi rows
-// across the strip (independent DPP scans), another barrier, and each output
-// thread forms kRpi clipped (2r+1)^2 box sums as differences of two prefixes
-// (independent FP64 chains).  Operands of the next kRpi rows are loaded while
-// the current ones are processed.  Means, var and cov are formed in FP64; a
-// and b leave as int32 fixed point with the frame's scale.
+// across the strip (independent DPP scans), another barrier, and the
+// kRpi x SW outputs of the phase, dealt NI to a thread, are formed from
+// clipped (2r+1)^2 box sums as differences of two prefixes.  Operands of the
+// next kRpi rows are loaded while the current ones are processed.  Means, var
+// and cov are formed in FP64; a and b leave as int32 fixed point with the
+// frame's scale, and their 8-row chunk sums per column (for stage 2's initial
+// windows) are merged in LDS.
 template <int NI>
 __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   __shared__ unsigned long long s_q[kRpi][4][kGfCols];
