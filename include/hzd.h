@@ -231,8 +231,12 @@ int hzd_server_stats_get(hzd_server* s, hzd_server_stats* out);
  * integers and every other reduction is integer or per pixel, so each result
  * is bit-identical for every allowed tile shape.  The table is process-wide
  * and keyed by frame size ((0, 0) = default for sizes without an entry).
- *   gf_rows  output rows per guided-filter block, a multiple of 8 in 8..256
- *            (default 16) */
+ *   gf_rows  output rows per guided-filter block, a multiple of 8 in 8..256.
+ *            With neither an entry for the size nor a (0, 0) entry, each
+ *            launch picks the smallest of 16, 32, 64, 128 at which its
+ *            frames' guided-filter blocks fit one round on the device (16 for
+ *            one 1080p frame, taller for 4K frames and large batches);
+ *            hzd_tile_config_get then reports 16. */
 typedef struct hzd_tile_config {
   int32_t gf_rows;
 } hzd_tile_config;

@@ -152,13 +152,67 @@ void tune_save(int w, int h, const hzd_tile_config& c) {
 }
 }  // namespace
 
-hzd_tile_config tile_config_for(int W, int H) {
+hzd_tile_config tile_config_for(int W, int H, bool* from_table) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   auto it = g_tune.find({W, H});
   if (it == g_tune.end()) it = g_tune.find({0, 0});
+  if (from_table) *from_table = it != g_tune.end();
   if (it != g_tune.end()) return it->second;
   return hzd_tile_config{kGfRowsDefault};
+}
+
+namespace {
+// Guided-filter blocks resident at once on the current device (4 per CU).
+int gf_round_blocks() {
+  static std::mutex mu;
+  static std::map<int, int> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1024;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = per_dev.find(dev);
+  if (it != per_dev.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  return per_dev[dev] = 4 * cus;
+}
+}  // namespace
+
+// Tile heights of an offline launch group.  Frames whose size has no table
+// entry take the smallest height in {16, 32, 64, 128} at which the group's
+// guided-filter blocks fit one round on the device: taller tiles amortise the
+// initial window of each block, shorter ones keep a single frame's launch
+// wide enough to fill the chip.  Results do not depend on the choice.
+void fit_gf_rows(Batch& b) {
+  bool fixed[kMaxBatch];
+  int n_free = 0, fixed_blocks = 0;
+  for (int i = 0; i < b.n; ++i) {
+    const FrameDev& f = b.f[i];
+    const hzd_tile_config c = tile_config_for(f.W, f.H, &fixed[i]);
+    if (fixed[i]) {
+      b.f[i].gf_rows = c.gf_rows;
+      fixed_blocks += gf_blocks(f.W, f.H, f.radius, c.gf_rows);
+    } else {
+      ++n_free;
+    }
+  }
+  if (!n_free) return;
+  const int round = gf_round_blocks();
+  int rows = 16;
+  for (; rows < 128; rows *= 2) {
+    int blocks = fixed_blocks;
+    for (int i = 0; i < b.n; ++i)
+      if (!fixed[i]) blocks += gf_blocks(b.f[i].W, b.f[i].H, b.f[i].radius, rows);
+    if (blocks <= round) break;
+  }
+  for (int i = 0; i < b.n; ++i)
+    if (!fixed[i]) b.f[i].gf_rows = rows;
 }
 
 // Fill the device descriptor of one frame; `ws` is the frame's workspace base.
@@ -336,7 +390,9 @@ void graph_evict_locked(size_t keep) {
 }  // namespace
 
 // Launch one group: replay a cached graph of its kernels when enabled.
-int launch_group(const GroupKey& g, const Batch& b, hipStream_t s) {
+int launch_group(const GroupKey& g, const Batch& bin, hipStream_t s) {
+  Batch b = bin;
+  if (g.mode == HZD_MODE_OFFLINE) fit_gf_rows(b);
   int cap;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
