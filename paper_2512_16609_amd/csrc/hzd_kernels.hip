@@ -115,19 +115,6 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   return v;
 }
 
-// Inclusive scan over a 256-thread block.  s_tmp: 4 elements of LDS.
-template <typename T>
-__device__ __forceinline__ T block_incl_scan(T v, T* s_tmp) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  T x = wave_incl_scan(v);
-  if (lane == 63) s_tmp[w] = x;
-  __syncthreads();
-  T add = 0;
-  for (int i = 0; i < w; ++i) add += s_tmp[i];
-  __syncthreads();
-  return x + add;
-}
-
 // Sum over a 256-thread block in a fixed order; every thread gets the total.
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* s_tmp) {
@@ -138,12 +125,6 @@ __device__ __forceinline__ T block_sum(T v, T* s_tmp) {
   T tot = (s_tmp[0] + s_tmp[1]) + (s_tmp[2] + s_tmp[3]);
   __syncthreads();
   return tot;
-}
-
-__device__ __forceinline__ void load_rgb(const uint8_t* p, float& r, float& g, float& b) {
-  r = (float)p[0];
-  g = (float)p[1];
-  b = (float)p[2];
 }
 
 // Eqs. (7)-(8) for one pixel: J^c = (I^c - A^c)/t + A^c clamped to [0, 255],
