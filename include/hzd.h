@@ -61,9 +61,13 @@ typedef enum { HZD_MODE_REALTIME = 0, HZD_MODE_OFFLINE = 1 } hzd_mode;
  *                pointwise expression printed as Eq. (4). */
 typedef enum { HZD_TX_HE = 0, HZD_TX_PAPER = 1 } hzd_tx;
 
-/* Precision of the transmission carried into Eq. (7).  FP32: binary32
- * throughout.  FP16: t is rounded to binary16 (and stored maps are binary16);
- * J and the gamma of Eq. (8) are still formed in binary32. */
+/* Precision of the stored transmission map.  The only floating-point map
+ * that crosses memory is the refined t of offline mode with colour balance
+ * (between the guided filter and the balanced reconstruction).  FP16 stores
+ * it as binary16, halving its traffic, and the colour-balance sums use the
+ * same rounded values.  Everywhere else t never leaves registers and is
+ * binary32 with either setting.  J and the gamma of Eq. (8) are always formed
+ * in binary32. */
 typedef enum { HZD_PREC_FP32 = 0, HZD_PREC_FP16 = 1 } hzd_prec;
 
 typedef enum {

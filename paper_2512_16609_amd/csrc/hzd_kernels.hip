@@ -1333,7 +1333,10 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         const double G = (double)curL[j] * (1.0 / 255000.0);
         const double qt = fma(qa * in, G, qb * in);
         float t = (float)fmin(fmax(qt, t0), 1.0);
-        if (FP16) t = round_half(t);
+        // FP16 applies to the stored t map (PHASE 1): the colour-balance sums here use
+        // the same binary16 value that the apply pass reads back.  The fused output
+        // (PHASE 0) keeps binary32 t, as it never leaves registers.
+        if (FP16 && PHASE == 1) t = round_half(t);
         const int64_t pi = (int64_t)y * W + x;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
         const uint32_t c = curRG[j] | (curB[j] << 16);
@@ -1445,9 +1448,8 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       } else if (TSRC == TSRC_PAPER) {
         t = tx_paper(k, fminf(fminf(I[0], I[1]), I[2]));
       } else {
-        t = tm[q][i];
+        t = tm[q][i];  // binary16 maps hold values exactly representable in binary32
       }
-      if (FP16) t = round_half(t);
       recon_pixel(rc, I, t, J, Jg);
       if (PHASE == 1) {
         acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);

@@ -261,3 +261,23 @@ def test_batch_larger_than_one_launch_group():
     torch.cuda.synchronize()
     for i, I in enumerate(frames):
         assert np.array_equal(dsts[i].cpu().numpy(), run_gpu(I, params[i], with_J=False)["out"]), i
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_parameter_sweep(case):
+    # seeded random combinations of every parameter, size and pitch, each checked against the
+    # oracle element by element (the other tests vary one or two knobs at a time)
+    rng = np.random.default_rng(9000 + case)
+    h, w = int(rng.integers(1, 200)), int(rng.integers(1, 300))
+    if h >= 16 and w >= 16:
+        I = make_frame(w, h, 9000 + case, beta=float(rng.uniform(0.5, 2.0))).I
+    else:
+        I = rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8)
+    p = P(mode=int(rng.integers(0, 2)), patch=int(rng.choice(np.arange(1, 32, 2))),
+          omega=float(rng.uniform(0.5, 1.0)), t0=float(rng.uniform(0.05, 0.3)),
+          top_frac=float(rng.uniform(0.0005, 0.05)), alpha=float(rng.uniform(0.5, 1.0)),
+          gamma=float(rng.uniform(0.8, 2.5)), gf_radius=int(rng.integers(1, 65)),
+          gf_eps=float(rng.choice([1e-6, 1e-4, 1e-3, 1e-2, 0.1])), color_balance=int(rng.integers(0, 2)),
+          tx=int(rng.integers(0, 2)), precision=int(rng.integers(0, 2)))
+    pad = int(rng.choice([0, 0, 1, 7]))
+    compare(I, p, run_gpu(I, p, pitch_pad=pad), label=f"sweep {case} {w}x{h} {p}")
