@@ -263,14 +263,10 @@ def test_batch_larger_than_one_launch_group():
         assert np.array_equal(dsts[i].cpu().numpy(), run_gpu(I, params[i], with_J=False)["out"]), i
 
 
-@pytest.mark.parametrize("case", range(40))
-def test_random_parameter_sweep(case):
-    # seeded random combinations of every parameter, size and pitch, each checked against the
-    # oracle element by element (the other tests vary one or two knobs at a time)
-    rng = np.random.default_rng(9000 + case)
+def _random_case(rng, seed):
     h, w = int(rng.integers(1, 200)), int(rng.integers(1, 300))
     if h >= 16 and w >= 16:
-        I = make_frame(w, h, 9000 + case, beta=float(rng.uniform(0.5, 2.0))).I
+        I = make_frame(w, h, seed, beta=float(rng.uniform(0.5, 2.0))).I
     else:
         I = rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8)
     p = P(mode=int(rng.integers(0, 2)), patch=int(rng.choice(np.arange(1, 32, 2))),
@@ -279,5 +275,31 @@ def test_random_parameter_sweep(case):
           gamma=float(rng.uniform(0.8, 2.5)), gf_radius=int(rng.integers(1, 65)),
           gf_eps=float(rng.choice([1e-6, 1e-4, 1e-3, 1e-2, 0.1])), color_balance=int(rng.integers(0, 2)),
           tx=int(rng.integers(0, 2)), precision=int(rng.integers(0, 2)))
+    return I, p
+
+
+@pytest.mark.parametrize("case", range(100))
+def test_random_parameter_sweep(case):
+    # seeded random combinations of every parameter, size and pitch, each checked against the
+    # oracle element by element (the other tests vary one or two knobs at a time)
+    rng = np.random.default_rng(9000 + case)
+    I, p = _random_case(rng, 9000 + case)
     pad = int(rng.choice([0, 0, 1, 7]))
-    compare(I, p, run_gpu(I, p, pitch_pad=pad), label=f"sweep {case} {w}x{h} {p}")
+    compare(I, p, run_gpu(I, p, pitch_pad=pad), label=f"sweep {case} {I.shape} {p}")
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_batch_sweep(case):
+    # random frames with random parameters in one hzd_dehaze_batch call (several launch groups,
+    # ragged block lists); every frame against the oracle
+    rng = np.random.default_rng(7000 + case)
+    cases = [_random_case(rng, 7000 + 100 * case + i) for i in range(int(rng.integers(2, 8)))]
+    srcs = [to_dev(I) for I, _ in cases]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    auxs = [hzd.make_aux(I.shape[0], I.shape[1]) for I, _ in cases]
+    hzd.dehaze_batch(srcs, dsts, P(), per_frame_params=[p for _, p in cases], auxs=auxs)
+    torch.cuda.synchronize()
+    for i, (I, p) in enumerate(cases):
+        g = {k: v.cpu().numpy() for k, v in auxs[i].items()}
+        g["out"] = dsts[i].cpu().numpy()
+        compare(I, p, g, label=f"batch sweep {case}/{i} {I.shape} {p}")
