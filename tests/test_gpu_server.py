@@ -99,3 +99,35 @@ def test_submit_rejects_wrong_size():
     assert e.value.status == hzd.HZD_E_INVAL
     st.close()
     srv.close()
+
+
+def test_random_stream_mix_equals_alone():
+    # streams with random sizes and parameters, frames interleaved so launches mix them; every
+    # served frame must equal the same frame run alone (results do not depend on batching)
+    rng = np.random.default_rng(4242)
+    specs = []
+    for i in range(7):
+        w, h = int(rng.integers(8, 400)), int(rng.integers(8, 300))
+        p = hzd.Params(mode=int(rng.integers(0, 2)), patch=int(rng.choice([1, 7, 15, 31])),
+                       gamma=float(rng.uniform(0.8, 2.5)), gf_radius=int(rng.integers(1, 65)),
+                       color_balance=int(rng.integers(0, 2)), tx=int(rng.integers(0, 2)),
+                       precision=int(rng.integers(0, 2)))
+        specs.append((w, h, p))
+    arena = sum(_need(p, w, h) for w, h, p in specs) + (1 << 20)
+    srv = hzd.Server(arena_bytes=arena, max_inflight=8, frames_per_launch=4, hip_streams=3)
+    streams = [srv.open(p, w, h) for w, h, p in specs]
+    frames = {i: [make_frame(w, h, 800 + 10 * i + k).I if min(w, h) >= 16 else
+                  rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8) for k in range(3)]
+              for i, (w, h, _) in enumerate(specs)}
+    srcs = {i: [to_dev(I) for I in frames[i]] for i in frames}
+    dsts = {i: [torch.zeros_like(s) for s in srcs[i]] for i in frames}
+    tickets = [(i, k, streams[i].submit(srcs[i][k], dsts[i][k])) for k in range(3) for i in range(len(specs))]
+    for i, k, t in tickets:
+        rc, _ = streams[i].wait(t)
+        assert rc == 0
+    for i, (w, h, p) in enumerate(specs):
+        for k in range(3):
+            assert np.array_equal(dsts[i][k].cpu().numpy(), run_gpu(frames[i][k], p, with_J=False)["out"]), (i, k)
+    for st in streams:
+        st.close()
+    srv.close()
