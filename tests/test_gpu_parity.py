@@ -303,3 +303,13 @@ def test_random_batch_sweep(case):
         g = {k: v.cpu().numpy() for k, v in auxs[i].items()}
         g["out"] = dsts[i].cpu().numpy()
         compare(I, p, g, label=f"batch sweep {case}/{i} {I.shape} {p}")
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_large_frames(case):
+    # random parameters on frames large enough for many strips and tiles
+    rng = np.random.default_rng(5100 + case)
+    _, p = _random_case(rng, 5100 + case)
+    w, h = int(rng.integers(300, 1200)), int(rng.integers(200, 800))
+    I = make_frame(w, h, 5100 + case, beta=float(rng.uniform(0.5, 2.0))).I
+    compare(I, p, run_gpu(I, p), label=f"large {case} {w}x{h} {p}")
