@@ -19,6 +19,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -100,6 +101,7 @@ struct hzd_stream {
   uint64_t next_ticket = 1;
   int queued = 0, inflight = 0;
   bool closing = false;
+  std::set<uint64_t> pending;    // submitted tickets not yet completed
   std::map<uint64_t, std::pair<int32_t, int64_t>> done;  // completed tickets not yet waited for: status, latency
   std::condition_variable cv;
 };
@@ -142,6 +144,9 @@ struct hzd_server {
 
 namespace {
 
+// Completed or failed jobs: callbacks, then (under the lock) the stream's
+// completion record and its in-flight count.  The count drops only here, so a
+// stream being closed cannot be freed while its completions are recorded.
 void finish(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
   // called without the lock: completion callbacks may submit again
   const int64_t t = now_ns();
@@ -152,6 +157,8 @@ void finish(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
   for (auto& d : done) {
     hzd_stream* st = d.first.st;
     st->done[d.first.ticket] = std::make_pair(d.second, t - d.first.t_submit);
+    st->pending.erase(d.first.ticket);
+    st->inflight--;
     st->cv.notify_all();
   }
   done.clear();
@@ -216,7 +223,6 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
   if (rc != HZD_OK) {
     for (auto& j : L.jobs) {
       j.st->slot_busy[j.slot] = false;
-      j.st->inflight--;
       s->stats.failed++;
       done.emplace_back(j, rc);
     }
@@ -241,7 +247,6 @@ bool reap(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     for (auto& j : L.jobs) {
       j.st->slot_busy[j.slot] = false;
       j.st->last_slot = j.slot;
-      j.st->inflight--;
       if (status == HZD_OK) s->stats.completed++;
       else s->stats.failed++;
       done.emplace_back(j, status);
@@ -298,10 +303,11 @@ int hzd_server_create(const hzd_server_config* cfg, hzd_server** out) {
   s->arena.init(cfg->arena_bytes);
   (void)hipSetDevice(cfg->device);
   for (int i = 0; i < cfg->hip_streams; ++i) {
-    hipStream_t hs;
-    hipEvent_t ev;
+    hipStream_t hs = nullptr;
+    hipEvent_t ev = nullptr;
     if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      if (hs) (void)hipStreamDestroy(hs);
       for (auto h : s->hstreams) (void)hipStreamDestroy(h);
       for (auto e : s->events) (void)hipEventDestroy(e);
       delete s;
@@ -325,6 +331,7 @@ int hzd_server_destroy(hzd_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     for (auto& j : s->queue) {
       j.st->queued--;
+      j.st->inflight++;  // finish() records the cancellation and drops it again
       cancelled.emplace_back(j, HZD_E_CLOSED);
     }
     s->queue.clear();
@@ -397,6 +404,7 @@ int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, vo
   j.ticket = st->next_ticket++;
   j.t_submit = now_ns();
   st->queued++;
+  st->pending.insert(j.ticket);
   s->queue.push_back(j);
   s->stats.submitted++;
   if (ticket) *ticket = j.ticket;
@@ -409,8 +417,8 @@ int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns, int64_t
   if (!st) return fail(HZD_E_INVAL, "stream is NULL");
   hzd_server* s = st->srv;
   std::unique_lock<std::mutex> lk(s->mu);
-  if (ticket == 0 || ticket >= st->next_ticket) return fail(HZD_E_INVAL, "unknown ticket %llu",
-                                                            (unsigned long long)ticket);
+  if (ticket == 0 || ticket >= st->next_ticket || (!st->pending.count(ticket) && !st->done.count(ticket)))
+    return fail(HZD_E_INVAL, "unknown or already collected ticket %llu", (unsigned long long)ticket);
   auto ready = [&] { return st->done.count(ticket) > 0; };
   if (timeout_ns < 0) {
     st->cv.wait(lk, ready);

@@ -131,3 +131,17 @@ def test_random_stream_mix_equals_alone():
     for st in streams:
         st.close()
     srv.close()
+
+
+def test_wait_twice_on_a_ticket_is_an_error():
+    srv = hzd.Server(arena_bytes=_need(RT, 160, 120) + (1 << 20))
+    st = srv.open(RT, 160, 120)
+    src = to_dev(make_frame(160, 120, 3).I)
+    dst = torch.zeros_like(src)
+    t = st.submit(src, dst)
+    rc, _ = st.wait(t)
+    assert rc == 0
+    assert st.wait(t)[0] == hzd.HZD_E_INVAL        # already collected: an error, not a wait forever
+    assert st.wait(t + 100)[0] == hzd.HZD_E_INVAL  # never issued
+    st.close()
+    srv.close()
