@@ -214,8 +214,9 @@ int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, vo
                       uint64_t* ticket);
 /* Wait until `ticket` completes (timeout_ns < 0: forever).  Returns the
  * frame's status, or HZD_E_TIMEOUT.  latency_ns (nullable): nanoseconds from
- * submit to the scheduler observing completion.  A ticket can be waited for
- * once. */
+ * submit to the scheduler observing completion.  A ticket can be collected
+ * once: waiting again for it (or for a ticket never issued) returns
+ * HZD_E_INVAL at once. */
 int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns, int64_t* latency_ns);
 /* Per-stream device state as of the last completed frame: A (3 floats) and
  * {K, vstar, cutoff}; host pointers, either may be NULL. */
