@@ -265,8 +265,10 @@ int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspa
  * when callers reuse buffers (frame pools, server slots).  capacity = 0
  * turns the cache off (every call launches its kernels directly); the
  * default is 0.  Calls on the null stream and calls made while profiling is
- * enabled always launch directly.  Shrinking the cache synchronises the
- * device before destroying evicted graphs. */
+ * enabled always launch directly.  A call made while the caller captures
+ * hip_stream launches directly into the caller's graph.  Graphs are keyed
+ * by device too.  Shrinking the cache synchronises the current device
+ * before destroying evicted graphs. */
 int hzd_graph_cache(int32_t capacity);
 
 /* ------------------------------------------------------------ profiling
@@ -275,7 +277,8 @@ int hzd_graph_cache(int32_t capacity);
  * pipeline is bracketed by a pair of events.  hzd_profile_read synchronises
  * the recorded events, adds each launch's elapsed time to its stage entry
  * and returns up to `cap` entries (stage name, launches, total ms);
- * reset != 0 clears the totals afterwards. */
+ * reset != 0 clears the totals afterwards.  Launches into a graph that the
+ * caller is capturing are not timed. */
 typedef struct hzd_profile_entry {
   char name[24];
   uint64_t launches;

@@ -319,10 +319,10 @@ hipEvent_t prof_event() {
   return e;
 }
 
-// Launch one stage; with profiling on, bracket it with events on its stream.
+// Launch one stage; with `prof`, bracket it with events on its stream.
 template <typename F>
-int stage(const char* name, hipStream_t s, F&& launch) {
-  if (!g_prof_on.load(std::memory_order_relaxed)) return check(launch(), name);
+int stage(bool prof, const char* name, hipStream_t s, F&& launch) {
+  if (!prof) return check(launch(), name);
   hipEvent_t a = prof_event(), b = prof_event();
   if (a) (void)hipEventRecord(a, s);
   const int rc = check(launch(), name);
@@ -338,28 +338,29 @@ int stage(const char* name, hipStream_t s, F&& launch) {
 }
 }  // namespace
 
-// The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames.
-int run_group(const GroupKey& g, const Batch& b, hipStream_t s) {
+// The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames;
+// `prof` brackets every launch with timing events.
+int run_group(const GroupKey& g, const Batch& b, hipStream_t s, bool prof) {
   int rc;
-  // with profiling on, an empty event pair measures what bracketing itself costs
-  if (g_prof_on.load(std::memory_order_relaxed)) (void)stage("event_pair", s, [] { return hipSuccess; });
-  if ((rc = stage("init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
+  // an empty event pair measures what bracketing itself costs
+  if (prof) (void)stage(prof, "event_pair", s, [] { return hipSuccess; });
+  if ((rc = stage(prof, "init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
   const bool he = g.tx == HZD_TX_HE;
-  if ((rc = stage("dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
-  if ((rc = stage("select", s, [&] { return launch_select(b, s); })) != HZD_OK) return rc;
+  if ((rc = stage(prof, "dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
+  if ((rc = stage(prof, "select", s, [&] { return launch_select(b, s); })) != HZD_OK) return rc;
   if (g.mode == HZD_MODE_OFFLINE) {
-    if ((rc = stage("gf_prep", s, [&] { return launch_gf_prep(b, g, s); })) != HZD_OK) return rc;
-    if ((rc = stage("gf_ab", s, [&] { return launch_gf_ab(b, g, s); })) != HZD_OK) return rc;
-    if ((rc = stage("gf_q", s, [&] { return launch_gf_q(b, g, s); })) != HZD_OK) return rc;
-    if (g.cb && (rc = stage("recon_apply", s, [&] { return launch_recon(b, g, TSRC_TMAP, 2, s); })) != HZD_OK)
+    if ((rc = stage(prof, "gf_prep", s, [&] { return launch_gf_prep(b, g, s); })) != HZD_OK) return rc;
+    if ((rc = stage(prof, "gf_ab", s, [&] { return launch_gf_ab(b, g, s); })) != HZD_OK) return rc;
+    if ((rc = stage(prof, "gf_q", s, [&] { return launch_gf_q(b, g, s); })) != HZD_OK) return rc;
+    if (g.cb && (rc = stage(prof, "recon_apply", s, [&] { return launch_recon(b, g, TSRC_TMAP, 2, s); })) != HZD_OK)
       return rc;
   } else {
     const int tsrc = he ? TSRC_HE : TSRC_PAPER;
     if (g.cb) {
-      if ((rc = stage("recon_sums", s, [&] { return launch_recon(b, g, tsrc, 1, s); })) != HZD_OK) return rc;
-      if ((rc = stage("recon_apply", s, [&] { return launch_recon(b, g, tsrc, 2, s); })) != HZD_OK) return rc;
+      if ((rc = stage(prof, "recon_sums", s, [&] { return launch_recon(b, g, tsrc, 1, s); })) != HZD_OK) return rc;
+      if ((rc = stage(prof, "recon_apply", s, [&] { return launch_recon(b, g, tsrc, 2, s); })) != HZD_OK) return rc;
     } else {
-      if ((rc = stage("recon", s, [&] { return launch_recon(b, g, tsrc, 0, s); })) != HZD_OK) return rc;
+      if ((rc = stage(prof, "recon", s, [&] { return launch_recon(b, g, tsrc, 0, s); })) != HZD_OK) return rc;
     }
   }
   return HZD_OK;
@@ -398,13 +399,26 @@ int launch_group(const GroupKey& g, const Batch& bin, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     cap = g_graph_cap;
   }
-  if (cap == 0 || s == nullptr || g_prof_on.load(std::memory_order_relaxed)) return run_group(g, b, s);
+  const bool prof = g_prof_on.load(std::memory_order_relaxed);
+  if (s == nullptr) return run_group(g, b, s, prof);
+  if (cap == 0 && !prof) return run_group(g, b, s, false);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
     (void)hipGetLastError();
-    return run_group(g, b, s);  // the caller is capturing: our launches join its graph
+    // the caller is capturing: our launches join its graph, without timing
+    // events, which would complete only when that graph runs
+    return run_group(g, b, s, false);
   }
-  std::string key(reinterpret_cast<const char*>(&g), sizeof(g));
+  if (cap == 0 || prof) return run_group(g, b, s, prof);
+  // A graph is bound to the device it was captured on, and a freed device
+  // address can come back on another device: the device is part of the key.
+  int dev = -1;
+  if (hipStreamGetDevice(s, &dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return run_group(g, b, s, false);
+  }
+  std::string key(reinterpret_cast<const char*>(&dev), sizeof(dev));
+  key.append(reinterpret_cast<const char*>(&g), sizeof(g));
   key.append(reinterpret_cast<const char*>(&b), sizeof(b));
   hipGraphExec_t exec = nullptr;
   {
@@ -418,7 +432,7 @@ int launch_group(const GroupKey& g, const Batch& bin, hipStream_t s) {
   if (!exec) {
     int rc = check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     if (rc) return rc;
-    const int rrc = run_group(g, b, s);
+    const int rrc = run_group(g, b, s, false);
     hipGraph_t graph = nullptr;
     rc = check(hipStreamEndCapture(s, &graph), "end capture");
     if (rrc) {

@@ -19,7 +19,7 @@ size_t frame_ws_bytes(const hzd_params& p, int W, int H);
 FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws);
 hzd_tile_config tile_config_for(int W, int H, bool* from_table = nullptr);
 void fit_gf_rows(Batch& b);
-int run_group(const GroupKey& g, const Batch& b, hipStream_t s);
+int run_group(const GroupKey& g, const Batch& b, hipStream_t s, bool prof);
 int launch_group(const GroupKey& g, const Batch& b, hipStream_t s);
 int check(hipError_t e, const char* what);
 

@@ -231,6 +231,51 @@ def test_graph_replay_matches_direct_launch():
         hzd.graph_cache(0)
 
 
+def test_stage_profiling_times_every_launch():
+    I = _frame(320, 240, 51)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
+    ref = run_gpu(I, p, with_J=False)["out"]
+    hzd.profile_read(reset=True)
+    hzd.profile_enable(True)
+    try:
+        for _ in range(2):
+            out = run_gpu(I, p, with_J=False)["out"]
+            assert np.array_equal(out, ref)
+        stages = hzd.profile_read(reset=True)
+    finally:
+        hzd.profile_enable(False)
+    for name in ("event_pair", "init", "dark", "select", "gf_prep", "gf_ab", "gf_q", "recon_apply"):
+        launches, ms = stages[name]
+        assert launches == 2 and ms >= 0.0, (name, stages[name])
+    assert set(stages) == {"event_pair", "init", "dark", "select", "gf_prep", "gf_ab", "gf_q", "recon_apply"}
+
+
+def test_caller_graph_capture_replays_and_is_not_timed():
+    # a call made while the caller captures its stream joins the caller's graph; profiling
+    # stays off for it (its events would complete only when the graph runs)
+    I1, I2 = _frame(320, 240, 52), _frame(320, 240, 53)
+    p = P(mode=hzd.MODE_OFFLINE, gf_radius=16, color_balance=1)
+    ref1, ref2 = run_gpu(I1, p, with_J=False)["out"], run_gpu(I2, p, with_J=False)["out"]
+    src, dst = to_dev(I1), torch.zeros((240, 320, 3), dtype=torch.uint8, device="cuda")
+    ws = hzd.alloc_workspace(hzd.workspace_size(p, [(240, 320)]))
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    hzd.profile_read(reset=True)
+    hzd.profile_enable(True)
+    try:
+        with torch.cuda.graph(graph, stream=stream):
+            hzd.dehaze_frame(src, dst, p, workspace=ws, stream=stream)
+        assert hzd.profile_read(reset=True) == {}
+    finally:
+        hzd.profile_enable(False)
+    for rep in range(4):
+        src.copy_(to_dev(I1 if rep % 2 == 0 else I2))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(dst.cpu().numpy(), ref1 if rep % 2 == 0 else ref2), rep
+
+
 def test_uneven_batch_each_size_matches_oracle():
     # the 64-frame configuration's four sizes in one batch call (offline r=60, no colour balance);
     # every frame is checked element by element against the FP64 oracle
