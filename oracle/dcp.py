@@ -36,7 +36,12 @@ parameter or a documented choice of the GPU library):
   * J is clamped to [0, 255] before the gamma of Eq. (8);
   * colour balance is gray-world on the gamma-corrected image:
     g_c = mean(mu) / mu_c (g_c = 1 when mu_c = 0), J_c <- min(255, g_c J_c);
-  * the output is rounded half to even and saturated to uint8.
+  * the output is rounded half to even and saturated to uint8;
+  * the optional resize of Sec. V step 1 (the paper names no interpolation) is
+    bilinear sampling with pixel centres aligned, source coordinates clamped
+    below at 0 and taps clamped at the last row/column, weights rounded to
+    multiples of 2^-11 (half up) and the result rounded half up to uint8;
+    every step is exact integer arithmetic.
 All functions are pinned by tests against brute force, closed forms,
 invariants or independent library routines (scipy.ndimage).
 """
@@ -66,9 +71,57 @@ class Params:
     gf_eps: float = 1e-3           # guided-filter regulariser epsilon
     color_balance: bool = False
     tx: str = "he"                 # "he" (dark(I/A)) or "paper" (literal Eq. (4))
+    resize_width: int = 0          # Sec. V step 1 target size; 0 x 0 = native size
+    resize_height: int = 0
 
     def f(self, name):
         return f32(getattr(self, name))
+
+
+# ------------------------------------------------------------- Sec. V, step 1
+RESIZE_BITS = 11   # fractional bits of the bilinear weights
+
+
+def resize_taps(n_in: int, n_out: int):
+    """Source taps and weights of bilinear resampling along one axis.
+
+    Output sample i sits at source coordinate s = (i + 1/2) n_in / n_out - 1/2
+    (pixel centres aligned), with s < 0 taken as 0.  Its taps are i0 = floor(s)
+    and i1 = min(i0 + 1, n_in - 1); the weight of i1 is the fractional part of
+    s rounded half up to a multiple of 2^-RESIZE_BITS, returned as an integer
+    numerator w1 (the weight of i0 is 2^RESIZE_BITS - w1).  s is carried as
+    the exact rational ((2i + 1) n_in - n_out) / (2 n_out).
+    """
+    i = np.arange(n_out, dtype=np.int64)
+    num = np.maximum((2 * i + 1) * n_in - n_out, 0)
+    den = 2 * n_out
+    i0 = num // den
+    frac = num - i0 * den
+    w1 = (frac * (1 << (RESIZE_BITS + 1)) + den) // (2 * den)
+    i1 = np.minimum(i0 + 1, n_in - 1)
+    return i0, i1, w1
+
+
+def resize(I: np.ndarray, width: int, height: int) -> np.ndarray:
+    """Sec. V step 1: the frame resized to width x height (uint8 RGB).
+
+    Bilinear interpolation with the taps and weights of resize_taps, first
+    along rows then along columns, in exact integers; the value
+    sum w_y w_x I / 2^(2 RESIZE_BITS) is rounded half up.
+    """
+    assert I.dtype == np.uint8 and width >= 1 and height >= 1
+    h, w, _ = I.shape
+    x0, x1, wx = resize_taps(w, width)
+    y0, y1, wy = resize_taps(h, height)
+    one = 1 << RESIZE_BITS
+    X = I.astype(np.int64)
+    wx = wx[None, :, None]
+    h0 = (one - wx) * X[y0][:, x0] + wx * X[y0][:, x1]
+    h1 = (one - wx) * X[y1][:, x0] + wx * X[y1][:, x1]
+    wy = wy[:, None, None]
+    v = (one - wy) * h0 + wy * h1
+    half = 1 << (2 * RESIZE_BITS - 1)
+    return ((v + half) >> (2 * RESIZE_BITS)).astype(np.uint8)
 
 
 # ------------------------------------------------------------- Sec. IV-A
@@ -294,14 +347,20 @@ class Result:
 
 
 def dehaze(I: np.ndarray, p: Params, A_inject=None) -> Result:
-    """One frame through the per-frame algorithm of Sec. V (steps 2-7).
+    """One frame through the per-frame algorithm of Sec. V (steps 1-7).
 
     I: (H, W, 3) uint8 RGB, or float64 on the 0..255 scale (for the
     exact-recovery checks; then A may be injected instead of estimated).
+    With resize_width/resize_height set, step 1 resizes I first and every
+    later step (and the output) is at that size.
     """
+    aux = {}
+    if p.resize_width or p.resize_height:
+        I = resize(I, p.resize_width, p.resize_height)
+        aux["I"] = I
     m = channel_min(I)
     D = erode(m, p.patch)
-    aux = {"m": m, "D": D}
+    aux.update(m=m, D=D)
     if A_inject is None:
         air = airlight(I, D, p.top_frac, p.alpha)
         A = air.A

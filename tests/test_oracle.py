@@ -360,3 +360,68 @@ def test_pipeline_offline_runs_and_bounds():
     t = res.aux["t"]
     assert t.min() >= float(np.float32(0.1)) and t.max() <= 1.0
     assert res.out.dtype == np.uint8 and res.out.shape == fr.I.shape
+
+
+# ------------------------------------------------------------ resize (Sec. V step 1)
+RESIZE_CASES = [((16, 12), (16, 12)), ((16, 12), (8, 6)), ((1920, 1080), (640, 480)),
+                ((37, 23), (11, 7)), ((11, 7), (37, 23)), ((9, 5), (1, 1)), ((1, 1), (5, 3)),
+                ((1, 9), (4, 2)), ((64, 48), (63, 47)), ((40, 30), (40, 31))]
+
+
+def test_resize_same_size_is_identity():
+    I = rng(71).integers(0, 256, (23, 37, 3), dtype=np.uint8)
+    assert np.array_equal(oracle.resize(I, 37, 23), I)
+
+
+def test_resize_halving_is_the_rounded_block_mean():
+    # at ratio 2 every output sits midway between four inputs: weights 1/2, 1/2
+    I = rng(72).integers(0, 256, (12, 16, 3), dtype=np.uint8)
+    block = I.astype(np.int64).reshape(6, 2, 8, 2, 3).sum(axis=(1, 3))
+    assert np.array_equal(oracle.resize(I, 8, 6), ((block + 2) >> 2).astype(np.uint8))
+
+
+def test_resize_constant_frame_stays_constant():
+    I = np.full((21, 34, 3), (7, 130, 255), dtype=np.uint8)
+    for w, h in [(5, 4), (34, 21), (70, 50), (1, 1)]:
+        assert np.all(oracle.resize(I, w, h) == np.array([7, 130, 255], dtype=np.uint8))
+
+
+@pytest.mark.parametrize("src,dst", RESIZE_CASES)
+def test_resize_matches_library_bilinear(src, dst):
+    # torch's bilinear interpolation (pixel centres aligned, no antialiasing) in
+    # float64 is the exact value the oracle approximates: weights rounded to
+    # 2^-11 move each one-axis interpolation by at most 255 * 2^-12, so the
+    # value before the final rounding is within 2 * 255 * 2^-12 < 0.125 of it
+    import torch
+    w, h = src
+    I = rng(73 + w + 1000 * h).integers(0, 256, (h, w, 3), dtype=np.uint8)
+    ref = torch.nn.functional.interpolate(
+        torch.from_numpy(I.astype(np.float64)).permute(2, 0, 1)[None], size=(dst[1], dst[0]),
+        mode="bilinear", align_corners=False, antialias=False)[0].permute(1, 2, 0).numpy()
+    out = oracle.resize(I, dst[0], dst[1]).astype(np.float64)
+    assert out.shape == ref.shape
+    assert np.max(np.abs(out - ref)) <= 0.5 + 0.125
+    # away from a rounding boundary the integer result is the rounded exact value
+    safe = np.abs(ref - np.floor(ref) - 0.5) > 0.125
+    assert np.array_equal(out[safe], np.floor(ref[safe] + 0.5))
+
+
+def test_resize_taps_bruteforce():
+    # taps and weights from the coordinate formula evaluated in exact rationals
+    from fractions import Fraction
+    for n_in, n_out in [(1920, 640), (7, 3), (3, 7), (1, 4), (5, 1), (480, 1080)]:
+        i0, i1, w1 = oracle.resize_taps(n_in, n_out)
+        for i in range(n_out):
+            s = max(Fraction(2 * i + 1, 2) * Fraction(n_in, n_out) - Fraction(1, 2), Fraction(0))
+            f0 = math.floor(s)
+            assert i0[i] == f0 and i1[i] == min(f0 + 1, n_in - 1)
+            assert w1[i] == math.floor((s - f0) * 2048 + Fraction(1, 2))
+
+
+def test_pipeline_with_resize_runs_at_the_target_size():
+    I = make_frame(96, 64, 9).I
+    p = Params(resize_width=48, resize_height=40)
+    r = oracle.dehaze(I, p)
+    assert r.out.shape == (40, 48, 3)
+    assert np.array_equal(r.aux["I"], oracle.resize(I, 48, 40))
+    assert np.array_equal(r.out, oracle.dehaze(oracle.resize(I, 48, 40), Params()).out)
