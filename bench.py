@@ -232,7 +232,7 @@ def serving_mix(hzd, torch, dev, seconds: float, scales, pool: int = 4):
             I = quantize_u8(haze(J, np.exp(-beta * d), A, noise_rng=np.random.Generator(np.random.PCG64((sp.seed, k)))))
             src = torch.from_numpy(I).to(dev)
             dst = torch.empty_like(src)
-            fl.append((src, dst, hzd._frame_struct(src, dst)))
+            fl.append((src, dst, hzd._frame_struct(src, dst, p_off if sp.offline else p_rt)))
         frames.append(fl)
         streams.append(srv.open(p_off if sp.offline else p_rt, sp.width, sp.height))
     torch.cuda.synchronize()

@@ -7,6 +7,7 @@
  * by estimating the global airlight A and the transmission t.  One frame runs
  * the paper's per-frame steps (Sec. V):
  *
+ *   optional resize to a working size                        Sec. V, step 1
  *   channel minimum + patch erosion -> dark channel D        Sec. IV-A, Eq. (2)
  *   fractional top-pixel average    -> airlight A            Sec. IV-B, Eq. (3)
  *   transmission with lower bound   -> t                     Sec. IV-C, Eqs. (4)-(5)
@@ -37,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HZD_ABI_VERSION 1
+#define HZD_ABI_VERSION 2
 
 typedef enum {
   HZD_OK = 0,
@@ -92,7 +93,21 @@ typedef enum {
  *                  the BT.601 luma of the hazy input scaled to [0, 1]
  *   color_balance  0/1: gray-world gains on the gamma-corrected image (Sec. IV-E)
  *   tx             hzd_tx
- *   precision      hzd_prec */
+ *   precision      hzd_prec
+ *   resize_width, resize_height
+ *                  working size of Sec. V step 1 (paper default 640 x 480):
+ *                  both 0 = process frames at their own size; else both in
+ *                  1..16384, and every frame is first resampled to that size
+ *                  (input width and height <= 32768).  The resampling is
+ *                  bilinear with pixel centres aligned: output sample i of an
+ *                  axis of n_in inputs and n_out outputs sits at source
+ *                  coordinate s = (i + 1/2) n_in / n_out - 1/2, taken as 0 when
+ *                  negative, between taps floor(s) and min(floor(s) + 1,
+ *                  n_in - 1); the weight of the second tap is frac(s) rounded
+ *                  half up to a multiple of 2^-11, and the weighted sum (rows,
+ *                  then columns) is rounded half up to uint8, all in exact
+ *                  integers.  Every later step, dst and the aux outputs are at
+ *                  the working size. */
 typedef struct hzd_params {
   uint32_t size;
   int32_t mode;
@@ -107,10 +122,14 @@ typedef struct hzd_params {
   int32_t color_balance;
   int32_t tx;
   int32_t precision;
+  int32_t resize_width;
+  int32_t resize_height;
 } hzd_params;
 
 /* One frame: device pointers and geometry (see the conventions above).
- * width, height >= 1 and width * height < 2^31.  src and dst must not overlap.
+ * width, height (>= 1, width * height < 2^31) are the input size; dst and
+ * the aux outputs have the output size, which is the input size unless the
+ * frame's params resize it.  src and dst must not overlap.
  * params: NULL = the params given to the call; in a batch, a per-frame
  * override (host pointer, read during the call only). */
 typedef struct hzd_frame {
@@ -124,6 +143,7 @@ typedef struct hzd_frame {
 } hzd_frame;
 
 /* Optional per-frame device outputs for inspection (NULL = not written).
+ * width and height below are the output size.
  *   A_out    3 floats: A^c of Eq. (3) on the 0..255 scale
  *   sel_out  3 int32: {K, vstar, cutoff}; the selected set of Eq. (3) is
  *            {D > vstar} U {D == vstar and raster index <= cutoff}

@@ -26,6 +26,7 @@ MODE_REALTIME, MODE_OFFLINE = 0, 1
 TX_HE, TX_PAPER = 0, 1
 PREC_FP32, PREC_FP16 = 0, 1
 PRESET_REALTIME, PRESET_OFFLINE, PRESET_PAPER_REALTIME = 0, 1, 2
+ABI_VERSION = 2
 
 
 class HzdError(RuntimeError):
@@ -39,7 +40,8 @@ class hzd_params(ctypes.Structure):
                 ("omega", ctypes.c_float), ("t0", ctypes.c_float), ("top_frac", ctypes.c_float),
                 ("alpha", ctypes.c_float), ("gamma", ctypes.c_float), ("gf_radius", ctypes.c_int32),
                 ("gf_eps", ctypes.c_float), ("color_balance", ctypes.c_int32), ("tx", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("resize_width", ctypes.c_int32),
+                ("resize_height", ctypes.c_int32)]
 
 
 class hzd_frame(ctypes.Structure):
@@ -128,6 +130,9 @@ def lib():
                 fn = getattr(L, name)
                 fn.restype = res
                 fn.argtypes = args
+            if L.hzd_abi_version() != ABI_VERSION:
+                raise ImportError(f"{LIB_PATH} has ABI {L.hzd_abi_version()}, the binding expects "
+                                  f"{ABI_VERSION}; rebuild it")
             _lib = L
     return _lib
 
@@ -157,22 +162,31 @@ class Params:
     color_balance: int = 0
     tx: int = TX_HE
     precision: int = PREC_FP32
+    resize_width: int = 0     # Sec. V step 1 working size; 0 x 0 = the frame's own size
+    resize_height: int = 0
 
     def c(self) -> hzd_params:
         return hzd_params(ctypes.sizeof(hzd_params), self.mode, self.patch, self.omega, self.t0,
                           self.top_frac, self.alpha, self.gamma, self.gf_radius, self.gf_eps,
-                          int(self.color_balance), self.tx, self.precision)
+                          int(self.color_balance), self.tx, self.precision, self.resize_width,
+                          self.resize_height)
+
+    def output_shape(self, h: int, w: int) -> tuple:
+        """(height, width) of the output of a frame of input shape (h, w)."""
+        if self.resize_width or self.resize_height:
+            return (self.resize_height, self.resize_width)
+        return (h, w)
 
     @staticmethod
     def preset(preset: int) -> "Params":
         p = hzd_params()
         _check(lib().hzd_params_default(ctypes.byref(p), preset), "hzd_params_default")
         return Params(p.mode, p.patch, p.omega, p.t0, p.top_frac, p.alpha, p.gamma, p.gf_radius,
-                      p.gf_eps, p.color_balance, p.tx, p.precision)
+                      p.gf_eps, p.color_balance, p.tx, p.precision, p.resize_width, p.resize_height)
 
 
 # ------------------------------------------------------------------ frames
-def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params_ptr=None) -> hzd_frame:
+def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params: "Params", params_ptr=None) -> hzd_frame:
     for name, t in (("src", src), ("dst", dst)):
         if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3:
             raise ValueError(f"{name} must be a uint8 (H, W, 3) tensor")
@@ -180,11 +194,12 @@ def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params_ptr=None) -> hzd_
             raise ValueError(f"{name} must be on the GPU")
         if t.stride(2) != 1 or t.stride(1) != 3:
             raise ValueError(f"{name} must have packed RGB rows (strides (pitch, 3, 1))")
-    if src.shape != dst.shape:
-        raise ValueError("src and dst shapes differ")
     h, w = int(src.shape[0]), int(src.shape[1])
+    ho, wo = params.output_shape(h, w)
+    if tuple(dst.shape[:2]) != (ho, wo):
+        raise ValueError(f"dst shape {tuple(dst.shape[:2])} != output shape {(ho, wo)}")
     f = hzd_frame(src.data_ptr(), src.stride(0) if h > 1 else 3 * w, dst.data_ptr(),
-                  dst.stride(0) if h > 1 else 3 * w, w, h, params_ptr)
+                  dst.stride(0) if ho > 1 else 3 * wo, w, h, params_ptr)
     return f
 
 
@@ -240,8 +255,9 @@ def _stream_handle(stream) -> int:
 
 def dehaze_frame(src: torch.Tensor, dst: torch.Tensor, params: Params, aux: dict | None = None,
                  workspace: torch.Tensor | None = None, stream=None) -> None:
-    """hzd_dehaze_frame on a (H, W, 3) uint8 device tensor (asynchronous, stream-ordered)."""
-    f = _frame_struct(src, dst)
+    """hzd_dehaze_frame on a (H, W, 3) uint8 device tensor (asynchronous, stream-ordered);
+    dst has the output shape params.output_shape(H, W)."""
+    f = _frame_struct(src, dst, params)
     pc = params.c()
     if workspace is None:
         workspace = alloc_workspace(workspace_size(params, [(src.shape[0], src.shape[1])]), src.device)
@@ -258,7 +274,8 @@ def dehaze_batch(srcs, dsts, params: Params, per_frame_params=None, auxs=None,
     pcs = [p.c() for p in per_frame_params] if per_frame_params else None
     arr = (hzd_frame * n)()
     for i in range(n):
-        arr[i] = _frame_struct(srcs[i], dsts[i], ctypes.pointer(pcs[i]) if pcs else None)
+        pi = per_frame_params[i] if per_frame_params else params
+        arr[i] = _frame_struct(srcs[i], dsts[i], pi, ctypes.pointer(pcs[i]) if pcs else None)
     aarr = None
     if auxs is not None:
         aarr = (hzd_frame_aux * n)()
@@ -293,7 +310,7 @@ class Server:
         pc = params.c()
         _check(lib().hzd_stream_open(self.handle, ctypes.byref(pc), width, height, ctypes.byref(h)),
                "hzd_stream_open")
-        return Stream(self, h, width, height)
+        return Stream(self, h, width, height, params)
 
     def stats(self) -> dict:
         s = hzd_server_stats()
@@ -313,12 +330,13 @@ class Server:
 
 
 class Stream:
-    def __init__(self, server: Server, handle, width, height):
+    def __init__(self, server: Server, handle, width, height, params: Params):
         self.server, self.handle, self.width, self.height = server, handle, width, height
+        self.params = params
 
     def submit(self, src: torch.Tensor, dst: torch.Tensor) -> int:
         """Queue one frame; no completion callback (completion and latency come from wait())."""
-        f = _frame_struct(src, dst)
+        f = _frame_struct(src, dst, self.params)
         t = ctypes.c_uint64(0)
         rc = lib().hzd_stream_submit(self.handle, ctypes.byref(f), DONE_FN(), None, ctypes.byref(t))
         _check(rc, "hzd_stream_submit")
@@ -363,7 +381,7 @@ class FrameCall:
 
     def __init__(self, src, dst, params: Params, workspace, aux: dict | None = None, stream=None):
         self._keep = (src, dst, workspace, aux)
-        self.f = _frame_struct(src, dst)
+        self.f = _frame_struct(src, dst, params)
         self.pc = params.c()
         a = _aux_struct(aux)
         self.aux = ctypes.pointer(a) if a is not None else None
@@ -396,7 +414,7 @@ def tile_config_get(width: int, height: int) -> int:
 
 def autotune(src, dst, params: Params, workspace=None, reps: int = 20, stream=None) -> int:
     """hzd_autotune on one frame; returns the chosen gf_rows (now in the table)."""
-    f = _frame_struct(src, dst)
+    f = _frame_struct(src, dst, params)
     pc = params.c()
     if workspace is None:
         workspace = alloc_workspace(workspace_size(params, [(src.shape[0], src.shape[1])]), src.device)

@@ -62,28 +62,49 @@ int validate_params(const hzd_params* p) {
       return fail(HZD_E_UNSUPPORTED, "gf_radius %d > %d", p->gf_radius, kMaxRadius);
     if (!in_range(p->gf_eps, 1e-8f, 1.0f)) return fail(HZD_E_INVAL, "gf_eps %g outside [1e-8,1]", p->gf_eps);
   }
+  if (p->resize_width != 0 || p->resize_height != 0) {
+    if (p->resize_width < 1 || p->resize_height < 1 || p->resize_width > kResizeMaxOut ||
+        p->resize_height > kResizeMaxOut)
+      return fail(HZD_E_INVAL, "resize %dx%d: both 0 or both in 1..%d", p->resize_width, p->resize_height,
+                  kResizeMaxOut);
+  }
   return HZD_OK;
 }
 
-static bool ranges_overlap(const hzd_frame& f) {
+void output_size(const hzd_params& p, int W, int H, int* Wo, int* Ho) {
+  const bool rs = p.resize_width != 0;
+  *Wo = rs ? p.resize_width : W;
+  *Ho = rs ? p.resize_height : H;
+}
+
+int validate_size(const hzd_params& p, int W, int H, int idx) {
+  if (W < 1 || H < 1) return fail(HZD_E_INVAL, "frame %d: size %dx%d", idx, W, H);
+  if ((int64_t)W * (int64_t)H >= (int64_t(1) << 31))
+    return fail(HZD_E_INVAL, "frame %d: width*height >= 2^31", idx);
+  if (p.resize_width != 0 && (W > kResizeMaxIn || H > kResizeMaxIn))
+    return fail(HZD_E_UNSUPPORTED, "frame %d: resize input %dx%d beyond %d per side", idx, W, H, kResizeMaxIn);
+  return HZD_OK;
+}
+
+static bool ranges_overlap(const hzd_frame& f, int Wo, int Ho) {
   const uintptr_t s0 = (uintptr_t)f.src, d0 = (uintptr_t)f.dst;
   const uintptr_t s1 = s0 + (uintptr_t)((int64_t)(f.height - 1) * f.src_pitch + 3 * (int64_t)f.width);
-  const uintptr_t d1 = d0 + (uintptr_t)((int64_t)(f.height - 1) * f.dst_pitch + 3 * (int64_t)f.width);
+  const uintptr_t d1 = d0 + (uintptr_t)((int64_t)(Ho - 1) * f.dst_pitch + 3 * (int64_t)Wo);
   return s0 < d1 && d0 < s1;
 }
 
-int validate_frame(const hzd_frame* f, int idx) {
+int validate_frame(const hzd_frame* f, const hzd_params& p, int idx) {
   if (!f) return fail(HZD_E_INVAL, "frame %d is NULL", idx);
-  if (f->width < 1 || f->height < 1)
-    return fail(HZD_E_INVAL, "frame %d: size %dx%d", idx, f->width, f->height);
-  if ((int64_t)f->width * (int64_t)f->height >= (int64_t(1) << 31))
-    return fail(HZD_E_INVAL, "frame %d: width*height >= 2^31", idx);
+  int rc = validate_size(p, f->width, f->height, idx);
+  if (rc) return rc;
+  int Wo, Ho;
+  output_size(p, f->width, f->height, &Wo, &Ho);
   if (!f->src || !f->dst) return fail(HZD_E_INVAL, "frame %d: NULL pixel pointer", idx);
-  if (f->src_pitch < 3 * (int64_t)f->width || f->dst_pitch < 3 * (int64_t)f->width)
-    return fail(HZD_E_INVAL, "frame %d: pitch < 3*width", idx);
+  if (f->src_pitch < 3 * (int64_t)f->width) return fail(HZD_E_INVAL, "frame %d: src_pitch < 3*width", idx);
+  if (f->dst_pitch < 3 * (int64_t)Wo) return fail(HZD_E_INVAL, "frame %d: dst_pitch < 3*output width", idx);
   if (f->src_pitch >= (int64_t(1) << 40) || f->dst_pitch >= (int64_t(1) << 40))
     return fail(HZD_E_INVAL, "frame %d: pitch too large", idx);
-  if (ranges_overlap(*f)) return fail(HZD_E_INVAL, "frame %d: src and dst overlap", idx);
+  if (ranges_overlap(*f, Wo, Ho)) return fail(HZD_E_INVAL, "frame %d: src and dst overlap", idx);
   return HZD_OK;
 }
 
@@ -98,6 +119,7 @@ GroupKey group_key(const hzd_params& p) {
   g.cb = p.color_balance;
   g.fp16 = p.precision == HZD_PREC_FP16;
   g.radius = p.mode == HZD_MODE_OFFLINE ? p.gf_radius : 0;
+  g.resize = p.resize_width != 0;
   return g;
 }
 
@@ -105,10 +127,14 @@ bool operator<(const GroupKey& a, const GroupKey& b) {
   return std::memcmp(&a, &b, sizeof(GroupKey)) < 0;
 }
 
-size_t frame_ws_bytes(const hzd_params& p, int W, int H) {
+// W, H: the input size.  Every map is at the output size.
+size_t frame_ws_bytes(const hzd_params& p, int Win, int Hin) {
   const bool offline = p.mode == HZD_MODE_OFFLINE;
   const bool needE = p.tx == HZD_TX_HE;
+  int W, H;
+  output_size(p, Win, Hin, &W, &H);
   size_t s = a256(sizeof(FrameState));
+  if (p.resize_width != 0) s += a256((size_t)H * a16(3 * W));  // resized input
   s += a256((size_t)H * a16(W));                       // D
   if (needE) s += a256((size_t)H * a16(3 * W));        // E
   s += a256((size_t)H * sizeof(RowSel));               // per-row selection records
@@ -216,10 +242,14 @@ void fit_gf_rows(Batch& b) {
 }
 
 // Fill the device descriptor of one frame; `ws` is the frame's workspace base.
-FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws) {
+// With a resize, *rz receives the resampling descriptor and the pipeline
+// reads the working-size copy in the workspace instead of the caller's frame.
+FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws,
+                        ResizeDev* rz) {
   FrameDev d;
   std::memset(&d, 0, sizeof(d));
-  const int W = fr.width, H = fr.height;
+  int W, H;
+  output_size(p, fr.width, fr.height, &W, &H);
   const bool offline = p.mode == HZD_MODE_OFFLINE;
   d.src = fr.src;
   d.dst = fr.dst;
@@ -230,6 +260,22 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   size_t off = 0;
   d.st = reinterpret_cast<FrameState*>(ws + off);
   off += a256(sizeof(FrameState));
+  if (p.resize_width != 0) {
+    uint8_t* copy = ws + off;
+    off += a256((size_t)H * a16(3 * W));
+    d.src = copy;
+    d.src_pitch = a16(3 * W);
+    if (rz) {
+      rz->src = fr.src;
+      rz->src_pitch = fr.src_pitch;
+      rz->dst = copy;
+      rz->dst_pitch = a16(3 * W);
+      rz->Ws = fr.width;
+      rz->Hs = fr.height;
+      rz->Wo = W;
+      rz->Ho = H;
+    }
+  }
   d.D_pitch = a16(W);
   d.D = ws + off;
   off += a256((size_t)H * d.D_pitch);
@@ -283,8 +329,8 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     d.ab_inv_scale = std::ldexp(1.0f, -k);
   }
   d.gf_rows = tile_config_for(W, H).gf_rows;
-  d.aligned = ((uintptr_t)fr.src % 4 == 0) && ((uintptr_t)fr.dst % 4 == 0) && (fr.src_pitch % 4 == 0) &&
-              (fr.dst_pitch % 4 == 0);
+  d.aligned = ((uintptr_t)d.src % 4 == 0) && ((uintptr_t)d.dst % 4 == 0) && (d.src_pitch % 4 == 0) &&
+              (d.dst_pitch % 4 == 0);
   return d;
 }
 
@@ -340,10 +386,11 @@ int stage(bool prof, const char* name, hipStream_t s, F&& launch) {
 
 // The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames;
 // `prof` brackets every launch with timing events.
-int run_group(const GroupKey& g, const Batch& b, hipStream_t s, bool prof) {
+int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s, bool prof) {
   int rc;
   // an empty event pair measures what bracketing itself costs
   if (prof) (void)stage(prof, "event_pair", s, [] { return hipSuccess; });
+  if (g.resize && (rc = stage(prof, "resize", s, [&] { return launch_resize(*rz, s); })) != HZD_OK) return rc;
   if ((rc = stage(prof, "init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
   const bool he = g.tx == HZD_TX_HE;
   if ((rc = stage(prof, "dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
@@ -391,7 +438,8 @@ void graph_evict_locked(size_t keep) {
 }  // namespace
 
 // Launch one group: replay a cached graph of its kernels when enabled.
-int launch_group(const GroupKey& g, const Batch& bin, hipStream_t s) {
+int launch_group(const GroupKey& g, const Batch& bin, const ResizeBatch* rz, hipStream_t s) {
+  if (g.resize && (!rz || rz->n != bin.n)) return fail(HZD_E_INVAL, "resize descriptors missing");
   Batch b = bin;
   if (g.mode == HZD_MODE_OFFLINE) fit_gf_rows(b);
   int cap;
@@ -400,26 +448,27 @@ int launch_group(const GroupKey& g, const Batch& bin, hipStream_t s) {
     cap = g_graph_cap;
   }
   const bool prof = g_prof_on.load(std::memory_order_relaxed);
-  if (s == nullptr) return run_group(g, b, s, prof);
-  if (cap == 0 && !prof) return run_group(g, b, s, false);
+  if (s == nullptr) return run_group(g, b, rz, s, prof);
+  if (cap == 0 && !prof) return run_group(g, b, rz, s, false);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
     (void)hipGetLastError();
     // the caller is capturing: our launches join its graph, without timing
     // events, which would complete only when that graph runs
-    return run_group(g, b, s, false);
+    return run_group(g, b, rz, s, false);
   }
-  if (cap == 0 || prof) return run_group(g, b, s, prof);
+  if (cap == 0 || prof) return run_group(g, b, rz, s, prof);
   // A graph is bound to the device it was captured on, and a freed device
   // address can come back on another device: the device is part of the key.
   int dev = -1;
   if (hipStreamGetDevice(s, &dev) != hipSuccess) {
     (void)hipGetLastError();
-    return run_group(g, b, s, false);
+    return run_group(g, b, rz, s, false);
   }
   std::string key(reinterpret_cast<const char*>(&dev), sizeof(dev));
   key.append(reinterpret_cast<const char*>(&g), sizeof(g));
   key.append(reinterpret_cast<const char*>(&b), sizeof(b));
+  if (g.resize) key.append(reinterpret_cast<const char*>(rz), sizeof(*rz));
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -432,7 +481,7 @@ int launch_group(const GroupKey& g, const Batch& bin, hipStream_t s) {
   if (!exec) {
     int rc = check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     if (rc) return rc;
-    const int rrc = run_group(g, b, s, false);
+    const int rrc = run_group(g, b, rz, s, false);
     hipGraph_t graph = nullptr;
     rc = check(hipStreamEndCapture(s, &graph), "end capture");
     if (rrc) {
@@ -462,10 +511,10 @@ int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, co
   if (!frames) return fail(HZD_E_INVAL, "frames is NULL");
   std::vector<const hzd_params*> ps(n);
   for (int i = 0; i < n; ++i) {
-    int rc = validate_frame(&frames[i], i);
-    if (rc) return rc;
     ps[i] = frames[i].params ? frames[i].params : params;
-    if ((rc = validate_params(ps[i])) != HZD_OK) return rc;
+    int rc = validate_params(ps[i]);
+    if (rc) return rc;
+    if ((rc = validate_frame(&frames[i], *ps[i], i)) != HZD_OK) return rc;
   }
   if (!workspace) return fail(HZD_E_INVAL, "workspace is NULL");
   if ((uintptr_t)workspace % 256) return fail(HZD_E_INVAL, "workspace not 256-byte aligned");
@@ -484,14 +533,16 @@ int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, co
     const std::vector<int>& idx = kv.second;
     for (size_t c = 0; c < idx.size(); c += kMaxBatch) {
       Batch b;
+      ResizeBatch rz;
       std::memset(&b, 0, sizeof(b));
-      b.n = (int)std::min<size_t>(kMaxBatch, idx.size() - c);
+      std::memset(&rz, 0, sizeof(rz));
+      b.n = rz.n = (int)std::min<size_t>(kMaxBatch, idx.size() - c);
       for (int j = 0; j < b.n; ++j) {
         const int i = idx[c + j];
         b.f[j] = make_frame_dev(*ps[i], frames[i], aux ? &aux[i] : nullptr,
-                                reinterpret_cast<uint8_t*>(workspace) + offs[i]);
+                                reinterpret_cast<uint8_t*>(workspace) + offs[i], &rz.f[j]);
       }
-      int rc = launch_group(kv.first, b, s);
+      int rc = launch_group(kv.first, b, &rz, s);
       if (rc) return rc;
     }
   }
@@ -563,9 +614,7 @@ int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_
     const hzd_params* p = frames[i].params ? frames[i].params : params;
     int rc = validate_params(p);
     if (rc) return rc;
-    if (frames[i].width < 1 || frames[i].height < 1 ||
-        (int64_t)frames[i].width * frames[i].height >= (int64_t(1) << 31))
-      return fail(HZD_E_INVAL, "frame %d: size %dx%d", i, frames[i].width, frames[i].height);
+    if ((rc = validate_size(*p, frames[i].width, frames[i].height, i)) != HZD_OK) return rc;
     need += frame_ws_bytes(*p, frames[i].width, frames[i].height);
   }
   *bytes = need;
@@ -599,7 +648,8 @@ int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspa
   const hzd_params* p = frame->params ? frame->params : params;
   int rc = validate_params(p);
   if (rc) return rc;
-  const int W = frame->width, H = frame->height;
+  int W, H;  // the guided filter runs at the output size
+  output_size(*p, frame->width, frame->height, &W, &H);
   if (p->mode != HZD_MODE_OFFLINE) {  // no tile knob on the real-time path
     *best = tile_config_for(W, H);
     clear_error();

@@ -78,12 +78,33 @@ struct Batch {
 };
 static_assert(sizeof(Batch) <= 4000, "kernel argument block too large");
 
+// Resampling of Sec. V step 1 for one frame: the caller's frame (Ws x Hs) to
+// the working-size copy in the frame's workspace (Wo x Ho, pitch dst_pitch),
+// which every later stage reads as its input.
+constexpr int kResizeMaxOut = 16384;   // output width/height limit
+constexpr int kResizeMaxIn = 32768;    // input width/height limit (keeps tap arithmetic in 32 bits)
+constexpr int kResizeBits = 11;        // fractional bits of the bilinear weights
+struct ResizeDev {
+  const uint8_t* src;
+  int64_t src_pitch;
+  uint8_t* dst;
+  int32_t dst_pitch;
+  int32_t Ws, Hs, Wo, Ho;
+};
+
+struct ResizeBatch {
+  int32_t n;
+  int32_t tile0[kMaxBatch + 1];
+  ResizeDev f[kMaxBatch];
+};
+
 // Group-wide kernel switches (identical for all frames of one launch).
 struct GroupKey {
-  int32_t mode, half_patch, tx, cb, fp16, radius;
+  int32_t mode, half_patch, tx, cb, fp16, radius, resize;
 };
 
 // Launches (hzd_kernels.hip).  Each fills b.tile0 for its own tiling.
+hipError_t launch_resize(ResizeBatch r, hipStream_t s);
 hipError_t launch_init(Batch b, hipStream_t s);
 hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s);
 hipError_t launch_select(Batch b, hipStream_t s);        // two kernels: rows, then one block per frame

@@ -31,7 +31,8 @@ constexpr int kChunkBatch = 8;                                 // chunk sums loa
 constexpr int kSelVec = 4;                                     // 16-byte D vectors per lane loaded at once
 
 // ------------------------------------------------------------------ helpers
-__device__ __forceinline__ int frame_of(const Batch& b, int blk) {
+template <typename B>
+__device__ __forceinline__ int frame_of(const B& b, int blk) {
   int f = 0;
   while (f + 1 < b.n && blk >= b.tile0[f + 1]) ++f;
   return f;
@@ -160,6 +161,92 @@ __global__ __launch_bounds__(256) void k_init(Batch b) {
   const FrameDev& fd = b.f[blockIdx.x];
   uint32_t* s = reinterpret_cast<uint32_t*>(fd.st);
   for (int i = threadIdx.x; i < (int)(sizeof(FrameState) / 4); i += 256) s[i] = 0u;
+}
+
+// ------------------------------------------------------------------ k_resize
+// Sec. V step 1: bilinear resampling of the frame to the working size, in
+// exact integers.  Along each axis output sample i lies at source coordinate
+// s = (i + 1/2) n_in / n_out - 1/2 (0 when negative), carried as the rational
+// ((2i + 1) n_in - n_out) / (2 n_out).  Its taps are floor(s) and the next
+// sample, clamped to the last; the second tap's weight is frac(s) rounded half
+// up to a multiple of 2^-11.  Rows are interpolated first, then columns, and
+// the sum is rounded half up.
+struct ResizeTap {
+  int i0, i1;
+  uint32_t w1;
+};
+
+__device__ __forceinline__ ResizeTap resize_tap(int i, int n_in, int n_out) {
+  // (2i + 1) n_in < 2^31 for n_in <= 32768 and i < n_out <= 16384
+  const int num = max((2 * i + 1) * n_in - n_out, 0);
+  const uint32_t den = 2u * (uint32_t)n_out;
+  const uint32_t i0 = (uint32_t)num / den;
+  const uint32_t frac = (uint32_t)num - i0 * den;   // < den <= 2^15
+  ResizeTap t;
+  t.i0 = (int)i0;                                   // <= n_in - 1 since s < n_in - 1/2
+  t.i1 = min((int)i0 + 1, n_in - 1);
+  t.w1 = (frac * (2u << kResizeBits) + den) / (2u * den);
+  return t;
+}
+
+// The RGB bytes of pixels x0 and x1 (x1 == x0 or x0 + 1) of a row, from
+// aligned dword loads that each hold at least one needed byte (so no load
+// leaves the row's allocation).
+__device__ __forceinline__ void load_pixel_pair(const uint8_t* row, int x0, int x1, uint32_t& p0, uint32_t& p1) {
+  const uintptr_t a = (uintptr_t)(row + 3 * (int64_t)x0);
+  const uintptr_t a0 = a & ~(uintptr_t)3;
+  const uintptr_t last = (a + (x1 > x0 ? 5 : 2)) & ~(uintptr_t)3;
+  const uint32_t sh = (uint32_t)(a & 3);
+  const uint32_t w0 = *reinterpret_cast<const uint32_t*>(a0);
+  const uint32_t w1 = a0 + 4 <= last ? *reinterpret_cast<const uint32_t*>(a0 + 4) : 0u;
+  const uint32_t w2 = a0 + 8 <= last ? *reinterpret_cast<const uint32_t*>(a0 + 8) : 0u;
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);   // bytes [a, a + 4)
+  const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, sh);   // bytes [a + 4, a + 8)
+  p0 = lo & 0xFFFFFFu;
+  p1 = x1 > x0 ? ((lo >> 24) | (hi << 8)) & 0xFFFFFFu : p0;
+}
+
+// One block: 4 output rows (one per wave) by 256 output columns (4 per lane);
+// each lane stores its 4 pixels as 3 aligned dwords (the copy's pitch is a
+// multiple of 16).
+__global__ __launch_bounds__(256) void k_resize(ResizeBatch rb) {
+  const int blk = blockIdx.x;
+  const int f = frame_of(rb, blk);
+  const ResizeDev& fd = rb.f[f];
+  const int tile = blk - rb.tile0[f];
+  const int tiles_x = (fd.Wo + 255) / 256;
+  const int y = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  const int xb = (tile % tiles_x) * 256 + (threadIdx.x & 63) * 4;
+  if (y >= fd.Ho || xb >= fd.Wo) return;
+  const ResizeTap ty = resize_tap(y, fd.Hs, fd.Ho);
+  const uint8_t* r0 = fd.src + (int64_t)ty.i0 * fd.src_pitch;
+  const uint8_t* r1 = fd.src + (int64_t)ty.i1 * fd.src_pitch;
+  constexpr uint32_t kOne = 1u << kResizeBits;
+  const uint32_t wy1 = ty.w1, wy0 = kOne - wy1;
+  uint32_t px[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const ResizeTap tx = resize_tap(min(xb + k, fd.Wo - 1), fd.Ws, fd.Wo);
+    uint32_t a0, a1, b0, b1;
+    load_pixel_pair(r0, tx.i0, tx.i1, a0, a1);
+    load_pixel_pair(r1, tx.i0, tx.i1, b0, b1);
+    const uint32_t wx1 = tx.w1, wx0 = kOne - wx1;
+    uint32_t v = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint32_t h0 = wx0 * ((a0 >> (8 * c)) & 255u) + wx1 * ((a1 >> (8 * c)) & 255u);
+      const uint32_t h1 = wx0 * ((b0 >> (8 * c)) & 255u) + wx1 * ((b1 >> (8 * c)) & 255u);
+      const uint32_t q = (wy0 * h0 + wy1 * h1 + (1u << (2 * kResizeBits - 1))) >> (2 * kResizeBits);
+      v |= q << (8 * c);
+    }
+    px[k] = v;
+  }
+  // a dword that starts inside the row ends inside the pitch (a multiple of 16)
+  uint32_t* out = reinterpret_cast<uint32_t*>(fd.dst + (int64_t)y * fd.dst_pitch + 3 * xb);
+  const int nbytes = 3 * (fd.Wo - xb);
+  out[0] = px[0] | (px[1] << 24);
+  if (nbytes > 4) out[1] = (px[1] >> 8) | (px[2] << 16);
+  if (nbytes > 8) out[2] = (px[2] >> 16) | (px[3] << 8);
 }
 
 // ------------------------------------------------------------------ k_dark
@@ -1491,8 +1578,8 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
 // ----------------------------------------------------------------- launches
 namespace {
 
-template <typename Fn>
-int fill_tiles(Batch& b, Fn blocks_of) {
+template <typename B, typename Fn>
+int fill_tiles(B& b, Fn blocks_of) {
   int acc = 0;
   for (int i = 0; i < b.n; ++i) {
     b.tile0[i] = acc;
@@ -1536,6 +1623,12 @@ hipError_t gf_q_p(const Batch& b, int nblk, int radius, bool fp16, bool aux, hip
 }
 
 }  // namespace
+
+hipError_t launch_resize(ResizeBatch r, hipStream_t s) {
+  const int nblk = fill_tiles(r, [](const ResizeDev& f) { return ((f.Ho + 3) / 4) * ((f.Wo + 255) / 256); });
+  hipLaunchKernelGGL(k_resize, dim3(nblk), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
 
 hipError_t launch_init(Batch b, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(b.n), dim3(256), 0, s, b);

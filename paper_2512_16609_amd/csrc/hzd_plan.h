@@ -12,15 +12,20 @@ namespace hzd {
 int fail(int status, const char* fmt, ...);
 void clear_error();
 int validate_params(const hzd_params* p);
-int validate_frame(const hzd_frame* f, int idx);
+// Output (working) size of a frame of input size W x H.
+void output_size(const hzd_params& p, int W, int H, int* Wo, int* Ho);
+int validate_size(const hzd_params& p, int W, int H, int idx);
+int validate_frame(const hzd_frame* f, const hzd_params& p, int idx);
 GroupKey group_key(const hzd_params& p);
 bool operator<(const GroupKey& a, const GroupKey& b);
 size_t frame_ws_bytes(const hzd_params& p, int W, int H);
-FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws);
+FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_frame_aux* aux, uint8_t* ws,
+                        ResizeDev* rz);
 hzd_tile_config tile_config_for(int W, int H, bool* from_table = nullptr);
 void fit_gf_rows(Batch& b);
-int run_group(const GroupKey& g, const Batch& b, hipStream_t s, bool prof);
-int launch_group(const GroupKey& g, const Batch& b, hipStream_t s);
+int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s, bool prof);
+// rz: the resampling descriptors of a group with g.resize (else unused, may be NULL)
+int launch_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s);
 int check(hipError_t e, const char* what);
 
 }  // namespace hzd

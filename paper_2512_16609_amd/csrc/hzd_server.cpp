@@ -203,8 +203,10 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
   }
   if (L.jobs.empty()) return false;
   Batch b;
+  ResizeBatch rz;
   std::memset(&b, 0, sizeof(b));
-  b.n = (int)L.jobs.size();
+  std::memset(&rz, 0, sizeof(rz));
+  b.n = rz.n = (int)L.jobs.size();
   for (int i = 0; i < b.n; ++i) {
     const Job& j = L.jobs[i];
     hzd_stream* st = j.st;
@@ -214,10 +216,10 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     aux.A_out = reinterpret_cast<float*>(state);
     aux.sel_out = reinterpret_cast<int32_t*>(state + 16);
     uint8_t* ws = base + 256 * kSlotsPerStream + st->ws_bytes * j.slot;
-    b.f[i] = make_frame_dev(st->p, j.fr, &aux, ws);
+    b.f[i] = make_frame_dev(st->p, j.fr, &aux, ws, &rz.f[i]);
   }
   (void)hipSetDevice(s->cfg.device);
-  int rc = launch_group(key, b, s->hstreams[hs]);
+  int rc = launch_group(key, b, &rz, s->hstreams[hs]);
   if (rc == HZD_OK) rc = check(hipEventRecord(s->events[hs], s->hstreams[hs]), "event record");
   s->stats.launches++;
   if (rc != HZD_OK) {
@@ -353,8 +355,7 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
   if (!s || !out) return fail(HZD_E_INVAL, "NULL argument");
   int rc = validate_params(params);
   if (rc) return rc;
-  if (width < 1 || height < 1 || (int64_t)width * height >= (int64_t(1) << 31))
-    return fail(HZD_E_INVAL, "size %dx%d", width, height);
+  if ((rc = validate_size(*params, width, height, 0)) != HZD_OK) return rc;
   hzd_stream* st = new hzd_stream();
   st->srv = s;
   st->p = *params;
@@ -386,7 +387,7 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
 int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
                       uint64_t* ticket) {
   if (!st || !frame) return fail(HZD_E_INVAL, "NULL argument");
-  int rc = validate_frame(frame, 0);
+  int rc = validate_frame(frame, st->p, 0);
   if (rc) return rc;
   if (frame->width != st->W || frame->height != st->H)
     return fail(HZD_E_INVAL, "frame %dx%d does not match stream %dx%d", frame->width, frame->height, st->W,

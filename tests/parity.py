@@ -34,7 +34,8 @@ def oracle_params(p: hzd.Params) -> oracle.Params:
     return oracle.Params(mode="offline" if p.mode == hzd.MODE_OFFLINE else "realtime", patch=p.patch,
                          omega=p.omega, t0=p.t0, top_frac=p.top_frac, alpha=p.alpha, gamma=p.gamma,
                          gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=bool(p.color_balance),
-                         tx="he" if p.tx == hzd.TX_HE else "paper")
+                         tx="he" if p.tx == hzd.TX_HE else "paper", resize_width=p.resize_width,
+                         resize_height=p.resize_height)
 
 
 def to_dev(I: np.ndarray, pitch_pad: int = 0) -> torch.Tensor:
@@ -50,12 +51,13 @@ def to_dev(I: np.ndarray, pitch_pad: int = 0) -> torch.Tensor:
 def run_gpu(I: np.ndarray, p: hzd.Params, pitch_pad: int = 0, with_J: bool = True):
     h, w, _ = I.shape
     src = to_dev(I, pitch_pad)
+    ho, wo = p.output_shape(h, w)
     if pitch_pad:
-        dbig = torch.zeros((h, 3 * w + pitch_pad), dtype=torch.uint8, device="cuda")
-        dst = torch.as_strided(dbig, (h, w, 3), (3 * w + pitch_pad, 3, 1))
+        dbig = torch.zeros((ho, 3 * wo + pitch_pad), dtype=torch.uint8, device="cuda")
+        dst = torch.as_strided(dbig, (ho, wo, 3), (3 * wo + pitch_pad, 3, 1))
     else:
-        dst = torch.zeros_like(src)
-    aux = hzd.make_aux(h, w, J=with_J)
+        dst = torch.zeros((ho, wo, 3), dtype=torch.uint8, device="cuda")
+    aux = hzd.make_aux(ho, wo, J=with_J)
     hzd.dehaze_frame(src, dst, p, aux=aux)
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy() for k, v in aux.items()}
@@ -91,6 +93,7 @@ def compare(I: np.ndarray, p: hzd.Params, g: dict, ref=None, label: str = "") ->
     if ref is None:
         ref = oracle.dehaze(I, oracle_params(p))
     a = ref.aux
+    I = a.get("I", I)   # the resized input when the params resize
     # dark channel and the airlight set: bit-exact
     assert np.array_equal(g["dark"], a["D"]), f"{label}: dark channel differs"
     assert int(g["sel"][0]) == a["K"], f"{label}: K {g['sel'][0]} != {a['K']}"

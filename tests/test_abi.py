@@ -31,11 +31,11 @@ def test_library_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(hzd.SYMBOLS), "binding and header disagree"
-    assert L.hzd_abi_version() == 1
+    assert L.hzd_abi_version() == hzd.ABI_VERSION == 2
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(hzd.hzd_params) == 4 * 13
+    assert ctypes.sizeof(hzd.hzd_params) == 4 * 15
     assert ctypes.sizeof(hzd.hzd_frame) == 8 + 8 + 8 + 8 + 4 + 4 + 8
     assert ctypes.sizeof(hzd.hzd_frame_aux) == 5 * 8
 
@@ -104,6 +104,27 @@ def test_frame_validation(L):
     assert L.hzd_dehaze_frame(None, None, None, None, 0, None) == hzd.HZD_E_INVAL
     pc = p.c()
     assert L.hzd_dehaze_batch(ctypes.byref(pc), None, 0, None, None, 0, None) == hzd.HZD_E_INVAL
+
+
+def test_resize_validation(L):
+    for rw, rh in [(640, 0), (0, 480), (-1, 480), (16385, 10), (10, 16385)]:
+        assert call_frame(L, hzd.Params(resize_width=rw, resize_height=rh)) == hzd.HZD_E_INVAL, (rw, rh)
+    p = hzd.Params(resize_width=640, resize_height=480)
+    # input sides beyond 32768 are not supported when resizing
+    assert call_frame(L, p, w=32769, h=2, dp=3 * 640) == hzd.HZD_E_UNSUPPORTED
+    # dst pitch and the src/dst overlap are checked at the output size
+    assert call_frame(L, p, w=64, h=48, dp=3 * 64) == hzd.HZD_E_INVAL
+    assert call_frame(L, p, w=64, h=48, dp=3 * 640, dst=FAKE_SRC - 100000) == hzd.HZD_E_INVAL
+    assert call_frame(L, p, w=64, h=48, dp=3 * 640, ws_bytes=1000) == hzd.HZD_E_NOMEM
+
+
+def test_workspace_size_with_resize(L):
+    # every map at the output size, plus the resized copy of the input (pitch 1920, 480 rows)
+    rs = hzd.workspace_size(hzd.Params(resize_width=640, resize_height=480), [(1080, 1920)])
+    assert rs == hzd.workspace_size(hzd.Params(), [(480, 640)]) + 480 * 1920
+    off = hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1, resize_width=640, resize_height=480)
+    assert hzd.workspace_size(off, [(2160, 3840)]) == hzd.workspace_size(
+        hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1), [(480, 640)]) + 480 * 1920
 
 
 def test_workspace_size_grows_with_mode(L):
