@@ -51,15 +51,17 @@ STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": 
                 "gf_prep": "hzd::k_gf_prep<0>", "gf_ab": "hzd::k_gf_ab<2>", "gf_q": "hzd::k_gf_q<2,1,false,false>",
                 "recon_apply": "hzd::k_recon<2,2,false,false>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1080p_offline.txt")
+RESIZE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_resize_1080p_to_640x480_x8.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_16609_amd", "csrc", "hzd_kernels.hip")
+EXTRAS = ("320", "video", "uneven", "resize1", "resize8")
 
 
-def measured_traffic(stage):
-    """Calibrated HBM-side bytes per launch of `stage` from the committed counter summary, or
+def measured_traffic(kernel, path=TRAFFIC_FILE):
+    """Calibrated HBM-side bytes per launch of `kernel` from a committed counter summary, or
     None if the kernels changed since the counters were taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
@@ -72,10 +74,9 @@ def measured_traffic(stage):
             scale = (float(f[2]), float(f[4]))
         elif f and f[0] == "SOURCE":
             recorded = f[1]
-    k = STAGE_KERNEL.get(stage)
-    if recorded != src or scale is None or k not in raw:
+    if recorded != src or scale is None or kernel not in raw:
         return None
-    fetch, write = raw[k]
+    fetch, write = raw[kernel]
     return round((fetch * scale[0] + write * scale[1]) * 1024.0)
 
 
@@ -134,12 +135,83 @@ def timed(fn, reps, sync):
     return (time.perf_counter() - t0) / reps
 
 
-def extra_workloads(hzd, torch, dev):
-    """The other configurations, each timed on its own (inputs resident in HBM)."""
-    from synth import make_frame, make_video
+def stage_us(hzd, run, reps, sync):
+    """Average µs of each stage's launches over `reps` calls of run(), from HIP events on the
+    launch stream, less the cost of an empty event pair."""
+    hzd.profile_read(reset=True)
+    hzd.profile_enable(True)
+    try:
+        for _ in range(reps):
+            run()
+        sync()
+        st = hzd.profile_read(reset=True)
+    finally:
+        hzd.profile_enable(False)
+    ev_n, ev_ms = st.pop("event_pair", (0, 0.0))
+    ev_us = 1e3 * ev_ms / max(ev_n, 1)
+    return {k: max(1e3 * ms / max(n, 1) - ev_us, 1e-3) for k, (n, ms) in st.items()}
+
+
+def resize_workloads(hzd, torch, dev, which):
+    """Sec. V step 1 at the paper's default working size: 1920x1080 inputs resized to 640x480,
+    then the real-time path, from a pool of 16 distinct device-resident inputs."""
+    from synth import make_frame
     out = {}
     sync = torch.cuda.synchronize
-    # 320x240 real-time single frame: launch-bound, so report latency
+    W, H, Wo, Ho = 1920, 1080, 640, 480
+    pool = [torch.from_numpy(make_frame(W, H, 700 + k).I).to(dev) for k in range(16)]
+    outs = [torch.empty((Ho, Wo, 3), dtype=torch.uint8, device=dev) for _ in range(16)]
+    p = hzd.Params(resize_width=Wo, resize_height=Ho)
+    if "resize1" in which:
+        ws = hzd.alloc_workspace(hzd.workspace_size(p, [(H, W)]), dev)
+        calls = [hzd.FrameCall(pool[k], outs[k], p, ws) for k in range(16)]
+        for k in range(20):
+            calls[k % 16]()
+        lat = []
+        for k in range(300):
+            t0 = time.perf_counter()
+            calls[k % 16]()
+            sync()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        n = [0]
+
+        def one():
+            calls[n[0] % 16]()
+            n[0] += 1
+        per = timed(one, 480, sync)
+        out["1920x1080_to_640x480_realtime"] = {
+            "input_MP_per_s": round(W * H / 1e6 / per, 1), "output_MP_per_s": round(Wo * Ho / 1e6 / per, 1),
+            "latency_ms": {"p50": rnd(percentile(lat, 50), 4), "p99": rnd(percentile(lat, 99), 4)}}
+    if "resize8" in which:
+        ws8 = hzd.alloc_workspace(hzd.workspace_size(p, [(H, W)] * 8), dev)
+        L = [0]
+
+        def batch8():
+            idx = [(8 * L[0] + k) % 16 for k in range(8)]
+            hzd.dehaze_batch([pool[i] for i in idx], [outs[i] for i in idx], p, workspace=ws8)
+            L[0] += 1
+        for _ in range(4):
+            batch8()
+        per = timed(batch8, 40, sync)
+        us = stage_us(hzd, batch8, 40, sync)
+        alg = 8 * (3 * W * H + 3 * Wo * Ho)   # read the inputs, write the working-size copies
+        gbs = alg / (us["resize"] * 1e-6) / 1e9
+        out["1920x1080_to_640x480_realtime_8_per_launch"] = {
+            "input_MP_per_s": round(8 * W * H / 1e6 / per, 1), "output_MP_per_s": round(8 * Wo * Ho / 1e6 / per, 1),
+            "ms_per_launch": round(per * 1e3, 4),
+            "stage_us": {k: round(v, 3) for k, v in us.items()},
+            "roofline": {"kernel": "hzd::k_resize", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic("hzd::k_resize", RESIZE_TRAFFIC_FILE),
+                         "alg_bytes_per_launch": alg, "avg_launch_us": round(us["resize"], 3)}}
+    del pool, outs
+    return out
+
+
+def realtime_320(hzd, torch, dev):
+    """320x240 real-time single frame: launch-bound, so report latency."""
+    from synth import make_frame
+    sync = torch.cuda.synchronize
     I = make_frame(320, 240, 1, beta=1.0).I
     p = hzd.Params()
     src = torch.from_numpy(I).to(dev)
@@ -155,10 +227,15 @@ def extra_workloads(hzd, torch, dev):
         sync()
         lat.append((time.perf_counter() - t0) * 1e3)
     per = timed(call, 500, sync)
-    out["320x240_realtime"] = {"MP_per_s": round(0.0768 / per, 1), "latency_ms": {
-        "p50": rnd(percentile(lat, 50), 4), "p99": rnd(percentile(lat, 99), 4)}}
-    # 1280x720 video, real-time mode with FP16 t, 8 frames per launch; a 300-frame clip is 38
-    # launches, drawn from a 16-frame device-resident pool of the panning clip
+    return {"320x240_realtime": {"MP_per_s": round(0.0768 / per, 1), "latency_ms": {
+        "p50": rnd(percentile(lat, 50), 4), "p99": rnd(percentile(lat, 99), 4)}}}
+
+
+def video_720p(hzd, torch, dev):
+    """1280x720 video, real-time mode with FP16 t, 8 frames per launch; a 300-frame clip is 38
+    launches, drawn from a 16-frame device-resident pool of the panning clip."""
+    from synth import make_video
+    sync = torch.cuda.synchronize
     v = make_video(1280, 720, nframes=300, seed=3)
     pool = [torch.from_numpy(v.frame(f).I).to(dev) for f in range(0, 300, 19)][:16]
     outs = [torch.empty_like(pool[0]) for _ in range(16)]
@@ -172,10 +249,15 @@ def extra_workloads(hzd, torch, dev):
             hzd.dehaze_batch([pool[i] for i in idx], [outs[i] for i in idx], p3, workspace=ws3)
     clip()
     per = timed(clip, 3, sync)
-    out["1280x720_video_rt_fp16_8_per_launch"] = {"MP_per_s": round(300 * 0.9216 / per, 1),
-                                                  "ms_per_300_frames": round(per * 1e3, 3)}
-    # 64 uneven frames (16 each of 480p, 720p, 1080p, 4K), offline mode r=60, no colour balance,
-    # one batch call; one seeded frame per size, copied into 16 distinct buffers
+    return {"1280x720_video_rt_fp16_8_per_launch": {"MP_per_s": round(300 * 0.9216 / per, 1),
+                                                    "ms_per_300_frames": round(per * 1e3, 3)}}
+
+
+def uneven_64(hzd, torch, dev):
+    """64 uneven frames (16 each of 480p, 720p, 1080p, 4K), offline mode r=60, no colour balance,
+    one batch call; one seeded frame per size, copied into 16 distinct buffers."""
+    from synth import make_frame
+    sync = torch.cuda.synchronize
     shapes = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
     srcs, dsts = [], []
     for i, (w, h) in enumerate(shapes):
@@ -189,9 +271,21 @@ def extra_workloads(hzd, torch, dev):
     batch()
     per = timed(batch, 3, sync)
     mp4 = sum(s.shape[0] * s.shape[1] for s in srcs) / 1e6
-    out["64_uneven_frames_offline"] = {"MP_per_s": round(mp4 / per, 1), "ms_per_batch": round(per * 1e3, 3),
-                                       "MP_per_batch": round(mp4, 2)}
-    del srcs, dsts, ws4, pool, outs, ws3
+    return {"64_uneven_frames_offline": {"MP_per_s": round(mp4 / per, 1), "ms_per_batch": round(per * 1e3, 3),
+                                         "MP_per_batch": round(mp4, 2)}}
+
+
+def extra_workloads(hzd, torch, dev, which=EXTRAS):
+    """The other configurations, each timed on its own (inputs resident in HBM)."""
+    out = {}
+    if "320" in which:
+        out.update(realtime_320(hzd, torch, dev))
+    if "video" in which:
+        out.update(video_720p(hzd, torch, dev))
+    if "uneven" in which:
+        out.update(uneven_64(hzd, torch, dev))
+    if "resize1" in which or "resize8" in which:
+        out.update(resize_workloads(hzd, torch, dev, which))
     torch.cuda.empty_cache()
     return out
 
@@ -304,6 +398,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other configurations")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma list of the other configurations to run: " + ", ".join(EXTRAS))
     ap.add_argument("--serving-seconds", type=float, default=1.5,
                     help="seconds of Poisson arrivals per point of the 32-stream serving mix (0 = skip)")
     ap.add_argument("--serving-scales", default="1,4,8,12,16", help="arrival-rate multipliers of the sweep")
@@ -312,6 +408,10 @@ def main():
                     help="also run 5 device-to-device copies of this many MB (a kernel of known traffic for "
                          "scaling hardware byte counters)")
     args = ap.parse_args()
+    which = set(x for x in args.extras.split(",") if x)
+    if which - set(EXTRAS):
+        print(f"unknown --extras {sorted(which - set(EXTRAS))}; choose from {EXTRAS}", file=sys.stderr)
+        sys.exit(2)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -406,7 +506,7 @@ def main():
                             "alg_bytes_per_px": bpp, "alg_GBps": round(gbs, 1)}
     dom = max(stage_rows, key=lambda k: stage_rows[k]["avg_us"])
     d = stage_rows[dom]
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(STAGE_KERNEL.get(dom))
     roofline = {"kernel": dom, "bound": "hbm", "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(d["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": d["alg_bytes_per_px"] * W * H, "avg_launch_us": d["avg_us"],
@@ -472,7 +572,7 @@ def main():
     if not args.no_extra:
         log("other configurations")
         hzd.graph_cache(0)
-        extra = extra_workloads(hzd, torch, dev)
+        extra = extra_workloads(hzd, torch, dev, which)
 
     serving = None
     if args.serving_seconds > 0:
