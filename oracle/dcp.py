@@ -41,7 +41,12 @@ parameter or a documented choice of the GPU library):
     bilinear sampling with pixel centres aligned, source coordinates clamped
     below at 0 and taps clamped at the last row/column, weights rounded to
     multiples of 2^-11 (half up) and the result rounded half up to uint8;
-    every step is exact integer arithmetic.
+    every step is exact integer arithmetic;
+  * optional temporal smoothing of the airlight over a stream's frames (the
+    flicker concern of Sec. V): A_t = lam A_{t-1} + (1 - lam) Ahat_t, where
+    Ahat_t is the frame's own Eq. (3) estimate (float64) and A_{t-1} is the
+    previous frame's A as stored (float32); the sum is formed in float64 as
+    (lam * A_{t-1}) + ((1 - lam) * Ahat_t).  The first frame takes A = Ahat.
 All functions are pinned by tests against brute force, closed forms,
 invariants or independent library routines (scipy.ndimage).
 """
@@ -73,6 +78,7 @@ class Params:
     tx: str = "he"                 # "he" (dark(I/A)) or "paper" (literal Eq. (4))
     resize_width: int = 0          # Sec. V step 1 target size; 0 x 0 = native size
     resize_height: int = 0
+    airlight_smoothing: float = 0.0  # lam of the temporal airlight average; 0 = none
 
     def f(self, name):
         return f32(getattr(self, name))
@@ -221,6 +227,17 @@ def airlight(I: np.ndarray, D: np.ndarray, top_frac: float, alpha: float) -> Air
     return Airlight(A=A, K=K, vstar=vstar, cutoff=cutoff, sel=sel, S=S)
 
 
+def airlight_smooth(A_prev: np.ndarray, A_hat: np.ndarray, lam: float) -> np.ndarray:
+    """Temporal airlight average: lam * A_prev + (1 - lam) * A_hat in float64.
+
+    A_prev is the previous frame's airlight as stored (float32 values), A_hat
+    this frame's estimate of Eq. (3); lam is taken as its float32 value.
+    """
+    lam = f32(lam)
+    A_prev = np.asarray(A_prev, dtype=np.float32).astype(np.float64)
+    return lam * A_prev + (1.0 - lam) * np.asarray(A_hat, dtype=np.float64)
+
+
 def airlight_divisor(A: np.ndarray) -> np.ndarray:
     """A^c guarded as a divisor: max(A^c, 1) on the 0..255 scale."""
     return np.maximum(A, 1.0)
@@ -346,13 +363,16 @@ class Result:
     aux: dict = field(default_factory=dict)
 
 
-def dehaze(I: np.ndarray, p: Params, A_inject=None) -> Result:
+def dehaze(I: np.ndarray, p: Params, A_inject=None, A_prev=None) -> Result:
     """One frame through the per-frame algorithm of Sec. V (steps 1-7).
 
     I: (H, W, 3) uint8 RGB, or float64 on the 0..255 scale (for the
     exact-recovery checks; then A may be injected instead of estimated).
     With resize_width/resize_height set, step 1 resizes I first and every
-    later step (and the output) is at that size.
+    later step (and the output) is at that size.  A_prev: the previous
+    frame's stored airlight (float32) of the same stream, blended in when
+    p.airlight_smoothing > 0 (None = first frame).  aux["A_state"] is this
+    frame's airlight as it would be stored for the next one.
     """
     aux = {}
     if p.resize_width or p.resize_height:
@@ -364,10 +384,13 @@ def dehaze(I: np.ndarray, p: Params, A_inject=None) -> Result:
     if A_inject is None:
         air = airlight(I, D, p.top_frac, p.alpha)
         A = air.A
-        aux.update(K=air.K, vstar=air.vstar, cutoff=air.cutoff, sel=air.sel, S=air.S)
+        aux.update(K=air.K, vstar=air.vstar, cutoff=air.cutoff, sel=air.sel, S=air.S, A_hat=air.A)
+        if p.airlight_smoothing > 0 and A_prev is not None:
+            A = airlight_smooth(A_prev, A, p.airlight_smoothing)
     else:
         A = np.asarray(A_inject, dtype=np.float64)
     aux["A"] = A
+    aux["A_state"] = np.asarray(A, dtype=np.float64).astype(np.float32)
     if p.tx == "he":
         t = transmission_he(I, A, p.omega, p.t0, p.patch)
     elif p.tx == "paper":
@@ -395,3 +418,13 @@ def dehaze(I: np.ndarray, p: Params, A_inject=None) -> Result:
     aux["gains"] = gains
     aux["Jf"] = Jf
     return Result(out=rne_u8(Jf), aux=aux)
+
+
+def dehaze_sequence(frames, p: Params):
+    """Frames of one stream in order, carrying the stored airlight between them."""
+    out, A_prev = [], None
+    for I in frames:
+        r = dehaze(I, p, A_prev=A_prev)
+        A_prev = r.aux["A_state"]
+        out.append(r)
+    return out

@@ -425,3 +425,55 @@ def test_pipeline_with_resize_runs_at_the_target_size():
     assert r.out.shape == (40, 48, 3)
     assert np.array_equal(r.aux["I"], oracle.resize(I, 48, 40))
     assert np.array_equal(r.out, oracle.dehaze(oracle.resize(I, 48, 40), Params()).out)
+
+
+# ------------------------------------------------------------ temporal airlight smoothing
+def _clip(n, seed=0):
+    return [make_frame(64, 48, seed + k, beta=0.5 + 0.2 * k).I for k in range(n)]
+
+
+def test_smoothing_zero_keeps_frames_independent():
+    frames = _clip(4)
+    seq = oracle.dehaze_sequence(frames, Params(airlight_smoothing=0.0))
+    for I, r in zip(frames, seq):
+        alone = oracle.dehaze(I, Params())
+        assert np.array_equal(r.aux["A"], alone.aux["A"])
+        assert np.array_equal(r.out, alone.out)
+
+
+def test_smoothing_of_a_repeated_frame_stays_at_its_estimate():
+    I = _clip(1)[0]
+    seq = oracle.dehaze_sequence([I] * 6, Params(airlight_smoothing=0.9))
+    A_hat = seq[0].aux["A_hat"]
+    for r in seq:
+        assert np.allclose(r.aux["A"], A_hat, rtol=1e-6, atol=0)
+
+
+def test_smoothing_matches_the_closed_form():
+    # A_t = lam^t Ahat_0 + (1 - lam) sum_{k=1..t} lam^(t-k) Ahat_k, up to the float32 storage of
+    # each A between frames
+    lam = 0.6
+    seq = oracle.dehaze_sequence(_clip(6, seed=10), Params(airlight_smoothing=lam))
+    lam = float(np.float32(lam))
+    hats = [r.aux["A_hat"] for r in seq]
+    for t, r in enumerate(seq):
+        closed = lam ** t * hats[0] + (1 - lam) * sum(lam ** (t - k) * hats[k] for k in range(1, t + 1))
+        assert np.allclose(r.aux["A"], closed, rtol=1e-6, atol=0), t
+
+
+def test_smoothing_step_response():
+    # a frame with estimate a followed by frames with estimate b: A_t - b = lam^t (a - b)
+    a_frame, b_frame = _clip(2, seed=20)
+    lam = 0.5
+    seq = oracle.dehaze_sequence([a_frame] + [b_frame] * 5, Params(airlight_smoothing=lam))
+    a, b = seq[0].aux["A_hat"], seq[1].aux["A_hat"]
+    for t in range(1, 6):
+        assert np.allclose(seq[t].aux["A"] - b, lam ** t * (a - b), rtol=1e-5, atol=1e-4), t
+
+
+def test_smoothed_airlight_drives_transmission_and_recovery():
+    f0, f1 = _clip(2, seed=30)
+    seq = oracle.dehaze_sequence([f0, f1], Params(airlight_smoothing=0.7, mode="offline", gf_radius=8))
+    injected = oracle.dehaze(f1, Params(mode="offline", gf_radius=8), A_inject=seq[1].aux["A"])
+    assert np.array_equal(seq[1].out, injected.out)
+    assert not np.array_equal(seq[1].aux["A"], seq[1].aux["A_hat"])
