@@ -107,7 +107,17 @@ typedef enum {
  *                  half up to a multiple of 2^-11, and the weighted sum (rows,
  *                  then columns) is rounded half up to uint8, all in exact
  *                  integers.  Every later step, dst and the aux outputs are at
- *                  the working size. */
+ *                  the working size.
+ *   airlight_smoothing
+ *                  lam in [0, 1): temporal average of the airlight over the
+ *                  frames of one stream, against the flicker that Sec. V
+ *                  addresses with the top-fraction average.  The frame's A is
+ *                  lam * A_prev + (1 - lam) * Ahat, where Ahat is its own
+ *                  Eq. (3) estimate and A_prev the previous frame's A as
+ *                  stored in the stream's airlight state; the sum is formed
+ *                  in double as (lam * A_prev) + ((1 - lam) * Ahat) and rounded
+ *                  to float.  0 (the default) = every frame on its own.  A
+ *                  frame call with lam > 0 needs hzd_frame.airlight_state. */
 typedef struct hzd_params {
   uint32_t size;
   int32_t mode;
@@ -124,6 +134,7 @@ typedef struct hzd_params {
   int32_t precision;
   int32_t resize_width;
   int32_t resize_height;
+  float airlight_smoothing;
 } hzd_params;
 
 /* One frame: device pointers and geometry (see the conventions above).
@@ -131,7 +142,12 @@ typedef struct hzd_params {
  * the aux outputs have the output size, which is the input size unless the
  * frame's params resize it.  src and dst must not overlap.
  * params: NULL = the params given to the call; in a batch, a per-frame
- * override (host pointer, read during the call only). */
+ * override (host pointer, read during the call only).
+ * airlight_state: NULL, or a device pointer to the 16-byte airlight state of
+ * the stream this frame belongs to: {float A[3]; uint32_t frames}, zeroed by
+ * the caller before the stream's first frame.  The frame reads it (blending
+ * when frames > 0 and airlight_smoothing > 0) and writes its own A back, in
+ * stream order.  Frames of one call must not share a state (HZD_E_INVAL). */
 typedef struct hzd_frame {
   const uint8_t* src;
   int64_t src_pitch;
@@ -140,6 +156,7 @@ typedef struct hzd_frame {
   int32_t width;
   int32_t height;
   const hzd_params* params;
+  float* airlight_state;
 } hzd_frame;
 
 /* Optional per-frame device outputs for inspection (NULL = not written).
@@ -224,11 +241,18 @@ int hzd_server_create(const hzd_server_config* cfg, hzd_server** out);
  * on the device, closes all streams and frees the server. */
 int hzd_server_destroy(hzd_server* s);
 
+/* Arena bytes that hzd_stream_open reserves for a stream of width x height
+ * frames with these parameters (a multiple of 256). */
+int hzd_stream_arena_size(const hzd_params* params, int32_t width, int32_t height, size_t* bytes);
 /* Open a stream of width x height frames with these parameters.
- * HZD_E_AGAIN when the arena cannot hold its state right now. */
+ * HZD_E_AGAIN when the arena cannot hold its state right now.  The server
+ * keeps the stream's airlight state (airlight_smoothing); a stream with
+ * smoothing has one frame on the device at a time, since each frame starts
+ * from its predecessor's airlight. */
 int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int32_t height,
                     hzd_stream** out);
-/* Queue one frame (frame->width/height must match the stream; params ignored).
+/* Queue one frame (frame->width/height must match the stream; params and
+ * airlight_state ignored).
  * Returns at once with a ticket.  HZD_E_AGAIN when the queue is full. */
 int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
                       uint64_t* ticket);

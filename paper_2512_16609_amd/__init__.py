@@ -41,13 +41,13 @@ class hzd_params(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("gamma", ctypes.c_float), ("gf_radius", ctypes.c_int32),
                 ("gf_eps", ctypes.c_float), ("color_balance", ctypes.c_int32), ("tx", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("resize_width", ctypes.c_int32),
-                ("resize_height", ctypes.c_int32)]
+                ("resize_height", ctypes.c_int32), ("airlight_smoothing", ctypes.c_float)]
 
 
 class hzd_frame(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("src_pitch", ctypes.c_int64), ("dst", ctypes.c_void_p),
                 ("dst_pitch", ctypes.c_int64), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("params", ctypes.POINTER(hzd_params))]
+                ("params", ctypes.POINTER(hzd_params)), ("airlight_state", ctypes.c_void_p)]
 
 
 class hzd_frame_aux(ctypes.Structure):
@@ -102,6 +102,8 @@ SYMBOLS = {
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "hzd_stream_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64)]),
+    "hzd_stream_arena_size": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
     "hzd_stream_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_int32)]),
     "hzd_stream_close": (ctypes.c_int, [ctypes.c_void_p]),
@@ -164,12 +166,13 @@ class Params:
     precision: int = PREC_FP32
     resize_width: int = 0     # Sec. V step 1 working size; 0 x 0 = the frame's own size
     resize_height: int = 0
+    airlight_smoothing: float = 0.0   # temporal airlight weight lam; needs an airlight state
 
     def c(self) -> hzd_params:
         return hzd_params(ctypes.sizeof(hzd_params), self.mode, self.patch, self.omega, self.t0,
                           self.top_frac, self.alpha, self.gamma, self.gf_radius, self.gf_eps,
                           int(self.color_balance), self.tx, self.precision, self.resize_width,
-                          self.resize_height)
+                          self.resize_height, self.airlight_smoothing)
 
     def output_shape(self, h: int, w: int) -> tuple:
         """(height, width) of the output of a frame of input shape (h, w)."""
@@ -182,11 +185,13 @@ class Params:
         p = hzd_params()
         _check(lib().hzd_params_default(ctypes.byref(p), preset), "hzd_params_default")
         return Params(p.mode, p.patch, p.omega, p.t0, p.top_frac, p.alpha, p.gamma, p.gf_radius,
-                      p.gf_eps, p.color_balance, p.tx, p.precision, p.resize_width, p.resize_height)
+                      p.gf_eps, p.color_balance, p.tx, p.precision, p.resize_width, p.resize_height,
+                      p.airlight_smoothing)
 
 
 # ------------------------------------------------------------------ frames
-def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params: "Params", params_ptr=None) -> hzd_frame:
+def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params: "Params", params_ptr=None,
+                  airlight_state: torch.Tensor | None = None) -> hzd_frame:
     for name, t in (("src", src), ("dst", dst)):
         if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3:
             raise ValueError(f"{name} must be a uint8 (H, W, 3) tensor")
@@ -198,9 +203,17 @@ def _frame_struct(src: torch.Tensor, dst: torch.Tensor, params: "Params", params
     ho, wo = params.output_shape(h, w)
     if tuple(dst.shape[:2]) != (ho, wo):
         raise ValueError(f"dst shape {tuple(dst.shape[:2])} != output shape {(ho, wo)}")
+    if airlight_state is not None and (not airlight_state.is_cuda or airlight_state.numel() * airlight_state.element_size() < 16):
+        raise ValueError("airlight_state must be a device tensor of at least 16 bytes")
     f = hzd_frame(src.data_ptr(), src.stride(0) if h > 1 else 3 * w, dst.data_ptr(),
-                  dst.stride(0) if ho > 1 else 3 * wo, w, h, params_ptr)
+                  dst.stride(0) if ho > 1 else 3 * wo, w, h, params_ptr,
+                  None if airlight_state is None else airlight_state.data_ptr())
     return f
+
+
+def make_airlight_state(device="cuda") -> torch.Tensor:
+    """A zeroed 16-byte airlight state {A[3], frames} for one stream of frame calls."""
+    return torch.zeros(4, dtype=torch.float32, device=device)
 
 
 def _ptr(t):
@@ -254,10 +267,12 @@ def _stream_handle(stream) -> int:
 
 
 def dehaze_frame(src: torch.Tensor, dst: torch.Tensor, params: Params, aux: dict | None = None,
-                 workspace: torch.Tensor | None = None, stream=None) -> None:
+                 workspace: torch.Tensor | None = None, stream=None,
+                 airlight_state: torch.Tensor | None = None) -> None:
     """hzd_dehaze_frame on a (H, W, 3) uint8 device tensor (asynchronous, stream-ordered);
-    dst has the output shape params.output_shape(H, W)."""
-    f = _frame_struct(src, dst, params)
+    dst has the output shape params.output_shape(H, W).  airlight_state: the stream's
+    state from make_airlight_state(), needed with params.airlight_smoothing > 0."""
+    f = _frame_struct(src, dst, params, airlight_state=airlight_state)
     pc = params.c()
     if workspace is None:
         workspace = alloc_workspace(workspace_size(params, [(src.shape[0], src.shape[1])]), src.device)
@@ -268,14 +283,16 @@ def dehaze_frame(src: torch.Tensor, dst: torch.Tensor, params: Params, aux: dict
 
 
 def dehaze_batch(srcs, dsts, params: Params, per_frame_params=None, auxs=None,
-                 workspace: torch.Tensor | None = None, stream=None) -> None:
-    """hzd_dehaze_batch over lists of (H_i, W_i, 3) uint8 device tensors."""
+                 workspace: torch.Tensor | None = None, stream=None, airlight_states=None) -> None:
+    """hzd_dehaze_batch over lists of (H_i, W_i, 3) uint8 device tensors; airlight_states: None or
+    a list with a state tensor (or None) per frame."""
     n = len(srcs)
     pcs = [p.c() for p in per_frame_params] if per_frame_params else None
     arr = (hzd_frame * n)()
     for i in range(n):
         pi = per_frame_params[i] if per_frame_params else params
-        arr[i] = _frame_struct(srcs[i], dsts[i], pi, ctypes.pointer(pcs[i]) if pcs else None)
+        arr[i] = _frame_struct(srcs[i], dsts[i], pi, ctypes.pointer(pcs[i]) if pcs else None,
+                               airlight_states[i] if airlight_states else None)
     aarr = None
     if auxs is not None:
         aarr = (hzd_frame_aux * n)()
@@ -293,6 +310,15 @@ def dehaze_batch(srcs, dsts, params: Params, per_frame_params=None, auxs=None,
 
 
 # ------------------------------------------------------------------ server
+def stream_arena_size(params: Params, width: int, height: int) -> int:
+    """hzd_stream_arena_size: arena bytes one opened stream reserves."""
+    out = ctypes.c_size_t(0)
+    pc = params.c()
+    _check(lib().hzd_stream_arena_size(ctypes.byref(pc), width, height, ctypes.byref(out)),
+           "hzd_stream_arena_size")
+    return int(out.value)
+
+
 class Server:
     """hzd_server_*: continuous batching of many frame streams on one GPU."""
 
@@ -379,9 +405,10 @@ class FrameCall:
     """A prepared hzd_dehaze_frame call: ctypes arguments built once, so a
     timing loop measures the library and the GPU, not argument marshalling."""
 
-    def __init__(self, src, dst, params: Params, workspace, aux: dict | None = None, stream=None):
-        self._keep = (src, dst, workspace, aux)
-        self.f = _frame_struct(src, dst, params)
+    def __init__(self, src, dst, params: Params, workspace, aux: dict | None = None, stream=None,
+                 airlight_state=None):
+        self._keep = (src, dst, workspace, aux, airlight_state)
+        self.f = _frame_struct(src, dst, params, airlight_state=airlight_state)
         self.pc = params.c()
         a = _aux_struct(aux)
         self.aux = ctypes.pointer(a) if a is not None else None

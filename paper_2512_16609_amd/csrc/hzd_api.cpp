@@ -62,6 +62,8 @@ int validate_params(const hzd_params* p) {
       return fail(HZD_E_UNSUPPORTED, "gf_radius %d > %d", p->gf_radius, kMaxRadius);
     if (!in_range(p->gf_eps, 1e-8f, 1.0f)) return fail(HZD_E_INVAL, "gf_eps %g outside [1e-8,1]", p->gf_eps);
   }
+  if (!(p->airlight_smoothing >= 0.0f && p->airlight_smoothing < 1.0f))
+    return fail(HZD_E_INVAL, "airlight_smoothing %g outside [0,1)", p->airlight_smoothing);
   if (p->resize_width != 0 || p->resize_height != 0) {
     if (p->resize_width < 1 || p->resize_height < 1 || p->resize_width > kResizeMaxOut ||
         p->resize_height > kResizeMaxOut)
@@ -329,6 +331,9 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     d.ab_inv_scale = std::ldexp(1.0f, -k);
   }
   d.gf_rows = tile_config_for(W, H).gf_rows;
+  d.A_state = fr.airlight_state;
+  d.ema = p.airlight_smoothing;
+  d.ema_first = 0;
   d.aligned = ((uintptr_t)d.src % 4 == 0) && ((uintptr_t)d.dst % 4 == 0) && (d.src_pitch % 4 == 0) &&
               (d.dst_pitch % 4 == 0);
   return d;
@@ -515,6 +520,19 @@ int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, co
     int rc = validate_params(ps[i]);
     if (rc) return rc;
     if ((rc = validate_frame(&frames[i], *ps[i], i)) != HZD_OK) return rc;
+    if (ps[i]->airlight_smoothing > 0.0f && !frames[i].airlight_state)
+      return fail(HZD_E_INVAL, "frame %d: airlight_smoothing > 0 needs an airlight_state", i);
+    if ((uintptr_t)frames[i].airlight_state % 16)
+      return fail(HZD_E_INVAL, "frame %d: airlight_state not 16-byte aligned", i);
+  }
+  {
+    // frames of one call run concurrently: each stream state at most once
+    std::vector<uintptr_t> states;
+    for (int i = 0; i < n; ++i)
+      if (frames[i].airlight_state) states.push_back((uintptr_t)frames[i].airlight_state);
+    std::sort(states.begin(), states.end());
+    if (std::adjacent_find(states.begin(), states.end()) != states.end())
+      return fail(HZD_E_INVAL, "two frames of one call share an airlight_state");
   }
   if (!workspace) return fail(HZD_E_INVAL, "workspace is NULL");
   if ((uintptr_t)workspace % 256) return fail(HZD_E_INVAL, "workspace not 256-byte aligned");

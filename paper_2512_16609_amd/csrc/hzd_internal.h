@@ -69,6 +69,9 @@ struct FrameDev {
   int32_t gamma_is_one;
   int32_t aligned;   // src, dst and both pitches are multiples of 4
   int32_t gf_rows;   // output rows per guided-filter block
+  float* A_state;    // stream airlight state {A[3], frames} (NULL = none)
+  float ema;         // temporal airlight weight lam (0 = none)
+  int32_t ema_first; // 1 = the stream's first frame: ignore the stored state
 };
 
 struct Batch {

@@ -762,10 +762,22 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     const int cx = (int)S[4] - 1;
     const int32_t cutoff = rstar * W + cx;
     const double a = (double)fd.alpha;
+    // temporal average with the stream's stored airlight: (lam A_prev) +
+    // ((1 - lam) Ahat) in double, each operation rounded on its own
+    float* ast = fd.A_state;
+    const bool blend = ast && fd.ema > 0.0f && !fd.ema_first && __float_as_uint(ast[3]) != 0u;
+    const double lam = (double)fd.ema;
     for (int ch = 0; ch < 3; ++ch) {
-      const float A = (float)(a * (double)S[ch] / (double)K);
+      double Ad = a * (double)S[ch] / (double)K;
+      if (blend) Ad = __dadd_rn(__dmul_rn(lam, (double)ast[ch]), __dmul_rn(__dsub_rn(1.0, lam), Ad));
+      const float A = (float)Ad;
       st->A[ch] = A;
       if (fd.A_out) fd.A_out[ch] = A;
+    }
+    if (ast) {
+      const uint32_t seen = blend ? __float_as_uint(ast[3]) : 0u;
+      for (int ch = 0; ch < 3; ++ch) ast[ch] = st->A[ch];
+      ast[3] = __uint_as_float(seen < 0xFFFFFFFFu ? seen + 1u : seen);
     }
     st->sel[0] = (int32_t)K;
     st->sel[1] = (int32_t)vstar;

@@ -85,6 +85,15 @@ struct Arena {
 constexpr int kSlotsPerStream = 2;   // frames of one stream on the device at once
 constexpr int kMaxQueuedPerStream = 256;
 
+// A stream's arena block: per-slot outputs (A, sel; 256 B each), the stream's
+// airlight state (256 B), then one workspace per slot.
+constexpr size_t kAirlightStateOff = 256 * kSlotsPerStream;
+constexpr size_t kWorkspacesOff = kAirlightStateOff + 256;
+
+size_t stream_ws_bytes(const hzd_params& p, int W, int H) {
+  return (frame_ws_bytes(p, W, H) + 255) & ~size_t(255);
+}
+
 struct Job;
 
 }  // namespace
@@ -98,6 +107,7 @@ struct hzd_stream {
   uint8_t* state_dev = nullptr; // A (3 floats) + sel (3 ints) of each slot
   bool slot_busy[kSlotsPerStream] = {false, false};
   int last_slot = -1;
+  bool ema_primed = false;      // a frame has completed and stored the airlight state
   uint64_t next_ticket = 1;
   int queued = 0, inflight = 0;
   bool closing = false;
@@ -158,6 +168,7 @@ void finish(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     hzd_stream* st = d.first.st;
     st->done[d.first.ticket] = std::make_pair(d.second, t - d.first.t_submit);
     st->pending.erase(d.first.ticket);
+    if (d.second == HZD_OK) st->ema_primed = true;
     st->inflight--;
     st->cv.notify_all();
   }
@@ -184,7 +195,10 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     for (int k = 0; k < kSlotsPerStream; ++k)
       if (!st->slot_busy[k]) { slot = k; break; }
     const GroupKey gk = group_key(st->p);
-    if (slot < 0 || (have_key && (gk < key || key < gk))) { ++it; continue; }
+    // with temporal airlight smoothing a frame needs its predecessor's
+    // airlight: one frame of such a stream on the device at a time
+    const bool ema_wait = st->p.airlight_smoothing > 0.0f && st->inflight > 0;
+    if (slot < 0 || ema_wait || (have_key && (gk < key || key < gk))) { ++it; continue; }
     // keep a stream's frames in submission order: skip later frames of a
     // stream whose earlier frame could not be taken
     bool earlier_waiting = false;
@@ -215,8 +229,12 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     hzd_frame_aux aux{};
     aux.A_out = reinterpret_cast<float*>(state);
     aux.sel_out = reinterpret_cast<int32_t*>(state + 16);
-    uint8_t* ws = base + 256 * kSlotsPerStream + st->ws_bytes * j.slot;
-    b.f[i] = make_frame_dev(st->p, j.fr, &aux, ws, &rz.f[i]);
+    uint8_t* ws = base + kWorkspacesOff + st->ws_bytes * j.slot;
+    hzd_frame fr = j.fr;
+    const bool ema = st->p.airlight_smoothing > 0.0f;
+    fr.airlight_state = ema ? reinterpret_cast<float*>(base + kAirlightStateOff) : nullptr;
+    b.f[i] = make_frame_dev(st->p, fr, &aux, ws, &rz.f[i]);
+    b.f[i].ema_first = ema && !st->ema_primed;
   }
   (void)hipSetDevice(s->cfg.device);
   int rc = launch_group(key, b, &rz, s->hstreams[hs]);
@@ -361,8 +379,8 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
   st->p = *params;
   st->W = width;
   st->H = height;
-  st->ws_bytes = (frame_ws_bytes(*params, width, height) + 255) & ~size_t(255);
-  st->arena_len = 256 * kSlotsPerStream + st->ws_bytes * kSlotsPerStream;
+  st->ws_bytes = stream_ws_bytes(*params, width, height);
+  st->arena_len = kWorkspacesOff + st->ws_bytes * kSlotsPerStream;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
@@ -430,6 +448,16 @@ int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns, int64_t
   st->done.erase(ticket);
   if (latency_ns) *latency_ns = res.second;
   return res.first;
+}
+
+int hzd_stream_arena_size(const hzd_params* params, int32_t width, int32_t height, size_t* bytes) {
+  if (!bytes) return fail(HZD_E_INVAL, "bytes is NULL");
+  int rc = validate_params(params);
+  if (rc) return rc;
+  if ((rc = validate_size(*params, width, height, 0)) != HZD_OK) return rc;
+  *bytes = kWorkspacesOff + stream_ws_bytes(*params, width, height) * kSlotsPerStream;
+  clear_error();
+  return HZD_OK;
 }
 
 int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host) {

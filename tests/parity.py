@@ -35,7 +35,7 @@ def oracle_params(p: hzd.Params) -> oracle.Params:
                          omega=p.omega, t0=p.t0, top_frac=p.top_frac, alpha=p.alpha, gamma=p.gamma,
                          gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=bool(p.color_balance),
                          tx="he" if p.tx == hzd.TX_HE else "paper", resize_width=p.resize_width,
-                         resize_height=p.resize_height)
+                         resize_height=p.resize_height, airlight_smoothing=p.airlight_smoothing)
 
 
 def to_dev(I: np.ndarray, pitch_pad: int = 0) -> torch.Tensor:
@@ -48,7 +48,7 @@ def to_dev(I: np.ndarray, pitch_pad: int = 0) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(I)).cuda()
 
 
-def run_gpu(I: np.ndarray, p: hzd.Params, pitch_pad: int = 0, with_J: bool = True):
+def run_gpu(I: np.ndarray, p: hzd.Params, pitch_pad: int = 0, with_J: bool = True, airlight_state=None):
     h, w, _ = I.shape
     src = to_dev(I, pitch_pad)
     ho, wo = p.output_shape(h, w)
@@ -58,7 +58,7 @@ def run_gpu(I: np.ndarray, p: hzd.Params, pitch_pad: int = 0, with_J: bool = Tru
     else:
         dst = torch.zeros((ho, wo, 3), dtype=torch.uint8, device="cuda")
     aux = hzd.make_aux(ho, wo, J=with_J)
-    hzd.dehaze_frame(src, dst, p, aux=aux)
+    hzd.dehaze_frame(src, dst, p, aux=aux, airlight_state=airlight_state)
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy() for k, v in aux.items()}
     out["out"] = dst.cpu().numpy() if not pitch_pad else dst.contiguous().cpu().numpy()

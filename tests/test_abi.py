@@ -35,8 +35,8 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(hzd.hzd_params) == 4 * 15
-    assert ctypes.sizeof(hzd.hzd_frame) == 8 + 8 + 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(hzd.hzd_params) == 4 * 16
+    assert ctypes.sizeof(hzd.hzd_frame) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(hzd.hzd_frame_aux) == 5 * 8
 
 
@@ -116,6 +116,31 @@ def test_resize_validation(L):
     assert call_frame(L, p, w=64, h=48, dp=3 * 64) == hzd.HZD_E_INVAL
     assert call_frame(L, p, w=64, h=48, dp=3 * 640, dst=FAKE_SRC - 100000) == hzd.HZD_E_INVAL
     assert call_frame(L, p, w=64, h=48, dp=3 * 640, ws_bytes=1000) == hzd.HZD_E_NOMEM
+
+
+def test_airlight_smoothing_validation(L):
+    for lam in (-0.1, 1.0, float("nan")):
+        assert call_frame(L, hzd.Params(airlight_smoothing=lam)) == hzd.HZD_E_INVAL, lam
+    # smoothing needs the stream's state; the state must be 16-byte aligned
+    assert call_frame(L, hzd.Params(airlight_smoothing=0.5)) == hzd.HZD_E_INVAL
+    p = hzd.Params(airlight_smoothing=0.5)
+    pc = p.c()
+    f = hzd.hzd_frame(FAKE_SRC, 192, FAKE_DST, 192, 64, 48, None, 0x30000008)
+    assert L.hzd_dehaze_frame(ctypes.byref(pc), ctypes.byref(f), None, 0x40000000, 1 << 40, None) == hzd.HZD_E_INVAL
+    # two frames of one call may not share a state
+    arr = (hzd.hzd_frame * 2)()
+    arr[0] = hzd.hzd_frame(FAKE_SRC, 192, FAKE_DST, 192, 64, 48, None, 0x30000000)
+    arr[1] = hzd.hzd_frame(FAKE_SRC + (1 << 20), 192, FAKE_DST + (1 << 20), 192, 64, 48, None, 0x30000000)
+    assert L.hzd_dehaze_batch(ctypes.byref(pc), arr, 2, None, 0x40000000, 1 << 40, None) == hzd.HZD_E_INVAL
+    assert "share" in hzd.last_error()
+
+
+def test_stream_arena_size(L):
+    for p, (w, h) in [(hzd.Params(), (320, 240)), (hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1), (640, 480)),
+                      (hzd.Params(resize_width=64, resize_height=48), (1920, 1080))]:
+        n = hzd.stream_arena_size(p, w, h)
+        ws = hzd.workspace_size(p, [(h, w)])
+        assert n % 256 == 0 and n >= 2 * ws + 3 * 256
 
 
 def test_workspace_size_with_resize(L):
