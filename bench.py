@@ -53,7 +53,7 @@ STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1080p_offline.txt")
 RESIZE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_resize_1080p_to_640x480_x8.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_16609_amd", "csrc", "hzd_kernels.hip")
-EXTRAS = ("320", "video", "uneven", "resize1", "resize8")
+EXTRAS = ("320", "video", "uneven", "resize1", "resize8", "smooth")
 
 
 def measured_traffic(kernel, path=TRAFFIC_FILE):
@@ -275,6 +275,58 @@ def uneven_64(hzd, torch, dev):
                                          "MP_per_batch": round(mp4, 2)}}
 
 
+def smoothing_workload(hzd, torch, dev, lams=(0.0, 0.9), n=32, passes=5, streams=8):
+    """Temporal airlight smoothing on the first frames of the 1280x720 panning clip (real time,
+    FP16 t): sequential frame calls carrying the stream's airlight state, and a server with
+    `streams` such streams, each at lam = 0 and lam > 0.  Reports throughput and the mean
+    frame-to-frame change of A (0..255 scale), the flicker the smoothing damps."""
+    from synth import make_video
+    sync = torch.cuda.synchronize
+    W, H = 1280, 720
+    mp = W * H / 1e6
+    v = make_video(W, H, nframes=300, seed=3)
+    frames = [torch.from_numpy(v.frame(f).I).to(dev) for f in range(n)]
+    out = {}
+    for lam in lams:
+        p = hzd.Params(precision=hzd.PREC_FP16, airlight_smoothing=lam)
+        state = hzd.make_airlight_state(dev)
+        ws = hzd.alloc_workspace(hzd.workspace_size(p, [(H, W)]), dev)
+        dst = torch.empty_like(frames[0])
+        As = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+        calls = [hzd.FrameCall(frames[k], dst, p, ws, aux={"A": As[k]}, airlight_state=state) for k in range(n)]
+        for c in calls:
+            c()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            for c in calls:
+                c()
+        sync()
+        seq_mps = passes * n * mp / (time.perf_counter() - t0)
+        A = As[:, :3].cpu().numpy().astype(np.float64)
+        dA = np.abs(np.diff(A, axis=0)).mean()
+        srv = hzd.Server(arena_bytes=streams * hzd.stream_arena_size(p, W, H) + 4096, max_inflight=16,
+                         frames_per_launch=8, hip_streams=4)
+        sts = [srv.open(p, W, H) for _ in range(streams)]
+        dsts = [torch.empty_like(frames[0]) for _ in range(streams)]
+        tk = [(st, st.submit(frames[0], dsts[i])) for i, st in enumerate(sts)]
+        for st, t in tk:
+            st.wait(t)
+        t0 = time.perf_counter()
+        tk = [(st, st.submit(frames[k], dsts[i])) for k in range(n) for i, st in enumerate(sts)]
+        for st, t in tk:
+            rc, _ = st.wait(t)
+            assert rc == 0, rc
+        served_mps = streams * n * mp / (time.perf_counter() - t0)
+        for st in sts:
+            st.close()
+        srv.close()
+        out[f"lambda_{lam:g}"] = {"sequential_frame_calls_MP_per_s": round(seq_mps, 1),
+                                  "served_MP_per_s": round(served_mps, 1),
+                                  "mean_abs_frame_to_frame_dA": round(float(dA), 4)}
+    return {"1280x720_clip_airlight_smoothing": dict(out, frames=n, served_streams=streams)}
+
+
 def extra_workloads(hzd, torch, dev, which=EXTRAS):
     """The other configurations, each timed on its own (inputs resident in HBM)."""
     out = {}
@@ -286,6 +338,8 @@ def extra_workloads(hzd, torch, dev, which=EXTRAS):
         out.update(uneven_64(hzd, torch, dev))
     if "resize1" in which or "resize8" in which:
         out.update(resize_workloads(hzd, torch, dev, which))
+    if "smooth" in which:
+        out.update(smoothing_workload(hzd, torch, dev))
     torch.cuda.empty_cache()
     return out
 
