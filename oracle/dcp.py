@@ -46,7 +46,12 @@ parameter or a documented choice of the GPU library):
     flicker concern of Sec. V): A_t = lam A_{t-1} + (1 - lam) Ahat_t, where
     Ahat_t is the frame's own Eq. (3) estimate (float64) and A_{t-1} is the
     previous frame's A as stored (float32); the sum is formed in float64 as
-    (lam * A_{t-1}) + ((1 - lam) * Ahat_t).  The first frame takes A = Ahat.
+    (lam * A_{t-1}) + ((1 - lam) * Ahat_t).  The first frame takes A = Ahat;
+  * the "gamma-adaptive" correction named in the abstract has no rule in the
+    paper; the reading here picks, per frame, the gamma that maps the mean
+    BT.601 luma mu of the recovered J (on [0, 1]) to a target tau:
+    mu^(1/gamma) = tau, i.e. gamma = ln(mu) / ln(tau), with mu floored at
+    2^-20 and gamma clamped to [1/2, 2].
 All functions are pinned by tests against brute force, closed forms,
 invariants or independent library routines (scipy.ndimage).
 """
@@ -79,6 +84,8 @@ class Params:
     resize_width: int = 0          # Sec. V step 1 target size; 0 x 0 = native size
     resize_height: int = 0
     airlight_smoothing: float = 0.0  # lam of the temporal airlight average; 0 = none
+    gamma_adaptive: bool = False     # per-frame gamma from the mean luma of J (gamma unused)
+    gamma_target: float = 0.5        # tau: the mean luma the adaptive gamma aims for
 
     def f(self, name):
         return f32(getattr(self, name))
@@ -343,6 +350,26 @@ def gamma_correct(J: np.ndarray, gamma: float) -> np.ndarray:
     return 255.0 * np.power(J / 255.0, 1.0 / f32(gamma))
 
 
+GAMMA_ADAPTIVE_MIN, GAMMA_ADAPTIVE_MAX = 0.5, 2.0
+MU_FLOOR = 2.0 ** -20
+
+
+def adaptive_gamma(J: np.ndarray, target: float) -> float:
+    """Per-frame gamma: ln(mu) / ln(tau) for the mean luma mu of J/255, clamped.
+
+    mu is the mean over pixels of (0.299 R + 0.587 G + 0.114 B) / 255 of the
+    clamped J of Eq. (7); tau is taken as its float32 value.
+    """
+    mu = float(np.mean(0.299 * J[:, :, 0] + 0.587 * J[:, :, 1] + 0.114 * J[:, :, 2])) / 255.0
+    g = math.log(max(mu, MU_FLOOR)) / math.log(f32(target))
+    return min(max(g, GAMMA_ADAPTIVE_MIN), GAMMA_ADAPTIVE_MAX)
+
+
+def gamma_power(J: np.ndarray, gamma: float) -> np.ndarray:
+    """Eq. (8) with a gamma given in float64 (the adaptive case)."""
+    return 255.0 * np.power(J / 255.0, 1.0 / gamma)
+
+
 def gray_world(Jg: np.ndarray):
     """Gray-world colour balance: g_c = mean(mu) / mu_c, output clamped to 255."""
     mu = Jg.reshape(-1, 3).mean(axis=0)
@@ -409,7 +436,12 @@ def dehaze(I: np.ndarray, p: Params, A_inject=None, A_prev=None) -> Result:
     aux["t"] = t
     J = reconstruct(I, A, t)
     aux["J"] = J
-    Jg = gamma_correct(J, p.gamma)
+    if p.gamma_adaptive:
+        g = adaptive_gamma(J, p.gamma_target)
+        aux["gamma"] = g
+        Jg = gamma_power(J, g)
+    else:
+        Jg = gamma_correct(J, p.gamma)
     aux["Jg"] = Jg
     if p.color_balance:
         Jf, gains = gray_world(Jg)

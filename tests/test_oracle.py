@@ -477,3 +477,43 @@ def test_smoothed_airlight_drives_transmission_and_recovery():
     injected = oracle.dehaze(f1, Params(mode="offline", gf_radius=8), A_inject=seq[1].aux["A"])
     assert np.array_equal(seq[1].out, injected.out)
     assert not np.array_equal(seq[1].aux["A"], seq[1].aux["A_hat"])
+
+
+# ------------------------------------------------------------ adaptive gamma
+def test_adaptive_gamma_maps_a_constant_frame_to_the_target():
+    # for a constant gray J = v the mean luma is v/255, and (v/255)^(1/gamma) = tau exactly
+    for v, tau in [(60.0, 0.5), (128.0, 0.45), (200.0, 0.6), (90.0, 0.3), (10.0, 0.5), (250.0, 0.5)]:
+        J = np.full((6, 9, 3), v)
+        g = oracle.adaptive_gamma(J, tau)
+        raw = math.log(v / 255.0) / math.log(float(np.float32(tau)))
+        assert g == pytest.approx(min(max(raw, 0.5), 2.0), rel=1e-15)
+        if 0.5 < g < 2.0:
+            assert np.allclose(oracle.gamma_power(J, g), 255.0 * float(np.float32(tau)), rtol=1e-12)
+
+
+def test_adaptive_gamma_weights_and_clamps():
+    # one channel at a time: the BT.601 weight of that channel sets the mean luma
+    for c, wgt in enumerate((0.299, 0.587, 0.114)):
+        J = np.zeros((4, 4, 3))
+        J[:, :, c] = 255.0
+        # tau = 3/8 is exact in binary32
+        assert oracle.adaptive_gamma(J, 0.375) == pytest.approx(
+            min(max(math.log(wgt) / math.log(0.375), 0.5), 2.0), rel=1e-12)
+    assert oracle.adaptive_gamma(np.zeros((3, 3, 3)), 0.5) == 2.0         # black: mu floored, gamma clamped
+    assert oracle.adaptive_gamma(np.full((3, 3, 3), 255.0), 0.5) == 0.5   # white: ln(1) = 0, clamped
+    # the mean is over every pixel: half black, half of a level
+    J = np.zeros((2, 8, 3))
+    J[:, :4] = 200.0
+    assert oracle.adaptive_gamma(J, 0.5) == pytest.approx(math.log(100.0 / 255.0) / math.log(0.5), rel=1e-12)
+
+
+def test_pipeline_with_adaptive_gamma_uses_the_frame_gamma():
+    I = (make_frame(64, 48, 5).I * 0.35).astype(np.uint8)   # a darker frame: gamma inside the clamp
+    r = oracle.dehaze(I, Params(gamma_adaptive=True, gamma_target=0.5))
+    assert 0.5 < r.aux["gamma"] < 2.0
+    g = r.aux["gamma"]
+    assert g == oracle.adaptive_gamma(r.aux["J"], 0.5)
+    assert np.allclose(r.aux["Jg"], 255.0 * (r.aux["J"] / 255.0) ** (1.0 / g), rtol=1e-14, atol=0)
+    # brighter target -> lower gamma exponent 1/gamma -> brighter output on average
+    r2 = oracle.dehaze(I, Params(gamma_adaptive=True, gamma_target=0.7))
+    assert r2.aux["gamma"] > g and r2.out.mean() > r.out.mean()
