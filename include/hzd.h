@@ -117,7 +117,17 @@ typedef enum {
  *                  stored in the stream's airlight state; the sum is formed
  *                  in double as (lam * A_prev) + ((1 - lam) * Ahat) and rounded
  *                  to float.  0 (the default) = every frame on its own.  A
- *                  frame call with lam > 0 needs hzd_frame.airlight_state. */
+ *                  frame call with lam > 0 needs hzd_frame.airlight_state.
+ *   gamma_adaptive 0/1: the "gamma-adaptive" correction the abstract names,
+ *                  for which the paper gives no rule.  With 1 each frame takes
+ *                  gamma = ln(mu) / ln(gamma_target), where mu is the mean
+ *                  BT.601 luma of its recovered J (Eq. (7), clamped) divided
+ *                  by 255, floored at 2^-20; gamma is clamped to [1/2, 2] and
+ *                  `gamma` is not used.  mu^(1/gamma) = gamma_target, so the
+ *                  frame's mean luma is mapped to the target.  Costs one more
+ *                  pass over the frame (the sums of J must be complete
+ *                  before any pixel is corrected).
+ *   gamma_target   tau in (0, 1), the mean luma aimed for (default 0.5). */
 typedef struct hzd_params {
   uint32_t size;
   int32_t mode;
@@ -135,6 +145,8 @@ typedef struct hzd_params {
   int32_t resize_width;
   int32_t resize_height;
   float airlight_smoothing;
+  int32_t gamma_adaptive;
+  float gamma_target;
 } hzd_params;
 
 /* One frame: device pointers and geometry (see the conventions above).

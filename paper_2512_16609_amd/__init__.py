@@ -41,7 +41,8 @@ class hzd_params(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("gamma", ctypes.c_float), ("gf_radius", ctypes.c_int32),
                 ("gf_eps", ctypes.c_float), ("color_balance", ctypes.c_int32), ("tx", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("resize_width", ctypes.c_int32),
-                ("resize_height", ctypes.c_int32), ("airlight_smoothing", ctypes.c_float)]
+                ("resize_height", ctypes.c_int32), ("airlight_smoothing", ctypes.c_float),
+                ("gamma_adaptive", ctypes.c_int32), ("gamma_target", ctypes.c_float)]
 
 
 class hzd_frame(ctypes.Structure):
@@ -167,12 +168,15 @@ class Params:
     resize_width: int = 0     # Sec. V step 1 working size; 0 x 0 = the frame's own size
     resize_height: int = 0
     airlight_smoothing: float = 0.0   # temporal airlight weight lam; needs an airlight state
+    gamma_adaptive: int = 0   # 1: per-frame gamma mapping the mean luma of J to gamma_target
+    gamma_target: float = 0.5
 
     def c(self) -> hzd_params:
         return hzd_params(ctypes.sizeof(hzd_params), self.mode, self.patch, self.omega, self.t0,
                           self.top_frac, self.alpha, self.gamma, self.gf_radius, self.gf_eps,
                           int(self.color_balance), self.tx, self.precision, self.resize_width,
-                          self.resize_height, self.airlight_smoothing)
+                          self.resize_height, self.airlight_smoothing, int(self.gamma_adaptive),
+                          self.gamma_target)
 
     def output_shape(self, h: int, w: int) -> tuple:
         """(height, width) of the output of a frame of input shape (h, w)."""
@@ -186,7 +190,7 @@ class Params:
         _check(lib().hzd_params_default(ctypes.byref(p), preset), "hzd_params_default")
         return Params(p.mode, p.patch, p.omega, p.t0, p.top_frac, p.alpha, p.gamma, p.gf_radius,
                       p.gf_eps, p.color_balance, p.tx, p.precision, p.resize_width, p.resize_height,
-                      p.airlight_smoothing)
+                      p.airlight_smoothing, p.gamma_adaptive, p.gamma_target)
 
 
 # ------------------------------------------------------------------ frames

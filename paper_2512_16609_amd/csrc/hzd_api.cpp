@@ -62,6 +62,10 @@ int validate_params(const hzd_params* p) {
       return fail(HZD_E_UNSUPPORTED, "gf_radius %d > %d", p->gf_radius, kMaxRadius);
     if (!in_range(p->gf_eps, 1e-8f, 1.0f)) return fail(HZD_E_INVAL, "gf_eps %g outside [1e-8,1]", p->gf_eps);
   }
+  if (p->gamma_adaptive != 0 && p->gamma_adaptive != 1)
+    return fail(HZD_E_INVAL, "gamma_adaptive %d must be 0 or 1", p->gamma_adaptive);
+  if (p->gamma_adaptive && !(p->gamma_target > 0.0f && p->gamma_target < 1.0f))
+    return fail(HZD_E_INVAL, "gamma_target %g outside (0,1)", p->gamma_target);
   if (!(p->airlight_smoothing >= 0.0f && p->airlight_smoothing < 1.0f))
     return fail(HZD_E_INVAL, "airlight_smoothing %g outside [0,1)", p->airlight_smoothing);
   if (p->resize_width != 0 || p->resize_height != 0) {
@@ -122,6 +126,7 @@ GroupKey group_key(const hzd_params& p) {
   g.fp16 = p.precision == HZD_PREC_FP16;
   g.radius = p.mode == HZD_MODE_OFFLINE ? p.gf_radius : 0;
   g.resize = p.resize_width != 0;
+  g.gadapt = p.gamma_adaptive;
   return g;
 }
 
@@ -145,7 +150,7 @@ size_t frame_ws_bytes(const hzd_params& p, int Win, int Hin) {
     s += a256((size_t)W * H * 8);                      // AB
     const size_t nch = (size_t)((H + 7) / 8);
     s += a256(nch * W * 8) + a256(nch * W * 16) + a256(nch * W * 16);  // 8-row chunk sums
-    if (p.color_balance) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
+    if (p.color_balance || p.gamma_adaptive) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
   }
   return s;
 }
@@ -300,7 +305,7 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     off += a256(nch * W * 16);
     d.S8ab = reinterpret_cast<longlong2*>(ws + off);
     off += a256(nch * W * 16);
-    if (p.color_balance) {
+    if (p.color_balance || p.gamma_adaptive) {  // the refined t waits for a frame-wide sum
       d.tmap = ws + off;
       off += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
     }
@@ -321,7 +326,7 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   const double g = (double)p.gamma;
   d.inv_gamma = (float)(1.0 / g);
   d.gamma_log_bias = (float)(std::log2(255.0) * (1.0 - 1.0 / g));
-  d.gamma_is_one = p.gamma == 1.0f;
+
   d.eps = p.gf_eps;
   if (offline) {
     // |a| <= 1 / (4 sqrt(eps)) for p in [0,1]; |b| <= 1 + |a|; scale 2^k keeps both in int32
@@ -333,9 +338,11 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   d.gf_rows = tile_config_for(W, H).gf_rows;
   d.A_state = fr.airlight_state;
   d.ema = p.airlight_smoothing;
-  d.ema_first = 0;
-  d.aligned = ((uintptr_t)d.src % 4 == 0) && ((uintptr_t)d.dst % 4 == 0) && (d.src_pitch % 4 == 0) &&
-              (d.dst_pitch % 4 == 0);
+  d.gamma_target = p.gamma_target;
+  const bool aligned = ((uintptr_t)d.src % 4 == 0) && ((uintptr_t)d.dst % 4 == 0) && (d.src_pitch % 4 == 0) &&
+                       (d.dst_pitch % 4 == 0);
+  d.flags = (p.gamma == 1.0f ? kFdGammaOne : 0u) | (aligned ? kFdAligned : 0u) |
+            (p.gamma_adaptive ? kFdGammaAdaptive : 0u);
   return d;
 }
 
@@ -404,10 +411,23 @@ int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStrea
     if ((rc = stage(prof, "gf_prep", s, [&] { return launch_gf_prep(b, g, s); })) != HZD_OK) return rc;
     if ((rc = stage(prof, "gf_ab", s, [&] { return launch_gf_ab(b, g, s); })) != HZD_OK) return rc;
     if ((rc = stage(prof, "gf_q", s, [&] { return launch_gf_q(b, g, s); })) != HZD_OK) return rc;
-    if (g.cb && (rc = stage(prof, "recon_apply", s, [&] { return launch_recon(b, g, TSRC_TMAP, 2, s); })) != HZD_OK)
+    if (g.gadapt) {  // the t map and luma sums are stored: gamma, then balance and output
+      if (g.cb) {
+        if ((rc = stage(prof, "recon_sums", s, [&] { return launch_recon(b, g, TSRC_TMAP, 1, s); })) != HZD_OK)
+          return rc;
+        if ((rc = stage(prof, "recon_apply", s, [&] { return launch_recon(b, g, TSRC_TMAP, 2, s); })) != HZD_OK)
+          return rc;
+      } else if ((rc = stage(prof, "recon", s, [&] { return launch_recon(b, g, TSRC_TMAP, 0, s); })) != HZD_OK) {
+        return rc;
+      }
+    } else if (g.cb &&
+               (rc = stage(prof, "recon_apply", s, [&] { return launch_recon(b, g, TSRC_TMAP, 2, s); })) != HZD_OK) {
       return rc;
+    }
   } else {
     const int tsrc = he ? TSRC_HE : TSRC_PAPER;
+    if (g.gadapt && (rc = stage(prof, "recon_luma", s, [&] { return launch_recon(b, g, tsrc, 3, s); })) != HZD_OK)
+      return rc;
     if (g.cb) {
       if ((rc = stage(prof, "recon_sums", s, [&] { return launch_recon(b, g, tsrc, 1, s); })) != HZD_OK) return rc;
       if ((rc = stage(prof, "recon_apply", s, [&] { return launch_recon(b, g, tsrc, 2, s); })) != HZD_OK) return rc;
@@ -607,6 +627,8 @@ int hzd_params_default(hzd_params* p, int32_t preset) {
   p->color_balance = 0;
   p->tx = HZD_TX_HE;
   p->precision = HZD_PREC_FP32;
+  p->gamma_adaptive = 0;
+  p->gamma_target = 0.5f;
   switch (preset) {
     case HZD_PRESET_REALTIME: break;
     case HZD_PRESET_OFFLINE:

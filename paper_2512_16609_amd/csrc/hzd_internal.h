@@ -26,6 +26,7 @@ struct FrameState {
   float A[4];                           // airlight A^c (0..255 scale)
   int32_t sel[4];                       // K, vstar, cutoff, consistency flag (0 = ok)
   unsigned long long cb[kCbSlots][4];   // sum of J_gamma^c in 2^-23 fixed point, per slot
+  unsigned long long luma[kCbSlots];    // adaptive gamma: sum of the BT.601 luma of J in 2^-16 fixed point
 };
 static_assert(sizeof(FrameState) <= 12288, "FrameState too large");
 
@@ -59,6 +60,7 @@ struct FrameDev {
   uint8_t* dark_out;
   float* t_out;
   float* J_out;
+  float* A_state;    // stream airlight state {A[3], frames} (NULL = none)
   int32_t W, H;
   int32_t D_pitch, E_pitch;
   int32_t K;
@@ -66,13 +68,17 @@ struct FrameDev {
   float omega, t0, alpha, inv_gamma, gamma_log_bias;  // gamma_log_bias = log2(255) (1 - 1/gamma)
   float eps;
   float ab_scale, ab_inv_scale;                      // fixed-point scale of a, b
-  int32_t gamma_is_one;
-  int32_t aligned;   // src, dst and both pitches are multiples of 4
   int32_t gf_rows;   // output rows per guided-filter block
-  float* A_state;    // stream airlight state {A[3], frames} (NULL = none)
   float ema;         // temporal airlight weight lam (0 = none)
-  int32_t ema_first; // 1 = the stream's first frame: ignore the stored state
+  float gamma_target;  // tau of the adaptive gamma
+  uint32_t flags;    // kFd* bits
 };
+
+// FrameDev.flags
+constexpr uint32_t kFdGammaOne = 1u;        // gamma == 1: Eq. (8) is the identity
+constexpr uint32_t kFdAligned = 2u;         // src, dst and both pitches are multiples of 4
+constexpr uint32_t kFdEmaFirst = 4u;        // the stream's first frame: ignore the stored airlight
+constexpr uint32_t kFdGammaAdaptive = 8u;   // per-frame gamma from the luma sums of J
 
 struct Batch {
   int32_t n;
@@ -103,7 +109,7 @@ struct ResizeBatch {
 
 // Group-wide kernel switches (identical for all frames of one launch).
 struct GroupKey {
-  int32_t mode, half_patch, tx, cb, fp16, radius, resize;
+  int32_t mode, half_patch, tx, cb, fp16, radius, resize, gadapt;
 };
 
 // Launches (hzd_kernels.hip).  Each fills b.tile0 for its own tiling.

@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
       if (!cand) continue;
       // the lane's 16 pixels of I in one round trip when the rows are dword aligned
       uint32_t iw[12];
-      const bool vec = fd.aligned && nx == 16;
+      const bool vec = (fd.flags & kFdAligned) && nx == 16;
       if (vec) {
         const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow + 3 * base);
 #pragma unroll
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     const uint32_t avail = (run + ex < k) ? min(cnt, k - run - ex) : 0u;
     if (avail) {
       uint32_t iw[12];
-      const bool vec = fd.aligned && x0 + 16 <= W;
+      const bool vec = (fd.flags & kFdAligned) && x0 + 16 <= W;
       if (vec) {
         const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow + 3 * x0);
 #pragma unroll
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     // temporal average with the stream's stored airlight: (lam A_prev) +
     // ((1 - lam) Ahat) in double, each operation rounded on its own
     float* ast = fd.A_state;
-    const bool blend = ast && fd.ema > 0.0f && !fd.ema_first && __float_as_uint(ast[3]) != 0u;
+    const bool blend = ast && fd.ema > 0.0f && !(fd.flags & kFdEmaFirst) && __float_as_uint(ast[3]) != 0u;
     const double lam = (double)fd.ema;
     for (int ch = 0; ch < 3; ++ch) {
       double Ad = a * (double)S[ch] / (double)K;
@@ -831,7 +831,7 @@ __device__ __forceinline__ ReconConsts recon_consts(const FrameDev& fd) {
   for (int c = 0; c < 3; ++c) rc.A[c] = fd.st->A[c];
   rc.inv_gamma = fd.inv_gamma;
   rc.bias = fd.gamma_log_bias;
-  rc.gamma_is_one = fd.gamma_is_one;
+  rc.gamma_is_one = (fd.flags & kFdGammaOne) != 0;
   return rc;
 }
 
@@ -1286,12 +1286,44 @@ __device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3], unsigne
   for (int c = 0; c < 3; ++c) g[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
 }
 
+// Adaptive gamma (the abstract's "gamma-adaptive" correction, with the rule
+// gamma = ln(mu) / ln(tau)): mu is the mean BT.601 luma of J / 255 from exact
+// fixed-point sums, floored at 2^-20, and gamma is clamped to [1/2, 2].
+// Every block of a launch derives the same value from the same integers.
+__device__ __forceinline__ uint32_t luma_fixed(const float J[3]) {
+  const float y = fmaf(0.114f, J[2], fmaf(0.587f, J[1], 0.299f * J[0]));   // <= 255
+  return (uint32_t)__builtin_rintf(y * 65536.0f);
+}
+
+__device__ __forceinline__ void luma_accumulate(const FrameDev& fd, int tile, unsigned long long acc,
+                                                unsigned long long* s_tmp) {
+  const unsigned long long v = block_sum(acc, s_tmp);
+  if (threadIdx.x == 0) atomicAdd(&fd.st->luma[tile % kCbSlots], v);
+}
+
+__device__ __forceinline__ void adaptive_gamma(const FrameDev& fd, ReconConsts& rc, unsigned long long* s_g) {
+  static_assert(kCbSlots == 64, "one slot per lane of wave 0");
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const unsigned long long v = wave_sum(fd.st->luma[t]);
+    if (t == 0) *s_g = v;
+  }
+  __syncthreads();
+  const double mu = (double)(*s_g) / (65536.0 * 255.0 * (double)fd.W * (double)fd.H);
+  double g = log(fmax(mu, 0x1p-20)) / log((double)fd.gamma_target);
+  g = fmin(fmax(g, 0.5), 2.0);
+  rc.inv_gamma = (float)(1.0 / g);
+  rc.bias = (float)(log2(255.0) * (1.0 - 1.0 / g));
+  rc.gamma_is_one = g == 1.0;
+}
+
 // ------------------------------------------------------------------- k_gf_q
 // Eq. (6), stage 2: box means of a and b (exact i64 sums of the fixed-point
 // values, same strip scheme, kRpi rows per barrier phase), q = mean(a) G +
 // mean(b), clamped to [t0, 1].  PHASE 0: fuse Eqs. (7)-(8) and write the
-// output.  PHASE 1: store the refined t and the colour-balance sums.  AUX:
-// some frame of the launch asks for its t or J maps.
+// output.  PHASE 1: store the refined t and the colour-balance sums.  PHASE 2:
+// store the refined t and the luma sums of J (adaptive gamma).  AUX: some
+// frame of the launch asks for its t or J maps.
 template <int NI, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   // two buffers, alternating by phase: a phase's scan and output read one
@@ -1432,10 +1464,10 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         const double G = (double)curL[j] * (1.0 / 255000.0);
         const double qt = fma(qa * in, G, qb * in);
         float t = (float)fmin(fmax(qt, t0), 1.0);
-        // FP16 applies to the stored t map (PHASE 1): the colour-balance sums here use
-        // the same binary16 value that the apply pass reads back.  The fused output
+        // FP16 applies to the stored t map (PHASE 1, 2): the sums here use the same
+        // binary16 value that the later passes read back.  The fused output
         // (PHASE 0) keeps binary32 t, as it never leaves registers.
-        if (FP16 && PHASE == 1) t = round_half(t);
+        if (FP16 && PHASE != 0) t = round_half(t);
         const int64_t pi = (int64_t)y * W + x;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
         const uint32_t c = curRG[j] | (curB[j] << 16);
@@ -1453,12 +1485,17 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         } else {
           if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
           else reinterpret_cast<float*>(fd.tmap)[pi] = t;
-          acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+          if (PHASE == 1) {
+            acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+          } else {
+            acc[0] += luma_fixed(J);
+          }
         }
       }
     }
   }
   if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
+  if (PHASE == 2) luma_accumulate(fd, tile, acc[0], s_red);
 }
 
 // ------------------------------------------------------------------ k_recon
@@ -1467,7 +1504,9 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 // groups of 4 pixels, kReconPx / 2 apart, and issues the loads of both groups
 // before any arithmetic.  PHASE 0: write the output.  PHASE 1: colour-balance
 // sums only.  PHASE 2: form the gray-world gains from the sums, apply them and
-// write.  AUX: some frame of the launch asks for its t or J maps.
+// write.  PHASE 3: luma sums of J only (adaptive gamma; the later phases of a
+// frame with adaptive gamma take its gamma from them).  AUX: some frame of
+// the launch asks for its t or J maps.
 __device__ __forceinline__ void load_rgb12(const uint8_t* p, int nx, bool aligned, uint32_t w[3]) {
   if (aligned && nx == 4) {
     const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
@@ -1484,7 +1523,9 @@ __device__ __forceinline__ void load_rgb12(const uint8_t* p, int nx, bool aligne
 template <int TSRC, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_recon(Batch b) {
   static_assert(kReconPx == 2 * 4 * 256, "two groups of 4 pixels per thread");
+  constexpr bool OUT = PHASE == 0 || PHASE == 2;   // this phase writes the output
   __shared__ unsigned long long s_red[4];
+  __shared__ unsigned long long s_gam[1];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -1494,7 +1535,8 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   const int y = tile / per_row;
   const int xb = (tile - y * per_row) * kReconPx + 4 * (int)threadIdx.x;
   const TxConsts k = tx_consts(fd);
-  const ReconConsts rc = recon_consts(fd);
+  ReconConsts rc = recon_consts(fd);
+  if (PHASE != 3 && (fd.flags & kFdGammaAdaptive)) adaptive_gamma(fd, rc, s_gam);   // uniform per block
   float gain[3] = {1.f, 1.f, 1.f};
   if (PHASE == 2) cb_gains(fd, gain, s_red);
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
@@ -1511,7 +1553,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
     ew[q][0] = ew[q][1] = ew[q][2] = 0u;
     tm[q][0] = tm[q][1] = tm[q][2] = tm[q][3] = 1.0f;
     if (nx[q] > 0) {
-      load_rgb12(fd.src + (int64_t)y * fd.src_pitch + 3 * x0[q], nx[q], fd.aligned, iw[q]);
+      load_rgb12(fd.src + (int64_t)y * fd.src_pitch + 3 * x0[q], nx[q], (fd.flags & kFdAligned), iw[q]);
       if (TSRC == TSRC_HE) load_rgb12(fd.E + (int64_t)y * fd.E_pitch + 3 * x0[q], nx[q], true, ew[q]);
       if (TSRC == TSRC_TMAP) {
         const int64_t pi = (int64_t)y * W + x0[q];
@@ -1550,7 +1592,9 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
         t = tm[q][i];  // binary16 maps hold values exactly representable in binary32
       }
       recon_pixel(rc, I, t, J, Jg);
-      if (PHASE == 1) {
+      if (PHASE == 3) {
+        acc[0] += luma_fixed(J);
+      } else if (PHASE == 1) {
         acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
       } else {
         const int64_t pi = (int64_t)y * W + x0[q] + i;
@@ -1574,9 +1618,9 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       for (int i = 0; i < 4; ++i)
         if (i < nx[q]) px(i);
     }
-    if (PHASE != 1) {
+    if (OUT) {
       uint8_t* Op = fd.dst + (int64_t)y * fd.dst_pitch + 3 * x0[q];
-      if (fd.aligned && nx[q] == 4) {
+      if ((fd.flags & kFdAligned) && nx[q] == 4) {
         uint32_t* o = reinterpret_cast<uint32_t*>(Op);
         o[0] = ow[0]; o[1] = ow[1]; o[2] = ow[2];
       } else {
@@ -1585,6 +1629,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
     }
   }
   if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
+  if (PHASE == 3) luma_accumulate(fd, tile, acc[0], s_red);
 }
 
 // ----------------------------------------------------------------- launches
@@ -1700,6 +1745,7 @@ hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s) {
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
   const bool aux = any_aux_maps(b);
+  if (g.gadapt) return gf_q_p<2>(b, nblk, g.radius, g.fp16, aux, s);
   if (g.cb) return gf_q_p<1>(b, nblk, g.radius, g.fp16, aux, s);
   return gf_q_p<0>(b, nblk, g.radius, g.fp16, aux, s);
 }
@@ -1722,6 +1768,7 @@ hipError_t recon_t(const Batch& b, int nblk, int phase, bool fp16, bool aux, hip
     case 0: return recon_tp<TSRC, 0>(b, nblk, fp16, aux, s);
     case 1: return recon_tp<TSRC, 1>(b, nblk, fp16, false, s);   // sums only: no maps written
     case 2: return recon_tp<TSRC, 2>(b, nblk, fp16, aux, s);
+    case 3: return recon_tp<TSRC, 3>(b, nblk, fp16, false, s);   // luma sums only
     default: return hipErrorInvalidValue;
   }
 }

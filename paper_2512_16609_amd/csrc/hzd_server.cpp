@@ -234,7 +234,7 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     const bool ema = st->p.airlight_smoothing > 0.0f;
     fr.airlight_state = ema ? reinterpret_cast<float*>(base + kAirlightStateOff) : nullptr;
     b.f[i] = make_frame_dev(st->p, fr, &aux, ws, &rz.f[i]);
-    b.f[i].ema_first = ema && !st->ema_primed;
+    if (ema && !st->ema_primed) b.f[i].flags |= kFdEmaFirst;
   }
   (void)hipSetDevice(s->cfg.device);
   int rc = launch_group(key, b, &rz, s->hstreams[hs]);

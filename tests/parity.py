@@ -35,7 +35,8 @@ def oracle_params(p: hzd.Params) -> oracle.Params:
                          omega=p.omega, t0=p.t0, top_frac=p.top_frac, alpha=p.alpha, gamma=p.gamma,
                          gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=bool(p.color_balance),
                          tx="he" if p.tx == hzd.TX_HE else "paper", resize_width=p.resize_width,
-                         resize_height=p.resize_height, airlight_smoothing=p.airlight_smoothing)
+                         resize_height=p.resize_height, airlight_smoothing=p.airlight_smoothing,
+                         gamma_adaptive=bool(p.gamma_adaptive), gamma_target=p.gamma_target)
 
 
 def to_dev(I: np.ndarray, pitch_pad: int = 0) -> torch.Tensor:
@@ -72,7 +73,7 @@ def fp16_output_bound(I: np.ndarray, p: hzd.Params, a: dict, rtol: float) -> np.
     scale = np.abs(I.astype(np.float64) - A[None, None, :]) / t_ref[..., None] + np.abs(A)[None, None, :]
     dJ = rtol * scale + 1e-4
     J = a["J"]
-    gamma = float(np.float32(p.gamma))
+    gamma = a["gamma"] if "gamma" in a else float(np.float32(p.gamma))   # the frame's gamma if adaptive
 
     def f(x):
         return 255.0 * (np.clip(x, 0.0, 255.0) / 255.0) ** (1.0 / gamma)
@@ -101,7 +102,8 @@ def compare(I: np.ndarray, p: hzd.Params, g: dict, ref=None, label: str = "") ->
     assert int(g["sel"][2]) == a["cutoff"], f"{label}: cutoff {g['sel'][2]} != {a['cutoff']}"
     A32 = a["A"].astype(np.float32)
     assert np.array_equal(g["A"], A32), f"{label}: A {g['A']} != {A32}"
-    fp16_map = p.precision == hzd.PREC_FP16 and p.mode == hzd.MODE_OFFLINE and bool(p.color_balance)
+    fp16_map = (p.precision == hzd.PREC_FP16 and p.mode == hzd.MODE_OFFLINE
+                and bool(p.color_balance or p.gamma_adaptive))
     rtol = RTOL_FP16 if fp16_map else RTOL_FP32
     t_ref = a["t"]
     t_err = np.abs(g["t"].astype(np.float64) - t_ref) / t_ref

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(hzd.hzd_params) == 4 * 16
+    assert ctypes.sizeof(hzd.hzd_params) == 4 * 18
     assert ctypes.sizeof(hzd.hzd_frame) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(hzd.hzd_frame_aux) == 5 * 8
 
@@ -116,6 +116,15 @@ def test_resize_validation(L):
     assert call_frame(L, p, w=64, h=48, dp=3 * 64) == hzd.HZD_E_INVAL
     assert call_frame(L, p, w=64, h=48, dp=3 * 640, dst=FAKE_SRC - 100000) == hzd.HZD_E_INVAL
     assert call_frame(L, p, w=64, h=48, dp=3 * 640, ws_bytes=1000) == hzd.HZD_E_NOMEM
+
+
+def test_adaptive_gamma_validation(L):
+    for flag, tau in [(2, 0.5), (-1, 0.5), (1, 0.0), (1, 1.0), (1, float("nan"))]:
+        assert call_frame(L, hzd.Params(gamma_adaptive=flag, gamma_target=tau)) == hzd.HZD_E_INVAL, (flag, tau)
+    # the target is only checked when the adaptive rule is on
+    off = hzd.Params(mode=hzd.MODE_OFFLINE, gamma_adaptive=1)
+    assert hzd.workspace_size(off, [(480, 640)]) == hzd.workspace_size(
+        hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1), [(480, 640)])   # both store the t map
 
 
 def test_airlight_smoothing_validation(L):
