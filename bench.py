@@ -53,7 +53,7 @@ STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1080p_offline.txt")
 RESIZE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_resize_1080p_to_640x480_x8.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_16609_amd", "csrc", "hzd_kernels.hip")
-EXTRAS = ("320", "video", "uneven", "resize1", "resize8", "smooth")
+EXTRAS = ("320", "video", "uneven", "resize1", "resize8", "smooth", "gamma")
 
 
 def measured_traffic(kernel, path=TRAFFIC_FILE):
@@ -327,6 +327,35 @@ def smoothing_workload(hzd, torch, dev, lams=(0.0, 0.9), n=32, passes=5, streams
     return {"1280x720_clip_airlight_smoothing": dict(out, frames=n, served_streams=streams)}
 
 
+def adaptive_gamma_workload(hzd, torch, dev, reps=200):
+    """Adaptive per-frame gamma against a fixed gamma on the 1920x1080 frame, one frame per call:
+    offline (guided filter r=60, colour balance) and real time.  The adaptive rule needs the
+    frame-wide luma sums of J before any pixel is corrected, so it adds a pass; its stage times
+    come from HIP events on the launch stream."""
+    from synth import make_frame
+    sync = torch.cuda.synchronize
+    W, H = 1920, 1080
+    mp = W * H / 1e6
+    src = torch.from_numpy(make_frame(W, H, 2).I).to(dev)
+    dst = torch.empty_like(src)
+    out = {}
+    for mode, name in ((hzd.MODE_OFFLINE, "offline"), (hzd.MODE_REALTIME, "realtime")):
+        row = {}
+        for adaptive in (0, 1):
+            p = hzd.Params(mode=mode, gf_radius=60, color_balance=int(mode == hzd.MODE_OFFLINE),
+                           gamma_adaptive=adaptive, gamma_target=0.7)
+            ws = hzd.alloc_workspace(hzd.workspace_size(p, [(H, W)]), dev)
+            call = hzd.FrameCall(src, dst, p, ws)
+            for _ in range(10):
+                call()
+            per = timed(call, reps, sync)
+            us = stage_us(hzd, call, 50, sync)
+            row["adaptive" if adaptive else "fixed"] = {"MP_per_s": round(mp / per, 1), "us_per_frame": round(per * 1e6, 2),
+                                                        "stage_us": {k: round(v, 2) for k, v in us.items()}}
+        out[name] = row
+    return {"1920x1080_adaptive_gamma": out}
+
+
 def extra_workloads(hzd, torch, dev, which=EXTRAS):
     """The other configurations, each timed on its own (inputs resident in HBM)."""
     out = {}
@@ -340,6 +369,8 @@ def extra_workloads(hzd, torch, dev, which=EXTRAS):
         out.update(resize_workloads(hzd, torch, dev, which))
     if "smooth" in which:
         out.update(smoothing_workload(hzd, torch, dev))
+    if "gamma" in which:
+        out.update(adaptive_gamma_workload(hzd, torch, dev))
     torch.cuda.empty_cache()
     return out
 
