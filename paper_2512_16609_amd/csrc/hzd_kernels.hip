@@ -206,47 +206,68 @@ __device__ __forceinline__ void load_pixel_pair(const uint8_t* row, int x0, int 
   p1 = x1 > x0 ? ((lo >> 24) | (hi << 8)) & 0xFFFFFFu : p0;
 }
 
-// One block: 4 output rows (one per wave) by 256 output columns (4 per lane);
-// each lane stores its 4 pixels as 3 aligned dwords (the copy's pitch is a
-// multiple of 16).
+// One block: 4 output rows (one per wave) by 256 output columns.  The 256
+// column taps are computed once per block into LDS.  Lane l of a wave
+// produces columns l, l + 64, l + 128 and l + 192, so the 64 lanes of one
+// load instruction read neighbouring source pixels.  Each row's bytes are
+// staged in LDS and stored as consecutive dwords (the copy's pitch is a
+// multiple of 16, so a dword that starts inside a row ends inside the pitch).
 __global__ __launch_bounds__(256) void k_resize(ResizeBatch rb) {
+  constexpr int kCols = 256, kRows = 4;
+  __shared__ int s_x0[kCols];
+  __shared__ uint32_t s_w[kCols];                 // weight of the second tap | (second tap != first) << 16
+  __shared__ uint32_t s_row[kRows][3 * kCols / 4];
   const int blk = blockIdx.x;
   const int f = frame_of(rb, blk);
   const ResizeDev& fd = rb.f[f];
   const int tile = blk - rb.tile0[f];
-  const int tiles_x = (fd.Wo + 255) / 256;
-  const int y = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
-  const int xb = (tile % tiles_x) * 256 + (threadIdx.x & 63) * 4;
-  if (y >= fd.Ho || xb >= fd.Wo) return;
-  const ResizeTap ty = resize_tap(y, fd.Hs, fd.Ho);
-  const uint8_t* r0 = fd.src + (int64_t)ty.i0 * fd.src_pitch;
-  const uint8_t* r1 = fd.src + (int64_t)ty.i1 * fd.src_pitch;
-  constexpr uint32_t kOne = 1u << kResizeBits;
-  const uint32_t wy1 = ty.w1, wy0 = kOne - wy1;
-  uint32_t px[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const ResizeTap tx = resize_tap(min(xb + k, fd.Wo - 1), fd.Ws, fd.Wo);
-    uint32_t a0, a1, b0, b1;
-    load_pixel_pair(r0, tx.i0, tx.i1, a0, a1);
-    load_pixel_pair(r1, tx.i0, tx.i1, b0, b1);
-    const uint32_t wx1 = tx.w1, wx0 = kOne - wx1;
-    uint32_t v = 0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const uint32_t h0 = wx0 * ((a0 >> (8 * c)) & 255u) + wx1 * ((a1 >> (8 * c)) & 255u);
-      const uint32_t h1 = wx0 * ((b0 >> (8 * c)) & 255u) + wx1 * ((b1 >> (8 * c)) & 255u);
-      const uint32_t q = (wy0 * h0 + wy1 * h1 + (1u << (2 * kResizeBits - 1))) >> (2 * kResizeBits);
-      v |= q << (8 * c);
-    }
-    px[k] = v;
+  const int tiles_x = (fd.Wo + kCols - 1) / kCols;
+  const int yb = (tile / tiles_x) * kRows, xb = (tile % tiles_x) * kCols;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int ncols = min(kCols, fd.Wo - xb);
+  {
+    const ResizeTap t = resize_tap(xb + min(tid, ncols - 1), fd.Ws, fd.Wo);
+    s_x0[tid] = t.i0;
+    s_w[tid] = t.w1 | ((uint32_t)(t.i1 > t.i0) << 16);
   }
-  // a dword that starts inside the row ends inside the pitch (a multiple of 16)
-  uint32_t* out = reinterpret_cast<uint32_t*>(fd.dst + (int64_t)y * fd.dst_pitch + 3 * xb);
-  const int nbytes = 3 * (fd.Wo - xb);
-  out[0] = px[0] | (px[1] << 24);
-  if (nbytes > 4) out[1] = (px[1] >> 8) | (px[2] << 16);
-  if (nbytes > 8) out[2] = (px[2] >> 16) | (px[3] << 8);
+  __syncthreads();
+  const int y = yb + wv;
+  uint8_t* srow = reinterpret_cast<uint8_t*>(s_row[wv]);
+  if (y < fd.Ho) {
+    const ResizeTap ty = resize_tap(y, fd.Hs, fd.Ho);
+    const uint8_t* r0 = fd.src + (int64_t)ty.i0 * fd.src_pitch;
+    const uint8_t* r1 = fd.src + (int64_t)ty.i1 * fd.src_pitch;
+    constexpr uint32_t kOne = 1u << kResizeBits;
+    const uint32_t wy1 = ty.w1, wy0 = kOne - wy1;
+    uint32_t a0[4], a1[4], b0[4], b1[4], wx[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {   // every load of the lane first
+      const int c = min(lane + 64 * k, ncols - 1);
+      const int x0 = s_x0[c];
+      wx[k] = s_w[c];
+      const int x1 = x0 + (int)(wx[k] >> 16);
+      load_pixel_pair(r0, x0, x1, a0[k], a1[k]);
+      load_pixel_pair(r1, x0, x1, b0[k], b1[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = lane + 64 * k;
+      const uint32_t wx1 = wx[k] & 0xFFFFu, wx0 = kOne - wx1;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const uint32_t h0 = wx0 * ((a0[k] >> (8 * ch)) & 255u) + wx1 * ((a1[k] >> (8 * ch)) & 255u);
+        const uint32_t h1 = wx0 * ((b0[k] >> (8 * ch)) & 255u) + wx1 * ((b1[k] >> (8 * ch)) & 255u);
+        const uint32_t q = (wy0 * h0 + wy1 * h1 + (1u << (2 * kResizeBits - 1))) >> (2 * kResizeBits);
+        if (c < ncols) srow[3 * c + ch] = (uint8_t)q;
+      }
+    }
+  }
+  __syncthreads();
+  if (y < fd.Ho) {
+    uint32_t* out = reinterpret_cast<uint32_t*>(fd.dst + (int64_t)y * fd.dst_pitch + 3 * xb);
+    const int nd = (3 * ncols + 3) / 4;
+    for (int j = lane; j < nd; j += 64) out[j] = s_row[wv][j];
+  }
 }
 
 // ------------------------------------------------------------------ k_dark
