@@ -531,24 +531,30 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   const int W = fd.W, H = fd.H;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
 
-  uint32_t vstar, cnt_gt;
-  find_vstar<4>(hist_count<4>(fd.st), (uint32_t)fd.K, s_u32, s_misc, vstar, cnt_gt);
-  (void)cnt_gt;
-
-  // one row per wave; each lane reads 16 consecutive bytes of D per step
+  // one row per wave; each lane reads 16 consecutive bytes of D per step.
+  // The first segment's D does not depend on vstar: it is loaded before the
+  // histogram scan, so the two round trips overlap.
   const int y = tile * 4 + wv;
-  if (y >= H) return;
-  unsigned long long gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;
-  uint32_t gN = 0, tN = 0;
-  const uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch;
-  const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
-  for (int seg = 0; seg < W; seg += 1024 * kSelVec) {
-    uint4 dvs[kSelVec];  // all of this lane's D vectors of the segment, loaded up front
+  const bool row_ok = y < H;
+  const uint8_t* Drow = fd.D + (int64_t)min(y, H - 1) * fd.D_pitch;
+  uint4 dvs[kSelVec];  // all of this lane's D vectors of a segment, loaded up front
+  auto load_d = [&](int seg) {
 #pragma unroll
     for (int q = 0; q < kSelVec; ++q) {
       const int bq = seg + 1024 * q + 16 * lane;
-      dvs[q] = (bq < W) ? *reinterpret_cast<const uint4*>(Drow + bq) : make_uint4(0u, 0u, 0u, 0u);
+      dvs[q] = (row_ok && bq < W) ? *reinterpret_cast<const uint4*>(Drow + bq) : make_uint4(0u, 0u, 0u, 0u);
     }
+  };
+  load_d(0);
+  uint32_t vstar, cnt_gt;
+  find_vstar<4>(hist_count<4>(fd.st), (uint32_t)fd.K, s_u32, s_misc, vstar, cnt_gt);
+  (void)cnt_gt;
+  if (!row_ok) return;
+  unsigned long long gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;
+  uint32_t gN = 0, tN = 0;
+  const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
+  for (int seg = 0; seg < W; seg += 1024 * kSelVec) {
+    if (seg > 0) load_d(seg);
 #pragma unroll
     for (int q = 0; q < kSelVec; ++q) {
       const int base = seg + 1024 * q + 16 * lane;
