@@ -308,7 +308,8 @@ int hzd_tile_config_get(int32_t width, int32_t height, hzd_tile_config* cfg);
 /* Autotuner: time `reps` calls of hzd_dehaze_frame on this frame for each
  * candidate tile shape (HIP events on hip_stream, which is synchronised),
  * store the fastest in the table for the frame's size and return it in *best.
- * The frame's dst is overwritten.  If the environment variable
+ * The frame's dst is overwritten; its airlight state is neither read nor
+ * written.  If the environment variable
  * HZD_AUTOTUNE_CACHE names a file, results are appended to it and entries
  * found there are loaded into the table on first use. */
 int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspace, size_t ws_bytes,

@@ -443,9 +443,9 @@ def tile_config_get(width: int, height: int) -> int:
     return int(c.gf_rows)
 
 
-def autotune(src, dst, params: Params, workspace=None, reps: int = 20, stream=None) -> int:
+def autotune(src, dst, params: Params, workspace=None, reps: int = 20, stream=None, airlight_state=None) -> int:
     """hzd_autotune on one frame; returns the chosen gf_rows (now in the table)."""
-    f = _frame_struct(src, dst, params)
+    f = _frame_struct(src, dst, params, airlight_state=airlight_state)
     pc = params.c()
     if workspace is None:
         workspace = alloc_workspace(workspace_size(params, [(src.shape[0], src.shape[1])]), src.device)

@@ -688,6 +688,13 @@ int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspa
   const hzd_params* p = frame->params ? frame->params : params;
   int rc = validate_params(p);
   if (rc) return rc;
+  // the timed calls leave the stream's airlight state alone: same kernels,
+  // no blend and no state write
+  hzd_params tp = *p;
+  tp.airlight_smoothing = 0.0f;
+  hzd_frame tf = *frame;
+  tf.params = &tp;
+  tf.airlight_state = nullptr;
   int W, H;  // the guided filter runs at the output size
   output_size(*p, frame->width, frame->height, &W, &H);
   if (p->mode != HZD_MODE_OFFLINE) {  // no tile knob on the real-time path
@@ -718,9 +725,9 @@ int hzd_autotune(const hzd_params* params, const hzd_frame* frame, void* workspa
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[{W, H}] = c;
     }
-    rc = dehaze_many(params, frame, 1, nullptr, workspace, ws_bytes, hip_stream);  // warm
+    rc = dehaze_many(&tp, &tf, 1, nullptr, workspace, ws_bytes, hip_stream);  // warm
     if (rc == HZD_OK) rc = check(hipEventRecord(e0, s), "event record");
-    for (int i = 0; i < reps && rc == HZD_OK; ++i) rc = dehaze_many(params, frame, 1, nullptr, workspace, ws_bytes, hip_stream);
+    for (int i = 0; i < reps && rc == HZD_OK; ++i) rc = dehaze_many(&tp, &tf, 1, nullptr, workspace, ws_bytes, hip_stream);
     if (rc == HZD_OK) rc = check(hipEventRecord(e1, s), "event record");
     if (rc == HZD_OK) rc = check(hipEventSynchronize(e1), "event sync");
     float ms = 0.f;

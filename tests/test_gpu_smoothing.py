@@ -105,3 +105,18 @@ def test_served_stream_with_smoothing_equals_frame_calls():
         other.close()
     finally:
         srv.close()
+
+
+def test_autotune_leaves_the_airlight_state_alone():
+    frames = _clip(320, 240, 2, seed=50)
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=30, airlight_smoothing=0.8)
+    _, state = _sequence_gpu(frames, p)
+    before = state.clone()
+    src = to_dev(frames[0])
+    try:
+        rows = hzd.autotune(src, torch.zeros_like(src), p, reps=2, airlight_state=state)
+        assert rows in (8, 16, 24, 32, 48, 64, 96, 128)
+        torch.cuda.synchronize()
+        assert torch.equal(state, before)
+    finally:
+        hzd.tile_config_set(320, 240, None)
