@@ -133,6 +133,47 @@ def test_random_stream_mix_equals_alone():
     srv.close()
 
 
+def test_random_stream_mix_with_optional_stages_equals_frame_calls():
+    # streams that resize, smooth the airlight over time or adapt gamma, mixed with plain ones;
+    # a smoothed stream is compared with the same frames run in order through frame calls that
+    # carry a state, every other stream with each frame run alone
+    rng = np.random.default_rng(4343)
+    specs = []
+    for i in range(8):
+        w, h = int(rng.integers(16, 400)), int(rng.integers(16, 300))
+        resize = bool(rng.random() < 0.5)
+        p = hzd.Params(mode=int(rng.integers(0, 2)), patch=int(rng.choice([1, 7, 15])),
+                       gf_radius=int(rng.integers(1, 65)), color_balance=int(rng.integers(0, 2)),
+                       precision=int(rng.integers(0, 2)),
+                       resize_width=int(rng.integers(8, 300)) if resize else 0,
+                       resize_height=int(rng.integers(8, 200)) if resize else 0,
+                       airlight_smoothing=float(rng.choice([0.0, 0.8])),
+                       gamma_adaptive=int(rng.integers(0, 2)), gamma_target=float(rng.uniform(0.4, 0.8)))
+        specs.append((w, h, p))
+    arena = sum(hzd.stream_arena_size(p, w, h) for w, h, p in specs) + (1 << 20)
+    srv = hzd.Server(arena_bytes=arena, max_inflight=8, frames_per_launch=4, hip_streams=3)
+    streams = [srv.open(p, w, h) for w, h, p in specs]
+    nf = 4
+    frames = {i: [make_frame(w, h, 900 + 10 * i + k).I for k in range(nf)] for i, (w, h, _) in enumerate(specs)}
+    srcs = {i: [to_dev(I) for I in frames[i]] for i in frames}
+    dsts = {}
+    for i, (w, h, p) in enumerate(specs):
+        ho, wo = p.output_shape(h, w)
+        dsts[i] = [torch.zeros((ho, wo, 3), dtype=torch.uint8, device="cuda") for _ in range(nf)]
+    tickets = [(i, k, streams[i].submit(srcs[i][k], dsts[i][k])) for k in range(nf) for i in range(len(specs))]
+    for i, k, t in tickets:
+        rc, _ = streams[i].wait(t)
+        assert rc == 0
+    for i, (w, h, p) in enumerate(specs):
+        state = hzd.make_airlight_state() if p.airlight_smoothing > 0 else None
+        for k in range(nf):
+            ref = run_gpu(frames[i][k], p, with_J=False, airlight_state=state)["out"]
+            assert np.array_equal(dsts[i][k].cpu().numpy(), ref), (i, k, p)
+    for st in streams:
+        st.close()
+    srv.close()
+
+
 def test_wait_twice_on_a_ticket_is_an_error():
     srv = hzd.Server(arena_bytes=_need(RT, 160, 120) + (1 << 20))
     st = srv.open(RT, 160, 120)
