@@ -195,15 +195,13 @@ hzd_tile_config tile_config_for(int W, int H, bool* from_table) {
   return hzd_tile_config{kGfRowsDefault};
 }
 
-namespace {
-// Guided-filter blocks resident at once on the current device (4 per CU).
-int gf_round_blocks() {
+int device_cu_count() {
   static std::mutex mu;
   static std::map<int, int> per_dev;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
-    return 1024;
+    return 256;
   }
   std::lock_guard<std::mutex> lk(mu);
   auto it = per_dev.find(dev);
@@ -213,8 +211,12 @@ int gf_round_blocks() {
     (void)hipGetLastError();
     cus = 256;
   }
-  return per_dev[dev] = 4 * cus;
+  return per_dev[dev] = cus;
 }
+
+namespace {
+// Guided-filter blocks resident at once on the current device (4 per CU).
+int gf_round_blocks() { return 4 * device_cu_count(); }
 }  // namespace
 
 // Tile heights of an offline launch group.  Frames whose size has no table

@@ -112,6 +112,9 @@ struct GroupKey {
   int32_t mode, half_patch, tx, cb, fp16, radius, resize, gadapt;
 };
 
+// Compute units of the current device (cached per device; 256 if the query fails).
+int device_cu_count();
+
 // Launches (hzd_kernels.hip).  Each fills b.tile0 for its own tiling.
 hipError_t launch_resize(ResizeBatch r, hipStream_t s);
 hipError_t launch_init(Batch b, hipStream_t s);
