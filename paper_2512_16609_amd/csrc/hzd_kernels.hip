@@ -278,17 +278,21 @@ __global__ __launch_bounds__(256) void k_resize(ResizeBatch rb) {
 // Herk per row segment, both in registers.  One LDS buffer serves as the byte
 // stage, the two planes and, in place, the vertical-pass output (each step
 // reads into registers, then a barrier, then writes), so that 5 blocks fit
-// on a CU at h = 7 and a 1080p frame's tiles run in one round.
+// on a CU at h = 7 (30.1 KB) and a 1080p frame's tiles run in one round.
 template <int HP, bool WRITE_E>
 __global__ __launch_bounds__(256) void k_dark(Batch b) {
   constexpr int TW = kDarkTW, TH = kDarkTH;
   constexpr int RW = TW + 2 * HP, RH = TH + 2 * HP, WIN = 2 * HP + 1;
+  // plane rows are RWP = RW + 1 dwords apart (an odd stride), so the 32
+  // lanes of a half-wave in the horizontal pass (8 rows x 4 segments 8
+  // columns apart) read 32 distinct banks
+  constexpr int RWP = RW | 1;
   constexpr int SROW = (3 * RW + 3) / 4 + 2;   // dwords of one staged region row (+ slack)
-  __shared__ uint32_t s_pl[2][RH][RW];
+  __shared__ uint32_t s_pl[2][RH][RWP];
   __shared__ uint32_t s_hist[256];
-  static_assert(RH * SROW <= 2 * RH * RW, "byte stage does not fit");
-  uint32_t(&s_rb)[RH][RW] = s_pl[0];
-  uint32_t(&s_g)[RH][RW] = s_pl[1];
+  static_assert(RH * SROW <= 2 * RH * RWP, "byte stage does not fit");
+  uint32_t(&s_rb)[RH][RWP] = s_pl[0];
+  uint32_t(&s_g)[RH][RWP] = s_pl[1];
   uint32_t* s_stage = &s_pl[0][0][0];
 
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -389,10 +393,11 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   }
   __syncthreads();
 
-  // horizontal pass: 32 rows x 8 segments of 8 output columns
+  // horizontal pass: 32 rows x 8 segments of 8 output columns; wave w takes
+  // rows 8w..8w+7, lane l row 8w + (l & 7) and segment l >> 3
   {
     constexpr int HS = 8, L = HS + WIN - 1;
-    const int r = tid >> 3, c0 = (tid & 7) * HS;
+    const int r = 8 * (tid >> 6) + (tid & 7), c0 = ((tid & 63) >> 3) * HS;
     uint32_t vrb[L], vg[L], orb[HS], og[HS];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -1076,15 +1081,26 @@ __device__ __forceinline__ void wave_incl_scan64(unsigned long long (&v)[NR]) {
 // wave per row of the array).
 // NR rows of 256 values each, `stride` elements apart: independent scans
 // whose DPP steps interleave.
+// Physical slot of strip column c in the scan buffers.  A lane of the scan
+// owns 4 consecutive 8-byte columns (32 bytes); the two 16-byte halves are
+// swapped in every other group of four lanes, so the 128-bit accesses of 8
+// consecutive lanes cover all 32 LDS banks once (without the swap, lanes l
+// and l + 4 hit the same banks).
+__device__ __forceinline__ int qsw(int c) { return c ^ ((c >> 3) & 2); }
+
 template <typename T, int NR>
 __device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
   static_assert(sizeof(T) == 8, "64-bit sums");
   const int lane = threadIdx.x & 63;
+  const int h0 = 4 * lane + (((lane >> 2) & 1) << 1);   // slot of columns 4l, 4l+1 (qsw)
+  const int h1 = h0 ^ 2;                                // slot of columns 4l+2, 4l+3
   T v[NR][4];
 #pragma unroll
-  for (int j = 0; j < NR; ++j)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[j][k] = base[j * stride + 4 * lane + k];
+  for (int j = 0; j < NR; ++j) {
+    const ulonglong2 lo = *reinterpret_cast<const ulonglong2*>(base + j * stride + h0);
+    const ulonglong2 hi = *reinterpret_cast<const ulonglong2*>(base + j * stride + h1);
+    v[j][0] = (T)lo.x; v[j][1] = (T)lo.y; v[j][2] = (T)hi.x; v[j][3] = (T)hi.y;
+  }
   unsigned long long ex[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
@@ -1097,8 +1113,10 @@ __device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     const T e = (T)(ex[j] - (unsigned long long)v[j][3]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) base[j * stride + 4 * lane + k] = v[j][k] + e;
+    *reinterpret_cast<ulonglong2*>(base + j * stride + h0) =
+        make_ulonglong2((unsigned long long)(v[j][0] + e), (unsigned long long)(v[j][1] + e));
+    *reinterpret_cast<ulonglong2*>(base + j * stride + h1) =
+        make_ulonglong2((unsigned long long)(v[j][2] + e), (unsigned long long)(v[j][3] + e));
   }
 }
 
@@ -1223,10 +1241,11 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
       if (enters(yb + u)) add(pin[u]);
       if (leaves(yb + u)) sub(pout[u]);
       fetch(yb + kRpi + u, pin[u], pout[u]);
-      s_q[u][0][tid] = sL;
-      s_q[u][1][tid] = sLL;
-      s_q[u][2][tid] = sP;
-      s_q[u][3][tid] = sLP;
+      const int qt = qsw(tid);
+      s_q[u][0][qt] = sL;
+      s_q[u][1][qt] = sLL;
+      s_q[u][2][qt] = sP;
+      s_q[u][3][qt] = sLP;
     }
     __syncthreads();
     wave_prefix256_rows<unsigned long long, kRpi>(&s_q[0][wv][0], 4 * kGfCols);
@@ -1235,13 +1254,13 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     for (int j = 0; j < NI; ++j) {
       const int u = iu[j], y = yb + u;
       if (iok[j] && y < g.y1) {
-        const int clo = iclo[j], chi = ichi[j];
+        const int clo = iclo[j], chi = qsw(ichi[j]), cl = qsw(max(clo - 1, 0));
         // box sums as differences of two prefixes; S_L < 2^32, so 32-bit wrap-around is exact
-        const uint32_t sl = (uint32_t)s_q[u][0][chi] - (clo > 0 ? (uint32_t)s_q[u][0][clo - 1] : 0u);
+        const uint32_t sl = (uint32_t)s_q[u][0][chi] - (clo > 0 ? (uint32_t)s_q[u][0][cl] : 0u);
         const double SL = (double)sl;
-        const double SLL = u64_to_f64(s_q[u][1][chi] - (clo > 0 ? s_q[u][1][clo - 1] : 0ull));
-        const double SP = u64_to_f64(s_q[u][2][chi] - (clo > 0 ? s_q[u][2][clo - 1] : 0ull));
-        const double SLP = u64_to_f64(s_q[u][3][chi] - (clo > 0 ? s_q[u][3][clo - 1] : 0ull));
+        const double SLL = u64_to_f64(s_q[u][1][chi] - (clo > 0 ? s_q[u][1][cl] : 0ull));
+        const double SP = u64_to_f64(s_q[u][2][chi] - (clo > 0 ? s_q[u][2][cl] : 0ull));
+        const double SLP = u64_to_f64(s_q[u][3][chi] - (clo > 0 ? s_q[u][3][cl] : 0ull));
         const double2 rw = s_rows[y - g.y0];  // {ch, 1 / ch}
         const double inv_n = icw[j] * rw.y;
         const double t1 = SL * inv_n;
@@ -1466,8 +1485,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         sb -= pout[u].y;
       }
       fetch(yb + kRpi + u, pin[u], pout[u]);
-      q[u][0][tid] = sa;
-      q[u][1][tid] = sb;
+      q[u][0][qsw(tid)] = sa;
+      q[u][1][qsw(tid)] = sb;
     }
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
@@ -1484,9 +1503,9 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     for (int j = 0; j < NI; ++j) {
       const int u = iu[j], y = yb + u;
       if (iok[j] && y < g.y1) {
-        const int clo = iclo[j], chi = ichi[j], x = g.x0 + ic[j];
-        const double qa = i64_to_f64(q[u][0][chi] - (clo > 0 ? q[u][0][clo - 1] : 0ll));
-        const double qb = i64_to_f64(q[u][1][chi] - (clo > 0 ? q[u][1][clo - 1] : 0ll));
+        const int clo = iclo[j], chi = qsw(ichi[j]), cl = qsw(max(clo - 1, 0)), x = g.x0 + ic[j];
+        const double qa = i64_to_f64(q[u][0][chi] - (clo > 0 ? q[u][0][cl] : 0ll));
+        const double qb = i64_to_f64(q[u][1][chi] - (clo > 0 ? q[u][1][cl] : 0ll));
         const double in = icw_s[j] * s_rows[y - g.y0].y;
         const double G = (double)curL[j] * (1.0 / 255000.0);
         const double qt = fma(qa * in, G, qb * in);
