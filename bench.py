@@ -477,7 +477,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--rotate", type=int, default=10, help="distinct buffer sets cycled by the timed loop")
     ap.add_argument("--served-streams", type=int, default=8)
-    ap.add_argument("--served-frames", type=int, default=40, help="frames per served stream")
+    ap.add_argument("--served-frames", type=int, default=100, help="frames per served stream")
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -612,10 +612,12 @@ def main():
         srcs = [src0.clone() for _ in range(S)]
         dsts = [[torch.empty_like(src0) for _ in range(2)] for _ in range(S)]
         torch.cuda.synchronize()
-        # warm
-        tk = [st.submit(srcs[i], dsts[i][0]) for i, st in enumerate(sts)]
-        for st, t in zip(sts, tk):
-            st.wait(t)
+        # warm: several saturated rounds, so every HIP stream of the new server has run
+        # launches before the timed region
+        for _ in range(4):
+            tk = [(st, st.submit(srcs[i], dsts[i][f % 2])) for f in range(4) for i, st in enumerate(sts)]
+            for st, t in tk:
+                st.wait(t)
         # saturation throughput: every stream keeps its queue full
         t0 = time.perf_counter()
         tickets = []
