@@ -104,14 +104,16 @@ def rnd(v, k):
     return None if v is None else round(v, k)
 
 
-def cpu_baseline(I, p_oracle, budget_s: float):
-    """The FP64 oracle as it stands, single process, on a bounded sample."""
+def cpu_baseline(I, p_oracle, budget_s: float, gpu_out=None):
+    """The FP64 oracle as it stands, single process, on a bounded sample.  With gpu_out (the
+    library's output for the same frame) also returns its error against the oracle's output."""
     import oracle  # test infrastructure: used only for this reported baseline
     times = []
     t_start = time.perf_counter()
+    ref = None
     while True:
         t0 = time.perf_counter()
-        oracle.dehaze(I, p_oracle)
+        ref = oracle.dehaze(I, p_oracle)
         times.append(time.perf_counter() - t0)
         if len(times) >= 3 and time.perf_counter() - t_start >= budget_s:
             break
@@ -120,10 +122,16 @@ def cpu_baseline(I, p_oracle, budget_s: float):
     h, w, _ = I.shape
     mp = w * h / 1e6
     med = float(np.median(times))
-    return {"value": round(mp / med, 4), "unit": "MP/s", "cores": 1, "kind": "oracle",
+    base = {"value": round(mp / med, 4), "unit": "MP/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(times)} runs of one {w}x{h} frame of this workload through the FP64 NumPy "
                       f"oracle (single thread), median {med:.2f} s/frame; host: {cpu_model()}, "
                       f"{os.cpu_count()} logical CPUs visible"}
+    err = None
+    if gpu_out is not None:
+        d = np.abs(gpu_out.astype(np.int32) - ref.out.astype(np.int32))
+        err = {"frame": f"{w}x{h}, this workload", "out_max_lsb": int(d.max()),
+               "out_share_1lsb": float((d == 1).mean()), "out_share_equal": float((d == 0).mean())}
+    return base, err
 
 
 def timed(fn, reps, sync):
@@ -668,13 +676,14 @@ def main():
         serving = serving_mix(hzd, torch, dev, args.serving_seconds,
                               [float(x) for x in args.serving_scales.split(",")])
 
-    cpu = None
+    cpu = oracle_err = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle")
         import oracle
         po = oracle.Params(mode="offline", patch=15, omega=0.95, t0=0.1, top_frac=0.001, alpha=0.8, gamma=1.2,
                            gf_radius=60, gf_eps=1e-3, color_balance=True, tx="he")
-        cpu = cpu_baseline(fr.I, po, args.cpu_budget)
+        gpu_out = sets[0][1].cpu().numpy()   # the timed loop's output for this frame
+        cpu, oracle_err = cpu_baseline(fr.I, po, args.cpu_budget, gpu_out)
 
     out = {
         "metric": METRIC, "value": round(plain_mps, 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
@@ -694,6 +703,7 @@ def main():
         "stages": stage_rows,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_error": oracle_err,
     }
     print(json.dumps(out), flush=True)
 
