@@ -56,13 +56,25 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2512_16609_amd", "csrc", "hzd_kernels.hip
 EXTRAS = ("320", "video", "uneven", "resize1", "resize8", "smooth", "gamma")
 
 
+def kernel_source_hash(path=KERNEL_SRC):
+    """sha256[:16] of the kernel source's code: line comments, trailing blanks and empty lines
+    removed (no string literal in the file contains //), so editing comments does not mark the
+    committed counter summaries as stale."""
+    import hashlib
+    lines = []
+    for line in open(path).read().splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel, path=TRAFFIC_FILE):
     """Calibrated HBM-side bytes per launch of `kernel` from a committed counter summary, or
     None if the kernels changed since the counters were taken."""
-    import hashlib
     try:
         text = open(path).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        src = kernel_source_hash()
     except OSError:
         return None
     raw, scale, recorded = {}, None, None

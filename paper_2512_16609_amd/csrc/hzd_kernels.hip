@@ -3,17 +3,23 @@
 //
 // Stage map (every kernel processes a batch of frames; a block finds its
 // frame from the per-launch block prefix in the kernel arguments):
-//   k_init     zero each frame's state (histogram, colour-balance sums)
+//   k_resize   Sec. V step 1 (optional): bilinear resampling to the working
+//              size in exact integers; the later stages read the copy
+//   k_init     zero each frame's state (histogram, colour-balance and luma sums)
 //   k_dark     Eq. (2): channel minimum + patch erosion on LDS tiles with halo;
 //              writes D (u8), optionally the per-channel erosions E, and a
 //              256-bin histogram of D
 //   k_select_rows   Eq. (3): vstar from the histogram, per-row counts and
 //              exact sums of the ties and of the pixels above vstar
 //   k_select_final  Eq. (3): the tie cut in raster order, A from exact sums
+//              (optionally averaged with the stream's previous airlight)
 //   k_gf_prep  offline: per-pixel luma and coarse t (Eqs. (4)-(5)) in fixed point
 //   k_gf_ab    Eq. (6) stage 1: exact integer box sums -> a, b
-//   k_gf_q     Eq. (6) stage 2: box means of a, b -> refined t (+ fused Eq. (7))
-//   k_recon    Eqs. (4)-(5) pointwise + Eq. (7) + Eq. (8) + colour balance
+//   k_gf_q     Eq. (6) stage 2: box means of a, b -> refined t (+ fused Eq. (7),
+//              or the stored t map with colour-balance or luma sums)
+//   k_recon    Eqs. (4)-(5) pointwise + Eq. (7) + Eq. (8) + colour balance;
+//              phases for colour-balance sums, luma sums (adaptive gamma) and
+//              the output
 //
 // Nothing here is a dense contraction, so no MFMA: the path is bound by HBM
 // traffic and VALU work.
