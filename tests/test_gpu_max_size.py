@@ -1,0 +1,67 @@
+"""The largest frames the ABI accepts (W * H just under 2^31), on the GPU.
+
+The oracle cannot run at this size (its top-K selection sorts every pixel), so
+these tests check what holds at any size: with omega = 0, gamma = 1 and no
+colour balance the pipeline is the identity (t = 1, J = I), K = floor(top_frac
+N), and t stays in [t0, 1].  A 32-bit overflow in any pixel index, row offset,
+histogram count or sum would break one of them.  Inputs are made on the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2512_16609_amd as hzd
+
+pytestmark = pytest.mark.gpu
+
+SIDE = 46340                        # 46340^2 = 2,147,395,600 < 2^31
+
+
+def _random_frame(h, w, seed):
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    return torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device="cuda", generator=g)
+
+
+def test_largest_frame_realtime_identity_and_selection():
+    src = _random_frame(SIDE, SIDE, 1)
+    dst = torch.empty_like(src)
+    p = hzd.Params(omega=0.0, gamma=1.0)
+    aux = {"A": torch.zeros(3, dtype=torch.float32, device="cuda"),
+           "sel": torch.zeros(3, dtype=torch.int32, device="cuda")}
+    hzd.dehaze_frame(src, dst, p, aux=aux)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    n = SIDE * SIDE
+    assert int(aux["sel"][0]) == max(1, int(np.floor(float(np.float32(p.top_frac)) * n)))
+    assert 0 <= int(aux["sel"][2]) < n
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+def test_largest_frame_realtime_transmission_range():
+    src = _random_frame(SIDE, SIDE, 2)
+    dst = torch.empty_like(src)
+    p = hzd.Params()
+    t = torch.empty((SIDE, SIDE), dtype=torch.float32, device="cuda")
+    A = torch.zeros(3, dtype=torch.float32, device="cuda")
+    hzd.dehaze_frame(src, dst, p, aux={"t": t, "A": A})
+    torch.cuda.synchronize()
+    t0 = float(np.float32(p.t0))
+    assert float(t.min()) >= t0 and float(t.max()) <= 1.0
+    assert bool(torch.all((A >= 0) & (A <= 255)))
+    del src, dst, t
+    torch.cuda.empty_cache()
+
+
+def test_large_offline_frame_identity():
+    # 16384 x 16384 (2^28 pixels) through the guided filter: with t = 1 everywhere the filter's
+    # a is 0 and b is exactly 1, so the output is the input
+    side = 16384
+    src = _random_frame(side, side, 3)
+    dst = torch.empty_like(src)
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=60, omega=0.0, gamma=1.0)
+    hzd.dehaze_frame(src, dst, p)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    del src, dst
+    torch.cuda.empty_cache()
