@@ -174,6 +174,38 @@ def test_random_stream_mix_with_optional_stages_equals_frame_calls():
     srv.close()
 
 
+def test_served_with_graph_cache_equals_frame_calls():
+    # the server's launches captured and replayed as HIP graphs (a smoothed stream's first frame
+    # and later frames differ in their launch arguments, so they take different graphs); repeated
+    # rounds with the same buffers replay the cached graphs
+    specs = [(320, 240, hzd.Params(airlight_smoothing=0.6)), (640, 480, OFF), (320, 240, RT)]
+    arena = sum(hzd.stream_arena_size(p, w, h) for w, h, p in specs) + (1 << 20)
+    frames = {i: [make_frame(w, h, 950 + 10 * i + k).I for k in range(3)] for i, (w, h, _) in enumerate(specs)}
+    refs = {}   # per stream, both rounds: a smoothed stream's second round continues its average
+    for i, (w, h, p) in enumerate(specs):
+        state = hzd.make_airlight_state() if p.airlight_smoothing > 0 else None
+        refs[i] = [run_gpu(frames[i][k % 3], p, with_J=False, airlight_state=state)["out"] for k in range(6)]
+    try:
+        hzd.graph_cache(64)
+        srv = hzd.Server(arena_bytes=arena, max_inflight=4, frames_per_launch=2, hip_streams=2)
+        streams = [srv.open(p, w, h) for w, h, p in specs]
+        srcs = {i: [to_dev(I) for I in frames[i]] for i in frames}
+        dsts = {i: [torch.zeros_like(s) for s in srcs[i]] for i in frames}
+        for rnd in range(2):
+            tickets = [(i, k, streams[i].submit(srcs[i][k], dsts[i][k])) for k in range(3) for i in range(len(specs))]
+            for i, k, t in tickets:
+                rc, _ = streams[i].wait(t)
+                assert rc == 0
+            for i in range(len(specs)):
+                for k in range(3):
+                    assert np.array_equal(dsts[i][k].cpu().numpy(), refs[i][3 * rnd + k]), (rnd, i, k)
+        for st in streams:
+            st.close()
+        srv.close()
+    finally:
+        hzd.graph_cache(0)
+
+
 def test_wait_twice_on_a_ticket_is_an_error():
     srv = hzd.Server(arena_bytes=_need(RT, 160, 120) + (1 << 20))
     st = srv.open(RT, 160, 120)
