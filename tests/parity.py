@@ -118,7 +118,7 @@ def compare(I: np.ndarray, p: hzd.Params, g: dict, ref=None, label: str = "") ->
         worst = (J_err / bound).max()
         assert worst <= 1.0, f"{label}: J error {J_err.max():.3g} exceeds bound (ratio {worst:.3g})"
         stats["J_abs_max"] = float(J_err.max())
-        stats["J_rel_scaled_max"] = float((J_err / scale).max())
+        stats["J_rel_scaled_max"] = float((J_err / np.maximum(scale, 1e-12)).max())   # scale is 0 on black frames
     d = np.abs(g["out"].astype(np.int32) - ref.out.astype(np.int32))
     if fp16_map:
         bound = fp16_output_bound(I, p, a, rtol)
