@@ -1457,11 +1457,11 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     ichi[j] = hi - (g.x0 - r);
     icw_s[j] = inv_s * rcp_nr((double)(hi - lo + 1));
   }
-  // an output pixel's guide value and colour (R, G in one 16-bit load, B),
-  // loaded one phase ahead (row clamped into the frame: unconditional loads)
-  auto fetch_px = [&](int yn, int xc, uint32_t& L, uint32_t& rg, uint32_t& bl) {
+  // an output pixel's colour (R, G in one 16-bit load, B), loaded one phase
+  // ahead (row clamped into the frame: unconditional loads); its guide value
+  // L = 299 R + 587 G + 114 B is formed from the same bytes, as k_gf_prep does
+  auto fetch_px = [&](int yn, int xc, uint32_t& rg, uint32_t& bl) {
     const int yc = min(yn, H - 1);
-    L = fd.LP[yc * W + xc].x;
     const uint8_t* p = fd.src + (int64_t)yc * fd.src_pitch + 3 * xc;
     uint16_t v;
     __builtin_memcpy(&v, p, 2);
@@ -1469,17 +1469,17 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     bl = p[2];
   };
   int2 pin[kRpi], pout[kRpi];
-  uint32_t pL[NI], pRG[NI], pB[NI];
+  uint32_t pRG[NI], pB[NI];
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
 #pragma unroll
-  for (int j = 0; j < NI; ++j) fetch_px(g.y0 + iu[j], ixc[j], pL[j], pRG[j], pB[j]);
+  for (int j = 0; j < NI; ++j) fetch_px(g.y0 + iu[j], ixc[j], pRG[j], pB[j]);
 
   const double t0 = (double)fd.t0;
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
   for (int yb = g.y0, buf = 0; yb < g.y1; yb += kRpi, buf ^= 1) {
     long long(&q)[kRpi][2][kGfCols] = s_q[buf];
-    uint32_t curL[NI], curRG[NI], curB[NI];
+    uint32_t curRG[NI], curB[NI];
 #pragma unroll
     for (int u = 0; u < kRpi; ++u) {
       if (enters(yb + u)) {
@@ -1496,10 +1496,9 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     }
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      curL[j] = pL[j];
       curRG[j] = pRG[j];
       curB[j] = pB[j];
-      fetch_px(yb + kRpi + iu[j], ixc[j], pL[j], pRG[j], pB[j]);
+      fetch_px(yb + kRpi + iu[j], ixc[j], pRG[j], pB[j]);
     }
     __syncthreads();
     // 2 quantities x kRpi rows of scans over the 4 waves
@@ -1513,7 +1512,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         const double qa = i64_to_f64(q[u][0][chi] - (clo > 0 ? q[u][0][cl] : 0ll));
         const double qb = i64_to_f64(q[u][1][chi] - (clo > 0 ? q[u][1][cl] : 0ll));
         const double in = icw_s[j] * s_rows[y - g.y0].y;
-        const double G = (double)curL[j] * (1.0 / 255000.0);
+        const uint32_t L = 299u * (curRG[j] & 0xFFu) + 587u * (curRG[j] >> 8) + 114u * curB[j];
+        const double G = (double)L * (1.0 / 255000.0);
         const double qt = fma(qa * in, G, qb * in);
         float t = (float)fmin(fmax(qt, t0), 1.0);
         // FP16 applies to the stored t map (PHASE 1, 2): the sums here use the same
