@@ -39,7 +39,7 @@ STAGE_BYTES_PER_PX = {
     "select": 1.0,        # D (1) in (+ I at the pixels with D >= vstar); two kernels
     "gf_prep": 17.0,      # I (3) + E (3) in; luma/t fixed point LP (8) + 8-row chunk sums (3) out
     "gf_ab": 18.0,        # LP (8) in; a/b fixed point (8) + chunk sums (2) out
-    "gf_q": 23.0,         # a/b (8) + LP (8) + I (3) in; refined t (4) out
+    "gf_q": 15.0,         # a/b (8) + I (3) in; refined t (4) out
     "recon_apply": 10.0,  # I (3) + refined t (4) in; output (3) out
     "recon": 9.0,         # I (3) + E (3) in; output (3) out
     "recon_sums": 6.0,    # I (3) + E (3) in
