@@ -209,8 +209,13 @@ int hzd_dehaze_frame(const hzd_params* params, const hzd_frame* frame,
 
 /* Dehaze n independent frames of possibly different sizes and parameters as
  * one batch: frames sharing (mode, patch, tx, colour balance, precision,
- * radius) are processed by the same launches.  Each frame's result equals
- * its hzd_dehaze_frame result bit for bit.  aux: NULL or an array of n. */
+ * radius, resize, adaptive gamma) are processed by the same launches, up to
+ * 16 frames per launch group.  Several launch groups run concurrently on
+ * streams the library keeps per calling thread (ordered after the work already
+ * on hip_stream, which in turn waits for all of them), unless hip_stream is
+ * being captured into a graph; so the frames of one call must not write
+ * overlapping dst or aux memory.  Each frame's result equals its
+ * hzd_dehaze_frame result bit for bit.  aux: NULL or an array of n. */
 int hzd_dehaze_batch(const hzd_params* params, const hzd_frame* frames, int32_t n,
                      const hzd_frame_aux* aux, void* workspace, size_t ws_bytes,
                      void* hip_stream);

@@ -547,6 +547,92 @@ int launch_group(const GroupKey& g, const Batch& bin, const ResizeBatch* rz, hip
   return check(hipGraphLaunch(exec, s), "graph launch");
 }
 
+// ------------------------------------------------------------ concurrent launch groups
+namespace {
+struct GroupLaunch {
+  GroupKey g;
+  Batch b;
+  ResizeBatch rz;
+  double work;  // pixels of the group
+};
+
+constexpr int kGroupStreams = 4;
+struct GroupStreams {
+  hipStream_t s[kGroupStreams];
+  int n = 0;
+  bool tried = false;
+};
+
+// Streams of the calling thread on device `dev` for concurrent launch groups.
+// Per thread, so that one thread's graph capture on such a stream never sees
+// another thread's launches; they live until the process ends.
+GroupStreams& group_streams(int dev) {
+  thread_local std::map<int, GroupStreams> per_dev;
+  GroupStreams& g = per_dev[dev];
+  if (!g.tried) {
+    g.tried = true;
+    for (int i = 0; i < kGroupStreams; ++i) {
+      if (hipStreamCreateWithFlags(&g.s[i], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        break;
+      }
+      ++g.n;
+    }
+  }
+  return g;
+}
+}  // namespace
+
+// Several launch groups of one call run concurrently on the thread's group
+// streams, largest first, so that the short, latency-bound stages of one group
+// overlap the work of another (the stream-ordered result is unchanged: groups
+// touch disjoint frames and workspace slices).  The groups wait for the work
+// enqueued on `s` before the call, and `s` waits for every group.  Returns
+// HZD_E_UNSUPPORTED (nothing enqueued) where this does not apply: `s` is being
+// captured into a graph, belongs to another device, or streams are missing.
+int launch_concurrent(std::vector<GroupLaunch>& ls, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return HZD_E_UNSUPPORTED;
+  }
+  if (s != nullptr) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    int sdev = -1;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone ||
+        hipStreamGetDevice(s, &sdev) != hipSuccess || sdev != dev) {
+      (void)hipGetLastError();
+      return HZD_E_UNSUPPORTED;
+    }
+  }
+  GroupStreams& gs = group_streams(dev);
+  if (gs.n < 2) return HZD_E_UNSUPPORTED;
+  const int k = std::min<int>(gs.n, (int)ls.size());
+  hipEvent_t fork = nullptr;
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return HZD_E_UNSUPPORTED;
+  }
+  int rc = check(hipEventRecord(fork, s), "fork record");
+  for (int i = 0; i < k && rc == HZD_OK; ++i) rc = check(hipStreamWaitEvent(gs.s[i], fork, 0), "fork wait");
+  (void)hipEventDestroy(fork);  // released once the record completes
+  if (rc != HZD_OK) return rc;
+  std::stable_sort(ls.begin(), ls.end(),
+                   [](const GroupLaunch& a, const GroupLaunch& b) { return a.work > b.work; });
+  for (size_t j = 0; j < ls.size() && rc == HZD_OK; ++j)
+    rc = launch_group(ls[j].g, ls[j].b, &ls[j].rz, gs.s[j % k]);
+  // join even after a failure: `s` follows whatever was enqueued on the group streams
+  for (int i = 0; i < k; ++i) {
+    hipEvent_t e = nullptr;
+    int jr = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "join event");
+    if (jr == HZD_OK) jr = check(hipEventRecord(e, gs.s[i]), "join record");
+    if (jr == HZD_OK) jr = check(hipStreamWaitEvent(s, e, 0), "join wait");
+    if (e) (void)hipEventDestroy(e);
+    if (rc == HZD_OK) rc = jr;
+  }
+  return rc;
+}
+
 int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, const hzd_frame_aux* aux,
                 void* workspace, size_t ws_bytes, void* stream) {
   if (n < 1) return fail(HZD_E_INVAL, "n = %d < 1", n);
@@ -584,22 +670,32 @@ int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, co
   std::map<GroupKey, std::vector<int>> groups;
   for (int i = 0; i < n; ++i) groups[group_key(*ps[i])].push_back(i);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<GroupLaunch> ls;
   for (auto& kv : groups) {
     const std::vector<int>& idx = kv.second;
     for (size_t c = 0; c < idx.size(); c += kMaxBatch) {
-      Batch b;
-      ResizeBatch rz;
-      std::memset(&b, 0, sizeof(b));
-      std::memset(&rz, 0, sizeof(rz));
-      b.n = rz.n = (int)std::min<size_t>(kMaxBatch, idx.size() - c);
-      for (int j = 0; j < b.n; ++j) {
+      ls.emplace_back();
+      GroupLaunch& L = ls.back();
+      std::memset(&L.b, 0, sizeof(L.b));
+      std::memset(&L.rz, 0, sizeof(L.rz));
+      L.g = kv.first;
+      L.work = 0.0;
+      L.b.n = L.rz.n = (int)std::min<size_t>(kMaxBatch, idx.size() - c);
+      for (int j = 0; j < L.b.n; ++j) {
         const int i = idx[c + j];
-        b.f[j] = make_frame_dev(*ps[i], frames[i], aux ? &aux[i] : nullptr,
-                                reinterpret_cast<uint8_t*>(workspace) + offs[i], &rz.f[j]);
+        L.b.f[j] = make_frame_dev(*ps[i], frames[i], aux ? &aux[i] : nullptr,
+                                  reinterpret_cast<uint8_t*>(workspace) + offs[i], &L.rz.f[j]);
+        L.work += (double)frames[i].width * (double)frames[i].height;
       }
-      int rc = launch_group(kv.first, b, &rz, s);
-      if (rc) return rc;
     }
+  }
+  if (ls.size() >= 2) {
+    const int rc = launch_concurrent(ls, s);
+    if (rc != HZD_E_UNSUPPORTED) return rc;
+  }
+  for (const GroupLaunch& L : ls) {
+    const int rc = launch_group(L.g, L.b, &L.rz, s);
+    if (rc) return rc;
   }
   return HZD_OK;
 }

@@ -276,6 +276,44 @@ def test_caller_graph_capture_replays_and_is_not_timed():
         assert np.array_equal(dst.cpu().numpy(), ref1 if rep % 2 == 0 else ref2), rep
 
 
+def test_concurrent_launch_groups_with_graph_cache_and_under_capture():
+    # three launch groups (two parameter sets, one with more than 16 frames) run concurrently on
+    # the library's group streams; with the graph cache on, each group is captured on its stream
+    # and replayed; inside a caller's graph capture the groups join the caller's graph in order
+    rng = np.random.default_rng(78)
+    shapes = [(int(rng.integers(20, 90)), int(rng.integers(20, 130))) for _ in range(20)]
+    params = [P() if i % 4 else P(mode=hzd.MODE_OFFLINE, gf_radius=7, color_balance=1) for i in range(20)]
+    sets = [[rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8) for (h, w) in shapes] for _ in range(2)]
+    refs = [[run_gpu(I, params[i], with_J=False)["out"] for i, I in enumerate(fs)] for fs in sets]
+    srcs = [to_dev(I) for I in sets[0]]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    ws = hzd.alloc_workspace(hzd.workspace_size(P(), shapes, params))
+    stream = torch.cuda.Stream()
+    try:
+        hzd.graph_cache(16)
+        with torch.cuda.stream(stream):
+            for rep in range(4):
+                for s_, I in zip(srcs, sets[rep % 2]):
+                    s_.copy_(to_dev(I))
+                hzd.dehaze_batch(srcs, dsts, P(), per_frame_params=params, workspace=ws, stream=stream)
+                stream.synchronize()
+                for i in range(20):
+                    assert np.array_equal(dsts[i].cpu().numpy(), refs[rep % 2][i]), (rep, i)
+    finally:
+        hzd.graph_cache(0)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        hzd.dehaze_batch(srcs, dsts, P(), per_frame_params=params, workspace=ws, stream=stream)
+    for rep in range(3):
+        for s_, I in zip(srcs, sets[rep % 2]):
+            s_.copy_(to_dev(I))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i in range(20):
+            assert np.array_equal(dsts[i].cpu().numpy(), refs[rep % 2][i]), ("captured", rep, i)
+
+
 def test_uneven_batch_each_size_matches_oracle():
     # the 64-frame configuration's four sizes in one batch call (offline r=60, no colour balance);
     # every frame is checked element by element against the FP64 oracle
