@@ -53,7 +53,7 @@ STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1080p_offline.txt")
 RESIZE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_resize_1080p_to_640x480_x8.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_16609_amd", "csrc", "hzd_kernels.hip")
-EXTRAS = ("320", "video", "uneven", "resize1", "resize8", "smooth", "gamma")
+EXTRAS = ("320", "video", "uneven", "offline8", "resize1", "resize8", "smooth", "gamma")
 
 
 def kernel_source_hash(path=KERNEL_SRC):
@@ -228,6 +228,44 @@ def resize_workloads(hzd, torch, dev, which):
     return out
 
 
+def offline_1080p_8(hzd, torch, dev):
+    """The headline workload (1920x1080 offline, r = 60, colour balance) at 8 frames per launch,
+    from two alternating sets of 8 distinct device-resident frames: throughput, and every stage's
+    launch time with its algorithmic HBM rate, so the kernels' rooflines can be read at a size
+    that fills the chip several times over."""
+    from synth import make_frame
+    sync = torch.cuda.synchronize
+    W, H = 1920, 1080
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=60, gf_eps=1e-3, color_balance=1)
+    base = [torch.from_numpy(make_frame(W, H, 5000 + k).I).to(dev) for k in range(8)]
+    sets = []
+    for _ in range(2):
+        srcs = [b.clone() for b in base]
+        dsts = [torch.empty_like(b) for b in base]
+        sets.append((srcs, dsts, hzd.alloc_workspace(hzd.workspace_size(p, [(H, W)] * 8), dev)))
+    L = [0]
+
+    def batch8():
+        srcs, dsts, ws = sets[L[0] % 2]
+        hzd.dehaze_batch(srcs, dsts, p, workspace=ws)
+        L[0] += 1
+    for _ in range(4):
+        batch8()
+    per = timed(batch8, 40, sync)
+    us = stage_us(hzd, batch8, 40, sync)
+    px = 8 * W * H
+    rates = {k: round(STAGE_BYTES_PER_PX.get(k, 0.0) * px / (v * 1e-6) / 1e9, 1) for k, v in us.items()}
+    dom = max(us, key=lambda k: us[k])
+    del sets, base
+    return {"1920x1080_offline_8_per_launch": {
+        "MP_per_s": round(px / 1e6 / per, 1), "ms_per_launch": round(per * 1e3, 4),
+        "stage_us": {k: round(v, 3) for k, v in us.items()}, "stage_alg_GBps": rates,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": rates[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(rates[dom] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": STAGE_BYTES_PER_PX.get(dom, 0.0) * px,
+                     "avg_launch_us": round(us[dom], 3)}}}
+
+
 def realtime_320(hzd, torch, dev):
     """320x240 real-time single frame: launch-bound, so report latency."""
     from synth import make_frame
@@ -387,6 +425,8 @@ def extra_workloads(hzd, torch, dev, which=EXTRAS):
         out.update(video_720p(hzd, torch, dev))
     if "uneven" in which:
         out.update(uneven_64(hzd, torch, dev))
+    if "offline8" in which:
+        out.update(offline_1080p_8(hzd, torch, dev))
     if "resize1" in which or "resize8" in which:
         out.update(resize_workloads(hzd, torch, dev, which))
     if "smooth" in which:
