@@ -559,21 +559,35 @@ struct GroupLaunch {
 constexpr int kGroupStreams = 4;
 struct GroupStreams {
   hipStream_t s[kGroupStreams];
+  hipEvent_t fork = nullptr;              // recorded on the caller's stream
+  hipEvent_t join[kGroupStreams] = {};    // recorded on s[i]
   int n = 0;
   bool tried = false;
 };
 
-// Streams of the calling thread on device `dev` for concurrent launch groups.
-// Per thread, so that one thread's graph capture on such a stream never sees
-// another thread's launches; they live until the process ends.
+// Streams and fork/join events of the calling thread on device `dev` for
+// concurrent launch groups.  Per thread, so that one thread's graph capture
+// on such a stream never sees another thread's launches, and an event is
+// re-recorded only by the thread that waits on it (a wait takes the record
+// made before it).  They live until the process ends.
 GroupStreams& group_streams(int dev) {
   thread_local std::map<int, GroupStreams> per_dev;
   GroupStreams& g = per_dev[dev];
   if (!g.tried) {
     g.tried = true;
+    if (hipEventCreateWithFlags(&g.fork, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      g.fork = nullptr;
+      return g;
+    }
     for (int i = 0; i < kGroupStreams; ++i) {
       if (hipStreamCreateWithFlags(&g.s[i], hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
+        break;
+      }
+      if (hipEventCreateWithFlags(&g.join[i], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(g.s[i]);
         break;
       }
       ++g.n;
@@ -608,14 +622,8 @@ int launch_concurrent(std::vector<GroupLaunch>& ls, hipStream_t s) {
   GroupStreams& gs = group_streams(dev);
   if (gs.n < 2) return HZD_E_UNSUPPORTED;
   const int k = std::min<int>(gs.n, (int)ls.size());
-  hipEvent_t fork = nullptr;
-  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    return HZD_E_UNSUPPORTED;
-  }
-  int rc = check(hipEventRecord(fork, s), "fork record");
-  for (int i = 0; i < k && rc == HZD_OK; ++i) rc = check(hipStreamWaitEvent(gs.s[i], fork, 0), "fork wait");
-  (void)hipEventDestroy(fork);  // released once the record completes
+  int rc = check(hipEventRecord(gs.fork, s), "fork record");
+  for (int i = 0; i < k && rc == HZD_OK; ++i) rc = check(hipStreamWaitEvent(gs.s[i], gs.fork, 0), "fork wait");
   if (rc != HZD_OK) return rc;
   std::stable_sort(ls.begin(), ls.end(),
                    [](const GroupLaunch& a, const GroupLaunch& b) { return a.work > b.work; });
@@ -623,11 +631,8 @@ int launch_concurrent(std::vector<GroupLaunch>& ls, hipStream_t s) {
     rc = launch_group(ls[j].g, ls[j].b, &ls[j].rz, gs.s[j % k]);
   // join even after a failure: `s` follows whatever was enqueued on the group streams
   for (int i = 0; i < k; ++i) {
-    hipEvent_t e = nullptr;
-    int jr = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "join event");
-    if (jr == HZD_OK) jr = check(hipEventRecord(e, gs.s[i]), "join record");
-    if (jr == HZD_OK) jr = check(hipStreamWaitEvent(s, e, 0), "join wait");
-    if (e) (void)hipEventDestroy(e);
+    int jr = check(hipEventRecord(gs.join[i], gs.s[i]), "join record");
+    if (jr == HZD_OK) jr = check(hipStreamWaitEvent(s, gs.join[i], 0), "join wait");
     if (rc == HZD_OK) rc = jr;
   }
   return rc;
