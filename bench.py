@@ -13,7 +13,7 @@ with exact fixed-point box sums.  Inputs are resident in HBM before timing;
 the loop rotates over distinct src/dst/workspace sets whose total exceeds the
 256 MB Infinity Cache, so each step reads cold data.
 
-Prints ONE JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -32,8 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "megapixels/sec dehazed at 1080p (plain vs served); p50/p99 frame latency"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per pixel of each kernel (what it must read and write;
-# the design doc derives each figure).  Keys are the library's stage names.
+# Algorithmic HBM bytes per pixel of each kernel (what it must read and write,
+# itemised per entry).  Keys are the library's stage names.
 STAGE_BYTES_PER_PX = {
     "dark": 7.0,          # I (3) in; D (1) + per-channel erosions E (3) out
     "select": 1.0,        # D (1) in (+ I at the pixels with D >= vstar); two kernels
@@ -563,7 +563,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "this build has no multi-GPU path: frames and streams are independent and would shard "
+              "the library has no multi-GPU path: frames and streams are independent and would shard "
               "across GPUs with no communication.", file=sys.stderr)
         sys.exit(2)
 

@@ -47,7 +47,7 @@ typedef enum {
   HZD_E_DEVICE = -3,       /* a HIP call failed (detail in hzd_last_error)     */
   HZD_E_AGAIN = -4,        /* no admission budget or queue space right now     */
   HZD_E_CLOSED = -5,       /* the stream/server is closed; the frame was dropped */
-  HZD_E_UNSUPPORTED = -6,  /* valid request outside what this build implements */
+  HZD_E_UNSUPPORTED = -6,  /* valid request outside what the library implements */
   HZD_E_TIMEOUT = -7       /* hzd_stream_wait timed out                        */
 } hzd_status;
 
