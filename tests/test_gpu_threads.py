@@ -76,3 +76,57 @@ def test_threads_share_the_library(cache):
     finally:
         hzd.graph_cache(0)
     assert not errors, errors[:10]
+
+
+def test_threads_submit_to_one_server():
+    # three client threads, two streams each (a real-time and an offline size), submitting and
+    # waiting at the same time; each served frame equals its frame-call result
+    T, nf = 3, 8
+    specs = []
+    for t in range(T):
+        rng = np.random.default_rng(120 + t)
+        pa, pb = P(), P(mode=hzd.MODE_OFFLINE, gf_radius=7 + t, color_balance=1)
+        fa = [rng.integers(0, 256, size=(120, 160, 3), dtype=np.uint8) for _ in range(nf)]
+        fb = [rng.integers(0, 256, size=(80 + 8 * t, 96, 3), dtype=np.uint8) for _ in range(nf)]
+        specs.append([(pa, fa), (pb, fb)])
+    refs = [[[run_gpu(I, p, with_J=False)["out"] for I in fs] for (p, fs) in sp] for sp in specs]
+    arena = sum(hzd.stream_arena_size(p, fs[0].shape[1], fs[0].shape[0]) for sp in specs for (p, fs) in sp)
+    srv = hzd.Server(arena_bytes=arena + 4096, max_inflight=16, frames_per_launch=8, hip_streams=4)
+    sts = [[srv.open(p, fs[0].shape[1], fs[0].shape[0]) for (p, fs) in sp] for sp in specs]
+    errors = []
+    start = threading.Barrier(T)
+
+    def client(t):
+        try:
+            bufs = [([to_dev(I) for I in fs], [torch.zeros((I.shape[0], I.shape[1], 3), dtype=torch.uint8,
+                                                         device="cuda") for I in fs]) for (_, fs) in specs[t]]
+            torch.cuda.synchronize()
+            start.wait(timeout=60)
+            tickets = []
+            for k in range(nf):
+                for s, (srcs, dsts) in enumerate(bufs):
+                    tickets.append((s, k, sts[t][s].submit(srcs[k], dsts[k])))
+            for s, k, tk in tickets:
+                rc, _ = sts[t][s].wait(tk, timeout_ns=60_000_000_000)
+                if rc != 0:
+                    errors.append(f"client {t} stream {s} frame {k}: status {rc}")
+                elif not np.array_equal(bufs[s][1][k].cpu().numpy(), refs[t][s][k]):
+                    errors.append(f"client {t} stream {s} frame {k}: differs from the frame call")
+        except Exception as e:  # reported by the main thread
+            errors.append(f"client {t}: {e!r}")
+            start.abort()
+
+    try:
+        threads = [threading.Thread(target=client, args=(t,), daemon=True) for t in range(T)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=120)
+        assert not any(th.is_alive() for th in threads), "a client thread did not finish"
+        assert srv.stats()["completed"] == T * 2 * nf
+    finally:
+        for row in sts:
+            for st in row:
+                st.close()
+        srv.close()
+    assert not errors, errors[:10]
