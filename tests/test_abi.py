@@ -204,3 +204,21 @@ def test_tile_config_table(L):
             hzd.tile_config_set(640, 480, bad)
     with pytest.raises(hzd.HzdError):
         hzd.tile_config_set(-1, 480, 16)
+
+
+def test_autotune_cache_file_is_loaded(tmp_path):
+    # HZD_AUTOTUNE_CACHE entries fill the tile table on its first use in a process; rows outside
+    # the accepted range (multiples of 8 in 8..256) are skipped.  A fresh interpreter, since the
+    # file is read once per process.
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("640 480 32\n1280 720 12\n1920 1080 300\n0 0 24\n")
+    code = ("import paper_2512_16609_amd as h; "
+            "print(h.tile_config_get(640, 480), h.tile_config_get(1280, 720), h.tile_config_get(1920, 1080))")
+    env = dict(os.environ, HZD_AUTOTUNE_CACHE=str(cache))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr[-2000:]
+    # 640x480 from its entry; the others fall back to the file's (0, 0) default of 24
+    assert out.stdout.split() == ["32", "24", "24"]
