@@ -198,15 +198,19 @@ def test_results_do_not_depend_on_tile_rows():
     compare(I, p, outs[0], label="tile rows")
 
 
-def test_autotune_picks_a_candidate():
+def test_autotune_picks_a_candidate(tmp_path, monkeypatch):
+    # the choice goes into the table and is appended to the HZD_AUTOTUNE_CACHE file
     I = _frame(640, 480, 32)
     p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
     src = to_dev(I)
     dst = torch.zeros_like(src)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HZD_AUTOTUNE_CACHE", str(cache))
     try:
         rows = hzd.autotune(src, dst, p, reps=3)
         assert rows in (8, 16, 24, 32, 48, 64, 96, 128)
         assert hzd.tile_config_get(640, 480) == rows
+        assert cache.read_text().split() == ["640", "480", str(rows)]
         compare(I, p, run_gpu(I, p), label="autotuned")
     finally:
         hzd.tile_config_set(640, 480, None)
