@@ -256,10 +256,12 @@ def offline_1080p_8(hzd, torch, dev):
     px = 8 * W * H
     rates = {k: round(STAGE_BYTES_PER_PX.get(k, 0.0) * px / (v * 1e-6) / 1e9, 1) for k, v in us.items()}
     dom = max(us, key=lambda k: us[k])
+    path_bytes = sum(STAGE_BYTES_PER_PX.get(k, 0.0) for k in us) * px
     del sets, base
     return {"1920x1080_offline_8_per_launch": {
         "MP_per_s": round(px / 1e6 / per, 1), "ms_per_launch": round(per * 1e3, 4),
         "stage_us": {k: round(v, 3) for k, v in us.items()}, "stage_alg_GBps": rates,
+        "path_alg_GBps": round(path_bytes / per / 1e9, 1),
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": rates[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(rates[dom] / HBM_PEAK_GBS, 4), "traffic": None,
                      "alg_bytes_per_launch": STAGE_BYTES_PER_PX.get(dom, 0.0) * px,
@@ -658,6 +660,11 @@ def main():
                 "frac": round(d["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": d["alg_bytes_per_px"] * W * H, "avg_launch_us": d["avg_us"],
                 "event_pair_us": round(ev_us, 3)}
+    # the whole path: every stage's algorithmic bytes per step over the timed step time
+    path_bytes = sum(r["alg_bytes_per_px"] for r in stage_rows.values()) * W * H
+    path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
+    path_roofline = {"alg_bytes_per_step": path_bytes, "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(path_gbs / HBM_PEAK_GBS, 4)}
 
     # ---- served
     served = None
@@ -756,6 +763,7 @@ def main():
         "serving_mix_32_streams": serving,
         "stages": stage_rows,
         "roofline": roofline,
+        "path_roofline": path_roofline,
         "cpu_baseline": cpu,
         "oracle_error": oracle_err,
     }
