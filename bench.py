@@ -309,8 +309,29 @@ def video_720p(hzd, torch, dev):
             hzd.dehaze_batch([pool[i] for i in idx], [outs[i] for i in idx], p3, workspace=ws3)
     clip()
     per = timed(clip, 3, sync)
+    # the same launches alternating over two HIP streams, each with its own workspace (the
+    # frames are independent in real-time mode without airlight smoothing); launch L writes
+    # outputs 8 (L % 2) .. 8 (L % 2) + 7, so the two streams never write the same buffer
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    wss = [ws3, hzd.alloc_workspace(hzd.workspace_size(p3, [(720, 1280)] * 8), dev)]
+
+    def clip2():
+        cur = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(cur)
+        for L in range(38):
+            n = 8 if L < 37 else 4
+            idx = [(8 * L + k) % 16 for k in range(n)]
+            hzd.dehaze_batch([pool[i] for i in idx], [outs[i] for i in idx], p3, workspace=wss[L % 2],
+                             stream=streams[L % 2])
+        for st in streams:
+            cur.wait_stream(st)
+    clip2()
+    per2 = timed(clip2, 3, sync)
     return {"1280x720_video_rt_fp16_8_per_launch": {"MP_per_s": round(300 * 0.9216 / per, 1),
-                                                    "ms_per_300_frames": round(per * 1e3, 3)}}
+                                                    "ms_per_300_frames": round(per * 1e3, 3),
+                                                    "two_streams_MP_per_s": round(300 * 0.9216 / per2, 1),
+                                                    "two_streams_ms_per_300_frames": round(per2 * 1e3, 3)}}
 
 
 def uneven_64(hzd, torch, dev):
