@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HZD_ABI_VERSION 2
+#define HZD_ABI_VERSION 3
 
 typedef enum {
   HZD_OK = 0,
@@ -174,8 +174,18 @@ typedef struct hzd_frame {
 /* Optional per-frame device outputs for inspection (NULL = not written).
  * width and height below are the output size.
  *   A_out    3 floats: A^c of Eq. (3) on the 0..255 scale
- *   sel_out  3 int32: {K, vstar, cutoff}; the selected set of Eq. (3) is
- *            {D > vstar} U {D == vstar and raster index <= cutoff}
+ *   sel_out  4 int32: {K, vstar, cutoff, status}; the selected set of
+ *            Eq. (3) is {D > vstar} U {D == vstar and raster index <= cutoff}.
+ *            status is the selection's own consistency check, 0 when the
+ *            per-row counts agree with the histogram of D.  Nonzero means
+ *            the device produced inconsistent intermediate data (a fault):
+ *            1 = the count of pixels above vstar or the cut pixel disagrees
+ *            (A was formed, the result is not trustworthy); 2 = no row holds
+ *            the cut (A is set to 0 and the output is undefined).  A frame
+ *            or batch call returns before its kernels run, so a caller that
+ *            needs this check passes sel_out (device or host-mapped memory)
+ *            and reads status once the stream has completed; served frames
+ *            report a nonzero status as HZD_E_DEVICE.
  *   dark_out width*height bytes (pitch = width): D of Eq. (2)
  *   t_out    width*height floats: the t used in Eq. (7) (after the guided
  *            filter in OFFLINE mode)
@@ -270,9 +280,13 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
                     hzd_stream** out);
 /* Queue one frame (frame->width/height must match the stream; params and
  * airlight_state ignored).
+ * ready_stream: the hipStream_t that produced src and last used dst (NULL =
+ * the null stream).  The call records an event on it, and the launch that
+ * takes the frame waits for that event, so the frame is read and written
+ * only after the work enqueued on ready_stream before this call.
  * Returns at once with a ticket.  HZD_E_AGAIN when the queue is full. */
-int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
-                      uint64_t* ticket);
+int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, void* ready_stream, hzd_done_fn cb,
+                      void* user, uint64_t* ticket);
 /* Wait until `ticket` completes (timeout_ns < 0: forever).  Returns the
  * frame's status, or HZD_E_TIMEOUT.  latency_ns (nullable): nanoseconds from
  * submit to the scheduler observing completion.  A ticket can be collected
@@ -280,7 +294,8 @@ int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, vo
  * HZD_E_INVAL at once. */
 int hzd_stream_wait(hzd_stream* st, uint64_t ticket, int64_t timeout_ns, int64_t* latency_ns);
 /* Per-stream device state as of the last completed frame: A (3 floats) and
- * {K, vstar, cutoff}; host pointers, either may be NULL. */
+ * {K, vstar, cutoff, status} (4 int32, as hzd_frame_aux.sel_out); host
+ * pointers, either may be NULL. */
 int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host);
 /* Wait for the stream's frames, release its arena space and free it. */
 int hzd_stream_close(hzd_stream* st);

@@ -26,7 +26,7 @@ MODE_REALTIME, MODE_OFFLINE = 0, 1
 TX_HE, TX_PAPER = 0, 1
 PREC_FP32, PREC_FP16 = 0, 1
 PRESET_REALTIME, PRESET_OFFLINE, PRESET_PAPER_REALTIME = 0, 1, 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class HzdError(RuntimeError):
@@ -99,8 +99,8 @@ SYMBOLS = {
     "hzd_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "hzd_stream_open": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_params), ctypes.c_int32,
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
-    "hzd_stream_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_frame), DONE_FN, ctypes.c_void_p,
-                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "hzd_stream_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hzd_frame), ctypes.c_void_p, DONE_FN,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "hzd_stream_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64)]),
     "hzd_stream_arena_size": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.c_int32, ctypes.c_int32,
@@ -234,7 +234,7 @@ def _aux_struct(aux: dict | None) -> hzd_frame_aux | None:
 def make_aux(h: int, w: int, device="cuda", J: bool = True) -> dict:
     """Device buffers for every optional per-frame output."""
     d = {"A": torch.zeros(3, dtype=torch.float32, device=device),
-         "sel": torch.zeros(3, dtype=torch.int32, device=device),
+         "sel": torch.zeros(4, dtype=torch.int32, device=device),   # K, vstar, cutoff, status
          "dark": torch.zeros((h, w), dtype=torch.uint8, device=device),
          "t": torch.zeros((h, w), dtype=torch.float32, device=device)}
     if J:
@@ -364,11 +364,14 @@ class Stream:
         self.server, self.handle, self.width, self.height = server, handle, width, height
         self.params = params
 
-    def submit(self, src: torch.Tensor, dst: torch.Tensor) -> int:
-        """Queue one frame; no completion callback (completion and latency come from wait())."""
+    def submit(self, src: torch.Tensor, dst: torch.Tensor, stream=None) -> int:
+        """Queue one frame; no completion callback (completion and latency come from wait()).
+        The frame is ordered after the work enqueued so far on `stream` (default: torch's
+        current stream), which produced src and last used dst."""
         f = _frame_struct(src, dst, self.params)
         t = ctypes.c_uint64(0)
-        rc = lib().hzd_stream_submit(self.handle, ctypes.byref(f), DONE_FN(), None, ctypes.byref(t))
+        rc = lib().hzd_stream_submit(self.handle, ctypes.byref(f), _stream_handle(stream), DONE_FN(), None,
+                                     ctypes.byref(t))
         _check(rc, "hzd_stream_submit")
         return int(t.value)
 
@@ -379,8 +382,9 @@ class Stream:
         return int(rc), int(lat.value)
 
     def state(self):
+        """(A, [K, vstar, cutoff, status]) of the stream's last completed frame."""
         A = (ctypes.c_float * 3)()
-        sel = (ctypes.c_int32 * 3)()
+        sel = (ctypes.c_int32 * 4)()
         _check(lib().hzd_stream_state(self.handle, A, sel), "hzd_stream_state")
         return list(A), list(sel)
 

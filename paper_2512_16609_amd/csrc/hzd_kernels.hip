@@ -709,12 +709,27 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
   __syncthreads();
   const int rstar = s_misc[2];
   const uint32_t before = (uint32_t)s_misc[3];
-  if (rstar < 0) {  // inconsistent counts: report instead of reading a row that is not there
+  if (rstar < 0) {
+    // inconsistent counts (the row records hold fewer ties than the histogram):
+    // no cut row exists.  A is set to 0 and the frame is flagged (status 2)
+    // instead of reading a row that is not there; the stream's stored airlight
+    // is left as it was.
     if (tid == 0) {
+      for (int ch = 0; ch < 3; ++ch) {
+        st->A[ch] = 0.0f;
+        if (fd.A_out) fd.A_out[ch] = 0.0f;
+      }
       st->sel[0] = (int32_t)K;
       st->sel[1] = (int32_t)vstar;
       st->sel[2] = -1;
       st->sel[3] = 2;
+      if (fd.sel_out) {
+        fd.sel_out[0] = (int32_t)K;
+        fd.sel_out[1] = (int32_t)vstar;
+        fd.sel_out[2] = -1;
+        fd.sel_out[3] = 2;
+        __threadfence_system();   // sel_out may be host memory read when the stream completes
+      }
     }
     return;
   }
@@ -826,6 +841,8 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
       fd.sel_out[0] = (int32_t)K;
       fd.sel_out[1] = (int32_t)vstar;
       fd.sel_out[2] = cutoff;
+      fd.sel_out[3] = st->sel[3];
+      __threadfence_system();   // sel_out may be host memory read when the stream completes
     }
   }
 }

@@ -83,9 +83,46 @@ struct Arena {
 };
 
 constexpr int kSlotsPerStream = 2;   // frames of one stream on the device at once
+
+// Host-coherent pinned cells of 4 int32 that k_select_final writes a served
+// frame's {K, vstar, cutoff, status} into, so that the scheduler reads the
+// selection's consistency status when the launch completes, without a copy.
+// Process-wide pool, allocated in blocks and never freed (a block is reused by
+// later streams and servers).
+struct StatusCells {
+  std::mutex mu;
+  std::vector<int32_t*> free_cells;
+  int32_t* get() {
+    std::lock_guard<std::mutex> lk(mu);
+    if (free_cells.empty()) {
+      constexpr int kBlock = 1024;
+      void* p = nullptr;
+      if (hipHostMalloc(&p, kBlock * 4 * sizeof(int32_t), hipHostMallocCoherent | hipHostMallocPortable) !=
+              hipSuccess ||
+          !p) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      int32_t* c = static_cast<int32_t*>(p);
+      for (int i = kBlock - 1; i >= 0; --i) free_cells.push_back(c + 4 * i);
+    }
+    int32_t* c = free_cells.back();
+    free_cells.pop_back();
+    return c;
+  }
+  void put(int32_t* c) {
+    if (!c) return;
+    std::lock_guard<std::mutex> lk(mu);
+    free_cells.push_back(c);
+  }
+};
+StatusCells& status_cells() {
+  static StatusCells* s = new StatusCells();   // outlives every server
+  return *s;
+}
 constexpr int kMaxQueuedPerStream = 256;
 
-// A stream's arena block: per-slot outputs (A, sel; 256 B each), the stream's
+// A stream's arena block: per-slot airlight outputs (A; 256 B each), the stream's
 // airlight state (256 B), then one workspace per slot.
 constexpr size_t kAirlightStateOff = 256 * kSlotsPerStream;
 constexpr size_t kWorkspacesOff = kAirlightStateOff + 256;
@@ -104,8 +141,10 @@ struct hzd_stream {
   int W = 0, H = 0;
   size_t arena_off = 0, arena_len = 0;
   size_t ws_bytes = 0;          // one slot's workspace
-  uint8_t* state_dev = nullptr; // A (3 floats) + sel (3 ints) of each slot
+  uint8_t* state_dev = nullptr; // A (3 floats) of each slot, 256 B apart
+  int32_t* status[kSlotsPerStream] = {nullptr, nullptr};  // pinned {K, vstar, cutoff, status} per slot
   bool slot_busy[kSlotsPerStream] = {false, false};
+  uint64_t blocked_pass = 0;    // admission pass in which a frame of this stream was left queued
   int last_slot = -1;
   bool ema_primed = false;      // a frame has completed and stored the airlight state
   uint64_t next_ticket = 1;
@@ -124,6 +163,7 @@ struct Job {
   void* user;
   uint64_t ticket;
   int64_t t_submit;
+  hipEvent_t ready = nullptr;  // recorded on the producer's stream at submit
   int slot = -1;
 };
 
@@ -149,6 +189,8 @@ struct hzd_server {
   std::deque<Job> queue;
   std::vector<Launch> inflight;
   int inflight_frames = 0;
+  uint64_t admit_pass = 0;
+  std::vector<hipEvent_t> ready_pool;  // events for the producers' streams, reused
   hzd_server_stats stats{};
 };
 
@@ -186,6 +228,10 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
   Launch L;
   GroupKey key{};
   bool have_key = false;
+  // keep a stream's frames in submission order: once a frame of a stream is
+  // left in the queue, this pass skips the stream's later frames (one flag per
+  // stream and pass, so a pass is linear in the queue length)
+  const uint64_t pass = ++s->admit_pass;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
     if ((int)L.jobs.size() >= s->cfg.frames_per_launch ||
         s->inflight_frames + (int)L.jobs.size() >= s->cfg.max_inflight)
@@ -198,13 +244,11 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     // with temporal airlight smoothing a frame needs its predecessor's
     // airlight: one frame of such a stream on the device at a time
     const bool ema_wait = st->p.airlight_smoothing > 0.0f && st->inflight > 0;
-    if (slot < 0 || ema_wait || (have_key && (gk < key || key < gk))) { ++it; continue; }
-    // keep a stream's frames in submission order: skip later frames of a
-    // stream whose earlier frame could not be taken
-    bool earlier_waiting = false;
-    for (auto jt = s->queue.begin(); jt != it; ++jt)
-      if (jt->st == st) { earlier_waiting = true; break; }
-    if (earlier_waiting) { ++it; continue; }
+    if (st->blocked_pass == pass || slot < 0 || ema_wait || (have_key && (gk < key || key < gk))) {
+      st->blocked_pass = pass;
+      ++it;
+      continue;
+    }
     key = gk;
     have_key = true;
     Job j = *it;
@@ -228,7 +272,8 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     uint8_t* state = base + 256 * j.slot;
     hzd_frame_aux aux{};
     aux.A_out = reinterpret_cast<float*>(state);
-    aux.sel_out = reinterpret_cast<int32_t*>(state + 16);
+    aux.sel_out = st->status[j.slot];
+    st->status[j.slot][3] = -1;   // overwritten by the frame's selection kernel
     uint8_t* ws = base + kWorkspacesOff + st->ws_bytes * j.slot;
     hzd_frame fr = j.fr;
     const bool ema = st->p.airlight_smoothing > 0.0f;
@@ -237,7 +282,17 @@ bool admit(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     if (ema && !st->ema_primed) b.f[i].flags |= kFdEmaFirst;
   }
   (void)hipSetDevice(s->cfg.device);
-  int rc = launch_group(key, b, &rz, s->hstreams[hs]);
+  // the launch follows the producers' work on src and dst; an event can be
+  // re-recorded as soon as a wait has been enqueued on it
+  int rc = HZD_OK;
+  for (auto& j : L.jobs) {
+    if (j.ready) {
+      if (rc == HZD_OK) rc = check(hipStreamWaitEvent(s->hstreams[hs], j.ready, 0), "ready wait");
+      s->ready_pool.push_back(j.ready);
+      j.ready = nullptr;
+    }
+  }
+  if (rc == HZD_OK) rc = launch_group(key, b, &rz, s->hstreams[hs]);
   if (rc == HZD_OK) rc = check(hipEventRecord(s->events[hs], s->hstreams[hs]), "event record");
   s->stats.launches++;
   if (rc != HZD_OK) {
@@ -263,8 +318,11 @@ bool reap(hzd_server* s, std::vector<std::pair<Job, int32_t>>& done) {
     Launch& L = s->inflight[i];
     const hipError_t q = hipEventQuery(L.ev);
     if (q == hipErrorNotReady) { ++i; continue; }
-    const int32_t status = (q == hipSuccess) ? HZD_OK : HZD_E_DEVICE;
+    const int32_t launch_status = (q == hipSuccess) ? HZD_OK : HZD_E_DEVICE;
     for (auto& j : L.jobs) {
+      // the selection's consistency status, written by the frame's kernels
+      const volatile int32_t* cell = j.st->status[j.slot];
+      const int32_t status = (launch_status == HZD_OK && cell[3] != 0) ? HZD_E_DEVICE : launch_status;
       j.st->slot_busy[j.slot] = false;
       j.st->last_slot = j.slot;
       if (status == HZD_OK) s->stats.completed++;
@@ -352,6 +410,8 @@ int hzd_server_destroy(hzd_server* s) {
     for (auto& j : s->queue) {
       j.st->queued--;
       j.st->inflight++;  // finish() records the cancellation and drops it again
+      if (j.ready) s->ready_pool.push_back(j.ready);
+      j.ready = nullptr;
       cancelled.emplace_back(j, HZD_E_CLOSED);
     }
     s->queue.clear();
@@ -360,9 +420,15 @@ int hzd_server_destroy(hzd_server* s) {
   }
   finish(s, cancelled);
   s->thr.join();
-  for (hzd_stream* st : s->streams) delete st;
+  (void)hipSetDevice(s->cfg.device);
+  for (auto h : s->hstreams) (void)hipStreamSynchronize(h);
+  for (hzd_stream* st : s->streams) {
+    for (int k = 0; k < kSlotsPerStream; ++k) status_cells().put(st->status[k]);
+    delete st;
+  }
   for (auto h : s->hstreams) (void)hipStreamDestroy(h);
   for (auto e : s->events) (void)hipEventDestroy(e);
+  for (auto e : s->ready_pool) (void)hipEventDestroy(e);
   delete s;
   clear_error();
   return HZD_OK;
@@ -381,14 +447,27 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
   st->H = height;
   st->ws_bytes = stream_ws_bytes(*params, width, height);
   st->arena_len = kWorkspacesOff + st->ws_bytes * kSlotsPerStream;
+  (void)hipSetDevice(s->cfg.device);
+  for (int k = 0; k < kSlotsPerStream; ++k) {
+    st->status[k] = status_cells().get();
+    if (!st->status[k]) {
+      for (int m = 0; m < k; ++m) status_cells().put(st->status[m]);
+      delete st;
+      return fail(HZD_E_DEVICE, "pinned status memory could not be allocated");
+    }
+  }
+  auto drop = [&] {
+    for (int k = 0; k < kSlotsPerStream; ++k) status_cells().put(st->status[k]);
+    delete st;
+  };
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
-      delete st;
+      drop();
       return fail(HZD_E_CLOSED, "server is shutting down");
     }
     if (!s->arena.alloc(st->arena_len, &st->arena_off)) {
-      delete st;
+      drop();
       return fail(HZD_E_AGAIN, "arena has no room for %zu bytes (%zu used of %zu)", st->arena_len,
                   s->arena.used(), s->arena.size);
     }
@@ -402,7 +481,7 @@ int hzd_stream_open(hzd_server* s, const hzd_params* params, int32_t width, int3
   return HZD_OK;
 }
 
-int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, void* user,
+int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, void* ready_stream, hzd_done_fn cb, void* user,
                       uint64_t* ticket) {
   if (!st || !frame) return fail(HZD_E_INVAL, "NULL argument");
   int rc = validate_frame(frame, st->p, 0);
@@ -411,10 +490,31 @@ int hzd_stream_submit(hzd_stream* st, const hzd_frame* frame, hzd_done_fn cb, vo
     return fail(HZD_E_INVAL, "frame %dx%d does not match stream %dx%d", frame->width, frame->height, st->W,
                 st->H);
   hzd_server* s = st->srv;
-  std::lock_guard<std::mutex> lk(s->mu);
+  std::unique_lock<std::mutex> lk(s->mu);
   if (st->closing || s->stop) return fail(HZD_E_CLOSED, "stream is closing");
   if (st->queued >= kMaxQueuedPerStream) return fail(HZD_E_AGAIN, "stream queue full");
+  // an event on the producer's stream, taken from the pool (or created)
+  hipEvent_t ev = nullptr;
+  if (!s->ready_pool.empty()) {
+    ev = s->ready_pool.back();
+    s->ready_pool.pop_back();
+  }
+  lk.unlock();
+  (void)hipSetDevice(s->cfg.device);
+  if (!ev && (rc = check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "ready event")) != HZD_OK) return rc;
+  if ((rc = check(hipEventRecord(ev, reinterpret_cast<hipStream_t>(ready_stream)), "ready record")) != HZD_OK) {
+    lk.lock();
+    s->ready_pool.push_back(ev);
+    return rc;
+  }
+  lk.lock();
+  if (st->closing || s->stop || st->queued >= kMaxQueuedPerStream) {   // changed while unlocked
+    s->ready_pool.push_back(ev);
+    return st->queued >= kMaxQueuedPerStream ? fail(HZD_E_AGAIN, "stream queue full")
+                                             : fail(HZD_E_CLOSED, "stream is closing");
+  }
   Job j;
+  j.ready = ev;
   j.st = st;
   j.fr = *frame;
   j.fr.params = nullptr;
@@ -469,11 +569,14 @@ int hzd_stream_state(hzd_stream* st, float* A_host, int32_t* sel_host) {
   }
   if (slot < 0) return fail(HZD_E_AGAIN, "no frame of this stream has completed yet");
   (void)hipSetDevice(st->srv->cfg.device);
-  uint8_t buf[32];
-  int rc = check(hipMemcpy(buf, st->state_dev + 256 * slot, 32, hipMemcpyDeviceToHost), "state copy");
-  if (rc) return rc;
-  if (A_host) std::memcpy(A_host, buf, 12);
-  if (sel_host) std::memcpy(sel_host, buf + 16, 12);
+  if (A_host) {
+    int rc = check(hipMemcpy(A_host, st->state_dev + 256 * slot, 12, hipMemcpyDeviceToHost), "state copy");
+    if (rc) return rc;
+  }
+  if (sel_host) {
+    const volatile int32_t* cell = st->status[slot];
+    for (int k = 0; k < 4; ++k) sel_host[k] = cell[k];
+  }
   clear_error();
   return HZD_OK;
 }
@@ -489,6 +592,7 @@ int hzd_stream_close(hzd_stream* st) {
   s->stats.open_streams = (int)s->streams.size();
   s->stats.arena_used = s->arena.used();
   lk.unlock();
+  for (int k = 0; k < kSlotsPerStream; ++k) status_cells().put(st->status[k]);
   delete st;
   clear_error();
   return HZD_OK;

@@ -100,6 +100,7 @@ def compare(I: np.ndarray, p: hzd.Params, g: dict, ref=None, label: str = "") ->
     assert int(g["sel"][0]) == a["K"], f"{label}: K {g['sel'][0]} != {a['K']}"
     assert int(g["sel"][1]) == int(a["vstar"]), f"{label}: vstar {g['sel'][1]} != {a['vstar']}"
     assert int(g["sel"][2]) == a["cutoff"], f"{label}: cutoff {g['sel'][2]} != {a['cutoff']}"
+    assert int(g["sel"][3]) == 0, f"{label}: selection consistency status {g['sel'][3]}"
     A32 = a["A"].astype(np.float32)
     assert np.array_equal(g["A"], A32), f"{label}: A {g['A']} != {A32}"
     fp16_map = (p.precision == hzd.PREC_FP16 and p.mode == hzd.MODE_OFFLINE

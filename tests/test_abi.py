@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(hzd.SYMBOLS), "binding and header disagree"
-    assert L.hzd_abi_version() == hzd.ABI_VERSION == 2
+    assert L.hzd_abi_version() == hzd.ABI_VERSION == 3
 
 
 def test_struct_sizes_match_header():

@@ -27,13 +27,14 @@ def test_largest_frame_realtime_identity_and_selection():
     dst = torch.empty_like(src)
     p = hzd.Params(omega=0.0, gamma=1.0)
     aux = {"A": torch.zeros(3, dtype=torch.float32, device="cuda"),
-           "sel": torch.zeros(3, dtype=torch.int32, device="cuda")}
+           "sel": torch.zeros(4, dtype=torch.int32, device="cuda")}
     hzd.dehaze_frame(src, dst, p, aux=aux)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
     n = SIDE * SIDE
     assert int(aux["sel"][0]) == max(1, int(np.floor(float(np.float32(p.top_frac)) * n)))
     assert 0 <= int(aux["sel"][2]) < n
+    assert int(aux["sel"][3]) == 0
     del src, dst
     torch.cuda.empty_cache()
 

@@ -47,6 +47,7 @@ def test_served_equals_alone_in_a_mix():
     A, sel = streams[0].state()
     ref = oracle.dehaze(frames[0][3], oracle_params(RT))
     assert sel[0] == ref.aux["K"] and sel[1] == int(ref.aux["vstar"])
+    assert sel[2] == ref.aux["cutoff"] and sel[3] == 0
     assert np.allclose(A, ref.aux["A"].astype(np.float32))
     for st in streams:
         st.close()
@@ -216,5 +217,33 @@ def test_wait_twice_on_a_ticket_is_an_error():
     assert rc == 0
     assert st.wait(t)[0] == hzd.HZD_E_INVAL        # already collected: an error, not a wait forever
     assert st.wait(t + 100)[0] == hzd.HZD_E_INVAL  # never issued
+    st.close()
+    srv.close()
+
+
+def test_submit_waits_for_the_producer_stream():
+    """A frame written on another stream just before submit is read only after that stream's
+    work: the submit records an event on the producer's stream and the launch waits for it."""
+    w, h = 640, 480
+    I = make_frame(w, h, 77).I
+    alone = run_gpu(I, RT, with_J=False)["out"]
+    srv = hzd.Server(arena_bytes=_need(RT, w, h) + (1 << 20), max_inflight=2, frames_per_launch=1, hip_streams=1)
+    st = srv.open(RT, w, h)
+    src = torch.zeros((h, w, 3), dtype=torch.uint8, device="cuda")
+    dst = torch.full((h, w, 3), 7, dtype=torch.uint8, device="cuda")
+    host = torch.from_numpy(I).pin_memory()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = torch.randn(4096, 4096, device="cuda")
+        for _ in range(6):            # keeps the producer stream busy for milliseconds
+            a = (a @ a) / 64.0
+        src.copy_(host, non_blocking=True)
+        dst.zero_()
+    t = st.submit(src, dst, stream=side)
+    rc, _ = st.wait(t)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(dst.cpu().numpy(), alone)
     st.close()
     srv.close()
