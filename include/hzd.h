@@ -230,6 +230,25 @@ int hzd_dehaze_batch(const hzd_params* params, const hzd_frame* frames, int32_t 
                      const hzd_frame_aux* aux, void* workspace, size_t ws_bytes,
                      void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as hzd_dehaze_frame, with the workspace taken from a static
+ * device array of HZD_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device it runs on until the process ends.  The frame's hzd_workspace_size
+ * must not exceed that size (a 1920x1080 offline frame fits; a 3840x2160
+ * offline frame does not): larger requests return HZD_E_NOMEM before any
+ * device work.  hip_stream must belong to the current device (HZD_E_INVAL
+ * otherwise).  The call allocates nothing: no hipMalloc/hipFree, no graph,
+ * event or stream creation; kernels are launched directly on hip_stream
+ * (the graph cache and profiling are not used).  Every call on one device
+ * shares that device's array and leaves its contents behind; the kernels
+ * clear what must start at zero.  Calls that overlap on one device (other
+ * streams or threads, before the previous call has completed in stream
+ * order) race on the array: the caller serialises them. */
+#define HZD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hzd_dehaze_frame_noalloc(const hzd_params* params, const hzd_frame* frame,
+                             const hzd_frame_aux* aux, void* hip_stream);
+
 /* ---------------------------------------------------------------- serving
  * A server owns a scheduler thread and a few HIP streams on one device.
  * Streams of frames (each of one size and one parameter set) are opened

@@ -27,6 +27,7 @@ TX_HE, TX_PAPER = 0, 1
 PREC_FP32, PREC_FP16 = 0, 1
 PRESET_REALTIME, PRESET_OFFLINE, PRESET_PAPER_REALTIME = 0, 1, 2
 ABI_VERSION = 3
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HZD_NOALLOC_SCRATCH_BYTES
 
 
 class HzdError(RuntimeError):
@@ -92,6 +93,8 @@ SYMBOLS = {
     "hzd_dehaze_frame": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame),
                                         ctypes.POINTER(hzd_frame_aux), ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "hzd_dehaze_frame_noalloc": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame),
+                                                ctypes.POINTER(hzd_frame_aux), ctypes.c_void_p]),
     "hzd_dehaze_batch": (ctypes.c_int, [ctypes.POINTER(hzd_params), ctypes.POINTER(hzd_frame),
                                         ctypes.c_int32, ctypes.POINTER(hzd_frame_aux), ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p]),
@@ -284,6 +287,19 @@ def dehaze_frame(src: torch.Tensor, dst: torch.Tensor, params: Params, aux: dict
     rc = lib().hzd_dehaze_frame(ctypes.byref(pc), ctypes.byref(f), ctypes.byref(a) if a else None,
                                 workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
     _check(rc, "hzd_dehaze_frame")
+
+
+def dehaze_frame_noalloc(src: torch.Tensor, dst: torch.Tensor, params: Params, aux: dict | None = None,
+                         stream=None, airlight_state: torch.Tensor | None = None) -> None:
+    """hzd_dehaze_frame_noalloc: as dehaze_frame, with the workspace taken from the library's
+    static device scratch (NOALLOC_SCRATCH_BYTES per device) instead of a caller buffer.
+    Calls that overlap on one device race on that scratch."""
+    f = _frame_struct(src, dst, params, airlight_state=airlight_state)
+    pc = params.c()
+    a = _aux_struct(aux)
+    rc = lib().hzd_dehaze_frame_noalloc(ctypes.byref(pc), ctypes.byref(f), ctypes.byref(a) if a else None,
+                                        _stream_handle(stream))
+    _check(rc, "hzd_dehaze_frame_noalloc")
 
 
 def dehaze_batch(srcs, dsts, params: Params, per_frame_params=None, auxs=None,

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhzd.so")
-SOURCES = ["hzd_kernels.hip", "hzd_api.cpp", "hzd_server.cpp"]
+SOURCES = ["hzd_kernels.hip", "hzd_api.cpp", "hzd_server.cpp", "hzd_noalloc.hip"]
 
 ARCH = os.environ.get("HZD_OFFLOAD_ARCH", "gfx950")
 COMMON = [

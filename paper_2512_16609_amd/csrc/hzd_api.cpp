@@ -638,11 +638,11 @@ int launch_concurrent(std::vector<GroupLaunch>& ls, hipStream_t s) {
   return rc;
 }
 
-int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, const hzd_frame_aux* aux,
-                void* workspace, size_t ws_bytes, void* stream) {
+int validate_call(const hzd_params* params, const hzd_frame* frames, int32_t n,
+                  std::vector<const hzd_params*>& ps, std::vector<size_t>& offs, size_t* need) {
   if (n < 1) return fail(HZD_E_INVAL, "n = %d < 1", n);
   if (!frames) return fail(HZD_E_INVAL, "frames is NULL");
-  std::vector<const hzd_params*> ps(n);
+  ps.assign(n, nullptr);
   for (int i = 0; i < n; ++i) {
     ps[i] = frames[i].params ? frames[i].params : params;
     int rc = validate_params(ps[i]);
@@ -662,14 +662,38 @@ int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, co
     if (std::adjacent_find(states.begin(), states.end()) != states.end())
       return fail(HZD_E_INVAL, "two frames of one call share an airlight_state");
   }
+  offs.assign(n, 0);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    offs[i] = total;
+    total += frame_ws_bytes(*ps[i], frames[i].width, frames[i].height);
+  }
+  *need = total;
+  return HZD_OK;
+}
+
+int run_frame_direct(const hzd_params* p, const hzd_frame& fr, const hzd_frame_aux* aux, void* ws,
+                     hipStream_t s) {
+  Batch b;
+  ResizeBatch rz;
+  std::memset(&b, 0, sizeof(b));
+  std::memset(&rz, 0, sizeof(rz));
+  b.n = rz.n = 1;
+  b.f[0] = make_frame_dev(*p, fr, aux, reinterpret_cast<uint8_t*>(ws), &rz.f[0]);
+  const GroupKey g = group_key(*p);
+  if (g.mode == HZD_MODE_OFFLINE) fit_gf_rows(b);
+  return run_group(g, b, &rz, s, false);
+}
+
+int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, const hzd_frame_aux* aux,
+                void* workspace, size_t ws_bytes, void* stream) {
+  std::vector<const hzd_params*> ps;
+  std::vector<size_t> offs;
+  size_t need = 0;
+  int vrc = validate_call(params, frames, n, ps, offs, &need);
+  if (vrc) return vrc;
   if (!workspace) return fail(HZD_E_INVAL, "workspace is NULL");
   if ((uintptr_t)workspace % 256) return fail(HZD_E_INVAL, "workspace not 256-byte aligned");
-  std::vector<size_t> offs(n);
-  size_t need = 0;
-  for (int i = 0; i < n; ++i) {
-    offs[i] = need;
-    need += frame_ws_bytes(*ps[i], frames[i].width, frames[i].height);
-  }
   if (ws_bytes < need) return fail(HZD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
 
   std::map<GroupKey, std::vector<int>> groups;

@@ -4,6 +4,8 @@
 
 #include <stddef.h>
 
+#include <vector>
+
 #include "hzd.h"
 #include "hzd_internal.h"
 
@@ -27,5 +29,14 @@ int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStrea
 // rz: the resampling descriptors of a group with g.resize (else unused, may be NULL)
 int launch_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s);
 int check(hipError_t e, const char* what);
+// Validation shared by the frame/batch entry points (parameters, frames,
+// airlight states); fills the per-frame parameters, workspace offsets and the
+// total workspace bytes.  No device work.
+int validate_call(const hzd_params* params, const hzd_frame* frames, int32_t n,
+                  std::vector<const hzd_params*>& ps, std::vector<size_t>& offs, size_t* need);
+// One validated frame, launched directly on s: no graph cache, no timing
+// events, no helper streams (nothing is created or allocated).
+int run_frame_direct(const hzd_params* p, const hzd_frame& fr, const hzd_frame_aux* aux, void* ws,
+                     hipStream_t s);
 
 }  // namespace hzd

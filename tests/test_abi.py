@@ -106,6 +106,23 @@ def test_frame_validation(L):
     assert L.hzd_dehaze_batch(ctypes.byref(pc), None, 0, None, None, 0, None) == hzd.HZD_E_INVAL
 
 
+def test_noalloc_rejects_before_device_work(L):
+    """hzd_dehaze_frame_noalloc validates and checks the static scratch size before any HIP
+    call, so on a machine without a GPU every rejection is observable."""
+    assert L.hzd_dehaze_frame_noalloc(None, None, None, None) == hzd.HZD_E_INVAL
+    pc = hzd.Params().c()
+    f = hzd.hzd_frame(FAKE_SRC, 0, FAKE_DST, 192, 64, 48, None, None)      # pitch < 3W
+    assert L.hzd_dehaze_frame_noalloc(ctypes.byref(pc), ctypes.byref(f), None, None) == hzd.HZD_E_INVAL
+    # a 3840x2160 offline frame needs more workspace than the static scratch holds
+    po = hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1)
+    assert hzd.workspace_size(po, [(2160, 3840)]) > hzd.NOALLOC_SCRATCH_BYTES
+    assert hzd.workspace_size(po, [(1080, 1920)]) <= hzd.NOALLOC_SCRATCH_BYTES
+    pc = po.c()
+    f = hzd.hzd_frame(FAKE_SRC, 3 * 3840, FAKE_DST, 3 * 3840, 3840, 2160, None, None)
+    assert L.hzd_dehaze_frame_noalloc(ctypes.byref(pc), ctypes.byref(f), None, None) == hzd.HZD_E_NOMEM
+    assert "static scratch" in hzd.last_error()
+
+
 def test_resize_validation(L):
     for rw, rh in [(640, 0), (0, 480), (-1, 480), (16385, 10), (10, 16385)]:
         assert call_frame(L, hzd.Params(resize_width=rw, resize_height=rh)) == hzd.HZD_E_INVAL, (rw, rh)
