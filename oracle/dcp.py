@@ -36,6 +36,12 @@ parameter or a documented choice of the GPU library):
   * J is clamped to [0, 255] before the gamma of Eq. (8);
   * colour balance is gray-world on the gamma-corrected image:
     g_c = mean(mu) / mu_c (g_c = 1 when mu_c = 0), J_c <- min(255, g_c J_c);
+  * the second balance (the "simple" white balance by percentiles): per
+    channel, the black and white points are the low and high percentiles of
+    the channel's unbalanced output codes q = RNE(J_gamma): with k =
+    floor(p W H), lo is the (k+1)-th smallest and hi the (k+1)-th largest
+    code; the channel is stretched linearly, J_c <- clamp((J_c - lo) 255 /
+    (hi - lo), 0, 255), and left as it is when hi <= lo;
   * the output is rounded half to even and saturated to uint8;
   * the optional resize of Sec. V step 1 (the paper names no interpolation) is
     bilinear sampling with pixel centres aligned, source coordinates clamped
@@ -79,7 +85,8 @@ class Params:
     gamma: float = 1.2             # gamma of Eq. (8)
     gf_radius: int = 60            # guided-filter box radius r
     gf_eps: float = 1e-3           # guided-filter regulariser epsilon
-    color_balance: bool = False
+    color_balance: int = 0         # 0 none, 1 gray-world, 2 percentile stretch (True = 1)
+    wb_percentile: float = 0.02    # fraction p of pixels ignored at each end of each channel (balance 2)
     tx: str = "he"                 # "he" (dark(I/A)) or "paper" (literal Eq. (4))
     resize_width: int = 0          # Sec. V step 1 target size; 0 x 0 = native size
     resize_height: int = 0
@@ -378,9 +385,65 @@ def gray_world(Jg: np.ndarray):
     return np.minimum(255.0, Jg * gains[None, None, :]), gains
 
 
+def percentile_points(q: np.ndarray, p: float):
+    """Black and white points of one channel's integer codes q (any shape).
+
+    With N codes and k = floor(p N) (p as its float32 value), lo is the
+    (k+1)-th smallest code and hi the (k+1)-th largest, read off the
+    256-bin histogram: lo is the smallest v with #{q <= v} > k, hi the
+    largest v with #{q >= v} > k.
+    """
+    q = np.asarray(q).reshape(-1).astype(np.int64)
+    n = q.size
+    k = int(math.floor(f32(p) * n))
+    hist = np.bincount(q, minlength=256)
+    below = np.cumsum(hist)                  # #{q <= v}
+    above = np.cumsum(hist[::-1])[::-1]      # #{q >= v}
+    lo = int(np.flatnonzero(below > k)[0])
+    hi = int(np.flatnonzero(above > k)[-1])
+    return lo, hi
+
+
+def percentile_stretch(Jg: np.ndarray, p: float, band: float = 0.0):
+    """The percentile ("simple") white balance on the gamma-corrected image.
+
+    Per channel: q = RNE(J_gamma) are the unbalanced output codes, (lo, hi)
+    = percentile_points(q, p), and J_c <- clamp((J_c - lo) 255 / (hi - lo),
+    0, 255), unchanged when hi <= lo.  Returns (balanced image, points,
+    candidates): points[c] = (lo, hi) from these codes, and candidates[c] =
+    ((lo_min, lo_max), (hi_min, hi_max)), the range each point can take when
+    every value may move by up to `band` before rounding (a computation with
+    that error could round codes within band of a half-integer either way).
+    """
+    out = np.empty_like(Jg, dtype=np.float64)
+    points, cands = [], []
+    for c in range(3):
+        x = Jg[..., c]
+        lo, hi = percentile_points(rne_u8(x), p)
+        lo_a, hi_a = percentile_points(rne_u8(x - band), p)
+        lo_b, hi_b = percentile_points(rne_u8(x + band), p)
+        points.append((lo, hi))
+        cands.append(((lo_a, lo_b), (hi_a, hi_b)))
+        out[..., c] = stretch_channel(x, lo, hi)
+    return out, points, cands
+
+
+def stretch_channel(x: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """clamp((x - lo) 255 / (hi - lo), 0, 255); x itself when hi <= lo."""
+    if hi <= lo:
+        return np.asarray(x, dtype=np.float64).copy()
+    return np.clip((x - lo) * (255.0 / (hi - lo)), 0.0, 255.0)
+
+
 def rne_u8(x: np.ndarray) -> np.ndarray:
     """Round half to even and saturate to uint8."""
     return np.clip(np.rint(x), 0, 255).astype(np.uint8)
+
+
+# Rounding margin for the percentile decisions: a single-precision J_gamma
+# may lie this far from the float64 value before rounding to a code (the
+# tolerances of t and J bound the difference well below it).
+WB_BAND = 2e-3
 
 
 # ------------------------------------------------------------- Sec. V
@@ -443,7 +506,12 @@ def dehaze(I: np.ndarray, p: Params, A_inject=None, A_prev=None) -> Result:
     else:
         Jg = gamma_correct(J, p.gamma)
     aux["Jg"] = Jg
-    if p.color_balance:
+    if p.color_balance == 2:
+        Jf, points, cands = percentile_stretch(Jg, p.wb_percentile, band=WB_BAND)
+        gains = np.ones(3)
+        aux["wb_points"] = points
+        aux["wb_candidates"] = cands
+    elif p.color_balance:
         Jf, gains = gray_world(Jg)
     else:
         Jf, gains = Jg, np.ones(3)

@@ -517,3 +517,83 @@ def test_pipeline_with_adaptive_gamma_uses_the_frame_gamma():
     # brighter target -> lower gamma exponent 1/gamma -> brighter output on average
     r2 = oracle.dehaze(I, Params(gamma_adaptive=True, gamma_target=0.7))
     assert r2.aux["gamma"] > g and r2.out.mean() > r.out.mean()
+
+
+# ------------------------------------------------- percentile ("simple") white balance
+def test_percentile_points_hand_example():
+    # ten codes, p = 0.1 -> k = 1: lo is the 2nd smallest, hi the 2nd largest (worked by hand)
+    q = np.array([20, 3, 41, 7, 3, 40, 21, 9, 40, 20])
+    assert oracle.percentile_points(q, 0.1) == (3, 40)
+    # p = 0 -> the extremes; p = 0.3 -> k = 3: sorted 3 3 7 9 20 20 21 40 40 41
+    assert oracle.percentile_points(q, 0.0) == (3, 41)
+    assert oracle.percentile_points(q, 0.3) == (9, 21)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_percentile_points_match_a_sort(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 5000))
+    q = rng.integers(0, 256, size=n) if seed % 2 else np.clip(rng.normal(120, 30, n), 0, 255).astype(int)
+    p = float(rng.choice([0.0, 0.001, 0.02, 0.1, 0.3]))
+    k = math.floor(float(np.float32(p)) * n)
+    srt = np.sort(q)
+    assert oracle.percentile_points(q, p) == (int(srt[k]), int(srt[n - 1 - k]))
+
+
+def test_percentile_stretch_of_a_ramp_is_the_closed_form():
+    x = np.arange(256, dtype=np.float64)
+    Jg = np.stack([x, x, x], axis=-1).reshape(16, 16, 3)
+    p = 10 / 256                               # float32-exact: k = 10
+    out, points, _ = oracle.percentile_stretch(Jg, p)
+    assert points == [(10, 245)] * 3
+    want = np.clip((x - 10) * 255.0 / 235.0, 0, 255).reshape(16, 16)
+    for c in range(3):
+        np.testing.assert_allclose(out[..., c], want, rtol=0, atol=1e-12)
+    assert out[..., 0].reshape(-1)[10] == 0.0 and abs(out[..., 0].reshape(-1)[245] - 255.0) < 1e-9
+
+
+def test_percentile_stretch_identity_and_flat_channel():
+    rng = np.random.default_rng(3)
+    Jg = rng.uniform(0, 255, size=(20, 30, 3))
+    Jg[0, 0, :] = 0.0
+    Jg[0, 1, :] = 255.0
+    Jg[..., 2] = 77.3                          # a flat channel: hi == lo, left as it is
+    out, points, _ = oracle.percentile_stretch(Jg, 0.0)
+    assert points[0] == (0, 255) and points[1] == (0, 255) and points[2] == (77, 77)
+    np.testing.assert_array_equal(out, Jg)
+
+
+def test_percentile_candidates_widen_only_near_half_codes():
+    x = np.full((1, 10), 50.2)
+    x[0, :3] = 10.4999                         # within the band of a half-integer: code 10 or 11
+    Jg = np.stack([x, x, x], axis=-1)
+    _, points, cands = oracle.percentile_stretch(Jg, 0.2, band=1e-3)    # k = 2: lo = 3rd smallest
+    assert points[0] == (10, 50)
+    assert cands[0] == ((10, 11), (50, 50))
+    _, _, cands0 = oracle.percentile_stretch(Jg, 0.2, band=0.0)
+    assert cands0[0] == ((10, 10), (50, 50))
+
+
+def test_pipeline_percentile_balance_stretches_each_channel():
+    I = make_frame(96, 64, 5, beta=1.2).I
+    base = oracle.dehaze(I, Params())
+    r = oracle.dehaze(I, Params(color_balance=2, wb_percentile=0.02))
+    q = oracle.rne_u8(base.aux["Jg"])
+    n = q.shape[0] * q.shape[1]
+    k = math.floor(float(np.float32(0.02)) * n)
+    for c in range(3):
+        srt = np.sort(q[..., c].reshape(-1))
+        lo, hi = int(srt[k]), int(srt[n - 1 - k])
+        assert r.aux["wb_points"][c] == (lo, hi)
+        # pixels at or below the black point map to 0, at or above the white point to 255
+        assert np.all(r.out[..., c][q[..., c] < lo] == 0)
+        assert np.all(r.out[..., c][q[..., c] > hi] == 255)
+    # the stretch is monotone per channel
+    for c in range(3):
+        order = np.argsort(base.aux["Jg"][..., c], axis=None)
+        assert np.all(np.diff(r.aux["Jf"][..., c].reshape(-1)[order]) >= 0)
+    # with p = 0 on a frame whose channels already span 0..255 nothing changes
+    Jspan = base.aux["Jg"].copy()
+    Jspan[0, 0, :], Jspan[0, 1, :] = 0.0, 255.0
+    out0, _, _ = oracle.percentile_stretch(Jspan, 0.0)
+    np.testing.assert_array_equal(out0, Jspan)
