@@ -59,7 +59,7 @@ STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1080p_offline.txt")
 RESIZE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_resize_1080p_to_640x480_x8.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_16609_amd", "csrc", "hzd_kernels.hip")
-EXTRAS = ("320", "video", "uneven", "offline8", "resize1", "resize8", "smooth", "gamma")
+EXTRAS = ("320", "video", "uneven", "offline8", "resize1", "resize8", "smooth", "gamma", "balance")
 
 
 def kernel_source_hash(path=KERNEL_SRC):
@@ -559,6 +559,37 @@ def adaptive_gamma_workload(hzd, torch, dev, samples, reps=200):
     return {"1920x1080_adaptive_gamma": out}
 
 
+def percentile_balance_workload(hzd, torch, dev, samples, reps=200):
+    """The balance stage's second reading, the percentile ("simple") white balance, against
+    gray-world on the 1920x1080 frame, one frame per call, offline (guided filter r=60) and
+    real time.  Both balances need a frame-wide reduction of J_gamma (channel sums or code
+    histograms) before any pixel is written, so both take one more pass."""
+    from synth import make_frame
+    sync = torch.cuda.synchronize
+    W, H = 1920, 1080
+    mp = W * H / 1e6
+    I = make_frame(W, H, 2).I
+    src = torch.from_numpy(I).to(dev)
+    dst = torch.empty_like(src)
+    out = {}
+    for mode, name in ((hzd.MODE_OFFLINE, "offline"), (hzd.MODE_REALTIME, "realtime")):
+        row = {}
+        for cb, cname in ((1, "gray_world"), (2, "percentile")):
+            p = hzd.Params(mode=mode, gf_radius=60, color_balance=cb, wb_percentile=0.02)
+            ws = hzd.alloc_workspace(hzd.workspace_size(p, [(H, W)]), dev)
+            call = hzd.FrameCall(src, dst, p, ws)
+            for _ in range(10):
+                call()
+            per = timed(call, reps, sync)
+            us = stage_us(hzd, call, 50, sync)
+            row[cname] = {"MP_per_s": round(mp / per, 1), "us_per_frame": round(per * 1e6, 2),
+                          "stage_us": {k: round(v, 2) for k, v in us.items()}}
+            if cb == 2:
+                samples.add(f"1920x1080_percentile_balance_{name}", I, p, capture_frame(hzd, torch, I, p, dev))
+        out[name] = row
+    return {"1920x1080_percentile_white_balance": dict(out, wb_percentile=0.02)}
+
+
 def extra_workloads(hzd, torch, dev, samples, which=EXTRAS):
     """The other configurations, each timed on its own (inputs resident in HBM)."""
     out = {}
@@ -576,6 +607,8 @@ def extra_workloads(hzd, torch, dev, samples, which=EXTRAS):
         out.update(smoothing_workload(hzd, torch, dev, samples))
     if "gamma" in which:
         out.update(adaptive_gamma_workload(hzd, torch, dev, samples))
+    if "balance" in which:
+        out.update(percentile_balance_workload(hzd, torch, dev, samples))
     torch.cuda.empty_cache()
     return out
 
@@ -722,10 +755,11 @@ def oracle_params(hzd, p):
     import oracle
     return oracle.Params(mode="offline" if p.mode == hzd.MODE_OFFLINE else "realtime", patch=p.patch,
                          omega=p.omega, t0=p.t0, top_frac=p.top_frac, alpha=p.alpha, gamma=p.gamma,
-                         gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=bool(p.color_balance),
+                         gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=int(p.color_balance),
                          tx="he" if p.tx == hzd.TX_HE else "paper", resize_width=p.resize_width,
                          resize_height=p.resize_height, airlight_smoothing=p.airlight_smoothing,
-                         gamma_adaptive=bool(p.gamma_adaptive), gamma_target=p.gamma_target)
+                         gamma_adaptive=bool(p.gamma_adaptive), gamma_target=p.gamma_target,
+                         wb_percentile=p.wb_percentile)
 
 
 def _oracle_worker(args):

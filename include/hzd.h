@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HZD_ABI_VERSION 3
+#define HZD_ABI_VERSION 4
 
 typedef enum {
   HZD_OK = 0,
@@ -91,7 +91,18 @@ typedef enum {
  *   gf_radius      guided-filter box radius r (OFFLINE), 1..64
  *   gf_eps         guided-filter regulariser (OFFLINE), [1e-8, 1]; the guide is
  *                  the BT.601 luma of the hazy input scaled to [0, 1]
- *   color_balance  0/1: gray-world gains on the gamma-corrected image (Sec. IV-E)
+ *   color_balance  the balance stage of Sec. IV-E, on the gamma-corrected image:
+ *                  0 = none; 1 = gray-world gains g_c = mean(mu) / mu_c, where
+ *                  mu_c is the channel mean (1 when mu_c = 0), clamped to 255;
+ *                  2 = percentile ("simple") white balance: per channel the
+ *                  black point lo is the (k+1)-th smallest and the white point
+ *                  hi the (k+1)-th largest of the unbalanced output codes
+ *                  RNE(J_gamma), k = floor(wb_percentile * W * H), and the
+ *                  channel becomes clamp((J_gamma - lo) * 255 / (hi - lo), 0,
+ *                  255) (unchanged when hi <= lo).  With 2, offline mode
+ *                  needs precision FP32 (HZD_E_UNSUPPORTED otherwise): the
+ *                  percentile decisions are taken on codes of J_gamma, which a
+ *                  binary16 t map would move.
  *   tx             hzd_tx
  *   precision      hzd_prec
  *   resize_width, resize_height
@@ -127,7 +138,9 @@ typedef enum {
  *                  frame's mean luma is mapped to the target.  Costs one more
  *                  pass over the frame (the sums of J must be complete
  *                  before any pixel is corrected).
- *   gamma_target   tau in (0, 1), the mean luma aimed for (default 0.5). */
+ *   gamma_target   tau in (0, 1), the mean luma aimed for (default 0.5).
+ *   wb_percentile  p in [0, 0.49]: fraction of pixels ignored at each end of
+ *                  each channel by the percentile white balance (default 0.02). */
 typedef struct hzd_params {
   uint32_t size;
   int32_t mode;
@@ -147,6 +160,7 @@ typedef struct hzd_params {
   float airlight_smoothing;
   int32_t gamma_adaptive;
   float gamma_target;
+  float wb_percentile;
 } hzd_params;
 
 /* One frame: device pointers and geometry (see the conventions above).

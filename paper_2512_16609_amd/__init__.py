@@ -26,7 +26,7 @@ MODE_REALTIME, MODE_OFFLINE = 0, 1
 TX_HE, TX_PAPER = 0, 1
 PREC_FP32, PREC_FP16 = 0, 1
 PRESET_REALTIME, PRESET_OFFLINE, PRESET_PAPER_REALTIME = 0, 1, 2
-ABI_VERSION = 3
+ABI_VERSION = 4
 NOALLOC_SCRATCH_BYTES = 64 << 20   # HZD_NOALLOC_SCRATCH_BYTES
 
 
@@ -43,7 +43,8 @@ class hzd_params(ctypes.Structure):
                 ("gf_eps", ctypes.c_float), ("color_balance", ctypes.c_int32), ("tx", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("resize_width", ctypes.c_int32),
                 ("resize_height", ctypes.c_int32), ("airlight_smoothing", ctypes.c_float),
-                ("gamma_adaptive", ctypes.c_int32), ("gamma_target", ctypes.c_float)]
+                ("gamma_adaptive", ctypes.c_int32), ("gamma_target", ctypes.c_float),
+                ("wb_percentile", ctypes.c_float)]
 
 
 class hzd_frame(ctypes.Structure):
@@ -165,7 +166,7 @@ class Params:
     gamma: float = 1.2
     gf_radius: int = 60
     gf_eps: float = 1e-3
-    color_balance: int = 0
+    color_balance: int = 0    # 0 none, 1 gray-world, 2 percentile white balance
     tx: int = TX_HE
     precision: int = PREC_FP32
     resize_width: int = 0     # Sec. V step 1 working size; 0 x 0 = the frame's own size
@@ -173,13 +174,14 @@ class Params:
     airlight_smoothing: float = 0.0   # temporal airlight weight lam; needs an airlight state
     gamma_adaptive: int = 0   # 1: per-frame gamma mapping the mean luma of J to gamma_target
     gamma_target: float = 0.5
+    wb_percentile: float = 0.02   # percentile white balance: fraction ignored at each end
 
     def c(self) -> hzd_params:
         return hzd_params(ctypes.sizeof(hzd_params), self.mode, self.patch, self.omega, self.t0,
                           self.top_frac, self.alpha, self.gamma, self.gf_radius, self.gf_eps,
                           int(self.color_balance), self.tx, self.precision, self.resize_width,
                           self.resize_height, self.airlight_smoothing, int(self.gamma_adaptive),
-                          self.gamma_target)
+                          self.gamma_target, self.wb_percentile)
 
     def output_shape(self, h: int, w: int) -> tuple:
         """(height, width) of the output of a frame of input shape (h, w)."""
@@ -193,7 +195,7 @@ class Params:
         _check(lib().hzd_params_default(ctypes.byref(p), preset), "hzd_params_default")
         return Params(p.mode, p.patch, p.omega, p.t0, p.top_frac, p.alpha, p.gamma, p.gf_radius,
                       p.gf_eps, p.color_balance, p.tx, p.precision, p.resize_width, p.resize_height,
-                      p.airlight_smoothing, p.gamma_adaptive, p.gamma_target)
+                      p.airlight_smoothing, p.gamma_adaptive, p.gamma_target, p.wb_percentile)
 
 
 # ------------------------------------------------------------------ frames

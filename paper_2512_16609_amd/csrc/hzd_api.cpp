@@ -51,8 +51,12 @@ int validate_params(const hzd_params* p) {
     return fail(HZD_E_INVAL, "top_frac %g outside (0,1]", p->top_frac);
   if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(HZD_E_INVAL, "alpha %g outside (0,1]", p->alpha);
   if (!in_range(p->gamma, 0.1f, 10.0f)) return fail(HZD_E_INVAL, "gamma %g outside [0.1,10]", p->gamma);
-  if (p->color_balance != 0 && p->color_balance != 1)
-    return fail(HZD_E_INVAL, "color_balance %d must be 0 or 1", p->color_balance);
+  if (p->color_balance < 0 || p->color_balance > 2)
+    return fail(HZD_E_INVAL, "color_balance %d must be 0, 1 or 2", p->color_balance);
+  if (p->color_balance == 2) {
+    if (!in_range(p->wb_percentile, 0.0f, 0.49f))
+      return fail(HZD_E_INVAL, "wb_percentile %g outside [0,0.49]", p->wb_percentile);
+  }
   if (p->tx != HZD_TX_HE && p->tx != HZD_TX_PAPER) return fail(HZD_E_INVAL, "tx %d unknown", p->tx);
   if (p->precision != HZD_PREC_FP32 && p->precision != HZD_PREC_FP16)
     return fail(HZD_E_INVAL, "precision %d unknown", p->precision);
@@ -61,6 +65,8 @@ int validate_params(const hzd_params* p) {
     if (p->gf_radius > kMaxRadius)
       return fail(HZD_E_UNSUPPORTED, "gf_radius %d > %d", p->gf_radius, kMaxRadius);
     if (!in_range(p->gf_eps, 1e-8f, 1.0f)) return fail(HZD_E_INVAL, "gf_eps %g outside [1e-8,1]", p->gf_eps);
+    if (p->color_balance == 2 && p->precision == HZD_PREC_FP16)
+      return fail(HZD_E_UNSUPPORTED, "the percentile white balance of offline mode needs FP32 precision");
   }
   if (p->gamma_adaptive != 0 && p->gamma_adaptive != 1)
     return fail(HZD_E_INVAL, "gamma_adaptive %d must be 0 or 1", p->gamma_adaptive);
@@ -359,7 +365,9 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   const bool aligned = ((uintptr_t)d.src % 4 == 0) && ((uintptr_t)d.dst % 4 == 0) && (d.src_pitch % 4 == 0) &&
                        (d.dst_pitch % 4 == 0);
   d.flags = (p.gamma == 1.0f ? kFdGammaOne : 0u) | (aligned ? kFdAligned : 0u) |
-            (p.gamma_adaptive ? kFdGammaAdaptive : 0u);
+            (p.gamma_adaptive ? kFdGammaAdaptive : 0u) | (p.color_balance == 2 ? kFdWbPercentile : 0u);
+  // percentile white balance: k = floor(p W H) pixels ignored at each end of each channel
+  d.wb_k = p.color_balance == 2 ? (int32_t)std::floor((double)p.wb_percentile * n) : 0;
   return d;
 }
 
@@ -771,6 +779,7 @@ int hzd_params_default(hzd_params* p, int32_t preset) {
   p->precision = HZD_PREC_FP32;
   p->gamma_adaptive = 0;
   p->gamma_target = 0.5f;
+  p->wb_percentile = 0.02f;
   switch (preset) {
     case HZD_PRESET_REALTIME: break;
     case HZD_PRESET_OFFLINE:

@@ -27,8 +27,9 @@ struct FrameState {
   int32_t sel[4];                       // K, vstar, cutoff, consistency flag (0 = ok)
   unsigned long long cb[kCbSlots][4];   // sum of J_gamma^c in 2^-23 fixed point, per slot
   unsigned long long luma[kCbSlots];    // adaptive gamma: sum of the BT.601 luma of J in 2^-16 fixed point
+  uint32_t wbh[kHistSlots][3][256];     // percentile white balance: histograms of the codes RNE(J_gamma^c), per slot
 };
-static_assert(sizeof(FrameState) <= 12288, "FrameState too large");
+static_assert(sizeof(FrameState) <= 40960, "FrameState too large");
 
 // Per-row record of the airlight selection pass: the row's pixels with
 // D == vstar (ties) and D > vstar, counted and summed per channel.
@@ -71,6 +72,7 @@ struct FrameDev {
   int32_t gf_rows;   // output rows per guided-filter block
   float ema;         // temporal airlight weight lam (0 = none)
   float gamma_target;  // tau of the adaptive gamma
+  int32_t wb_k;      // percentile white balance: k = floor(p W H)
   uint32_t flags;    // kFd* bits
 };
 
@@ -79,6 +81,7 @@ constexpr uint32_t kFdGammaOne = 1u;        // gamma == 1: Eq. (8) is the identi
 constexpr uint32_t kFdAligned = 2u;         // src, dst and both pitches are multiples of 4
 constexpr uint32_t kFdEmaFirst = 4u;        // the stream's first frame: ignore the stored airlight
 constexpr uint32_t kFdGammaAdaptive = 8u;   // per-frame gamma from the luma sums of J
+constexpr uint32_t kFdWbPercentile = 16u;   // balance by percentile stretch (else gray-world)
 
 struct Batch {
   int32_t n;

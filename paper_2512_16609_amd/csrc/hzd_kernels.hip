@@ -1355,6 +1355,74 @@ __device__ __forceinline__ void cb_gains(const FrameDev& fd, float g[3], unsigne
   for (int c = 0; c < 3; ++c) g[c] = (float)(mu[c] > 0.0 ? mbar / mu[c] : 1.0);
 }
 
+// Percentile ("simple") white balance, the second balance of Sec. IV-E.  The
+// sums pass histograms the codes RNE(J_gamma^c) the unbalanced output would
+// have (per block in LDS, merged into the frame's slots with integer
+// atomics); the output pass reads the black point lo (the (k+1)-th smallest
+// code) and the white point hi (the (k+1)-th largest) of each channel off the
+// merged histograms and stretches the channel: clamp((J_gamma - lo) 255 /
+// (hi - lo), 0, 255), or leaves it when hi <= lo.  Every block derives the
+// same points from the same integers.
+constexpr int kWbBins = 3 * 256;
+
+__device__ __forceinline__ void wb_hist_zero(uint32_t* s_wbh) {
+  for (int i = threadIdx.x; i < kWbBins; i += 256) s_wbh[i] = 0u;
+}
+
+__device__ __forceinline__ void wb_hist_add(uint32_t* s_wbh, const float Jg[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) atomicAdd(&s_wbh[c * 256 + rne_u8(Jg[c])], 1u);
+}
+
+__device__ __forceinline__ void wb_hist_merge(const FrameDev& fd, int tile, const uint32_t* s_wbh) {
+  __syncthreads();
+  uint32_t* slot = &fd.st->wbh[tile % kHistSlots][0][0];
+  for (int i = threadIdx.x; i < kWbBins; i += 256) {
+    const uint32_t v = s_wbh[i];
+    if (v) atomicAdd(&slot[i], v);
+  }
+}
+
+struct WbConsts {
+  float lo[3], sc[3];
+  bool on[3];
+};
+
+// Black and white points of the three channels (256-thread blocks: thread t
+// holds bin t; an inclusive scan gives #{q <= t}).  lo is the bin where the
+// count first exceeds k; hi is the last bin with more than k codes at or
+// above it, i.e. the bin where #{q < t} < N - k <= #{q <= t}.
+__device__ __forceinline__ WbConsts wb_points(const FrameDev& fd, uint32_t* s_tmp, int* s_pts) {
+  const int t = threadIdx.x;
+  uint32_t h[3] = {0u, 0u, 0u};
+#pragma unroll
+  for (int sl = 0; sl < kHistSlots; ++sl)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) h[c] += fd.st->wbh[sl][c][t];
+  const uint32_t N = (uint32_t)fd.W * (uint32_t)fd.H, k = (uint32_t)fd.wb_k;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uint32_t tot;
+    const uint32_t incl = block_scan_total<4>(h[c], s_tmp, tot), excl = incl - h[c];
+    if (incl > k && excl <= k) s_pts[2 * c] = t;
+    if (excl < N - k && incl >= N - k) s_pts[2 * c + 1] = t;
+  }
+  __syncthreads();
+  WbConsts w;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int lo = s_pts[2 * c], hi = s_pts[2 * c + 1];
+    w.on[c] = hi > lo;
+    w.lo[c] = (float)lo;
+    w.sc[c] = w.on[c] ? 255.0f / (float)(hi - lo) : 1.0f;
+  }
+  return w;
+}
+
+__device__ __forceinline__ float wb_apply(const WbConsts& w, int c, float jg) {
+  return w.on[c] ? __builtin_amdgcn_fmed3f((jg - w.lo[c]) * w.sc[c], 0.0f, 255.0f) : jg;
+}
+
 // Adaptive gamma (the abstract's "gamma-adaptive" correction, with the rule
 // gamma = ln(mu) / ln(tau)): mu is the mean BT.601 luma of J / 255 from exact
 // fixed-point sums, floored at 2^-20, and gamma is clamped to [1/2, 2].
@@ -1402,6 +1470,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   __shared__ long long s_q[2][kRpi][2][kGfCols];
   __shared__ double2 s_rows[kGfRowsMax];
   __shared__ unsigned long long s_red[4];
+  __shared__ uint32_t s_wbh[PHASE == 1 ? kWbBins : 1];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -1414,6 +1483,8 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   const int2* col = fd.AB + min(max(g.xl, 0), W - 1);
   gf_row_table(g, s_rows);
   const ReconConsts rc = recon_consts(fd);
+  const bool wb = PHASE == 1 && (fd.flags & kFdWbPercentile);   // block-uniform
+  if (wb) wb_hist_zero(s_wbh);   // ordered before its first use by the row loop's first barrier
 
   long long sa = 0, sb = 0;
   if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
@@ -1555,7 +1626,11 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
           if (FP16) reinterpret_cast<__half*>(fd.tmap)[pi] = __float2half_rn(t);
           else reinterpret_cast<float*>(fd.tmap)[pi] = t;
           if (PHASE == 1) {
-            acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+            if (wb) {
+              wb_hist_add(s_wbh, Jg);
+            } else {
+              acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+            }
           } else {
             acc[0] += luma_fixed(J);
           }
@@ -1563,7 +1638,10 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
       }
     }
   }
-  if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
+  if (PHASE == 1) {
+    if (wb) wb_hist_merge(fd, tile, s_wbh);
+    else cb_accumulate(fd, tile, acc, s_red);
+  }
   if (PHASE == 2) luma_accumulate(fd, tile, acc[0], s_red);
 }
 
@@ -1595,6 +1673,9 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   constexpr bool OUT = PHASE == 0 || PHASE == 2;   // this phase writes the output
   __shared__ unsigned long long s_red[4];
   __shared__ unsigned long long s_gam[1];
+  __shared__ uint32_t s_wbh[PHASE == 1 ? kWbBins : 1];
+  __shared__ uint32_t s_wtmp[4];
+  __shared__ int s_wpts[6];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -1606,8 +1687,17 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   const TxConsts k = tx_consts(fd);
   ReconConsts rc = recon_consts(fd);
   if (PHASE != 3 && (fd.flags & kFdGammaAdaptive)) adaptive_gamma(fd, rc, s_gam);   // uniform per block
+  const bool wb = (PHASE == 1 || PHASE == 2) && (fd.flags & kFdWbPercentile);   // block-uniform
   float gain[3] = {1.f, 1.f, 1.f};
-  if (PHASE == 2) cb_gains(fd, gain, s_red);
+  WbConsts wbc;
+  if (PHASE == 2) {
+    if (wb) wbc = wb_points(fd, s_wtmp, s_wpts);
+    else cb_gains(fd, gain, s_red);
+  }
+  if (PHASE == 1 && wb) {
+    wb_hist_zero(s_wbh);
+    __syncthreads();
+  }
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
 
   constexpr int NG = 2;
@@ -1664,7 +1754,11 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       if (PHASE == 3) {
         acc[0] += luma_fixed(J);
       } else if (PHASE == 1) {
-        acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+        if (wb) {
+          wb_hist_add(s_wbh, Jg);
+        } else {
+          acc[0] += cb_fixed(Jg[0]); acc[1] += cb_fixed(Jg[1]); acc[2] += cb_fixed(Jg[2]);
+        }
       } else {
         const int64_t pi = (int64_t)y * W + x0[q] + i;
         if (AUX && fd.t_out) fd.t_out[pi] = t;
@@ -1673,7 +1767,7 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float v = (PHASE == 2) ? fminf(255.0f, gain[c] * Jg[c]) : Jg[c];
+          const float v = (PHASE == 2) ? (wb ? wb_apply(wbc, c, Jg[c]) : fminf(255.0f, gain[c] * Jg[c])) : Jg[c];
           const int byte = 3 * i + c;
           ow[byte >> 2] |= rne_u8(v) << (8 * (byte & 3));
         }
@@ -1697,7 +1791,10 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       }
     }
   }
-  if (PHASE == 1) cb_accumulate(fd, tile, acc, s_red);
+  if (PHASE == 1) {
+    if (wb) wb_hist_merge(fd, tile, s_wbh);
+    else cb_accumulate(fd, tile, acc, s_red);
+  }
   if (PHASE == 3) luma_accumulate(fd, tile, acc[0], s_red);
 }
 

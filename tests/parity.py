@@ -33,10 +33,11 @@ RTOL_FP16 = 1e-3
 def oracle_params(p: hzd.Params) -> oracle.Params:
     return oracle.Params(mode="offline" if p.mode == hzd.MODE_OFFLINE else "realtime", patch=p.patch,
                          omega=p.omega, t0=p.t0, top_frac=p.top_frac, alpha=p.alpha, gamma=p.gamma,
-                         gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=bool(p.color_balance),
+                         gf_radius=p.gf_radius, gf_eps=p.gf_eps, color_balance=int(p.color_balance),
                          tx="he" if p.tx == hzd.TX_HE else "paper", resize_width=p.resize_width,
                          resize_height=p.resize_height, airlight_smoothing=p.airlight_smoothing,
-                         gamma_adaptive=bool(p.gamma_adaptive), gamma_target=p.gamma_target)
+                         gamma_adaptive=bool(p.gamma_adaptive), gamma_target=p.gamma_target,
+                         wb_percentile=p.wb_percentile)
 
 
 def to_dev(I: np.ndarray, pitch_pad: int = 0) -> torch.Tensor:
@@ -121,6 +122,25 @@ def compare(I: np.ndarray, p: hzd.Params, g: dict, ref=None, label: str = "") ->
         stats["J_abs_max"] = float(J_err.max())
         stats["J_rel_scaled_max"] = float((J_err / np.maximum(scale, 1e-12)).max())   # scale is 0 on black frames
     d = np.abs(g["out"].astype(np.int32) - ref.out.astype(np.int32))
+    if p.color_balance == 2:
+        # Percentile white balance: each channel's black and white points are integer
+        # decisions on the codes of J_gamma.  The oracle lists the points each channel
+        # can take when values within its rounding margin of a half code round either
+        # way (almost always one); the channel must match the oracle's stretch for one
+        # of them.  The expected outputs all come from the oracle.
+        stats["wb_points"] = [list(pt) for pt in a["wb_points"]]
+        ambiguous = 0
+        for c in range(3):
+            (lo_a, lo_b), (hi_a, hi_b) = a["wb_candidates"][c]
+            best = None
+            for lo in range(lo_a, lo_b + 1):
+                for hi in range(hi_a, hi_b + 1):
+                    want = oracle.rne_u8(oracle.stretch_channel(a["Jg"][..., c], lo, hi))
+                    dc = np.abs(g["out"][..., c].astype(np.int32) - want.astype(np.int32))
+                    best = dc if best is None or dc.max() < best.max() else best
+            ambiguous += (lo_b - lo_a) + (hi_b - hi_a)
+            d[..., c] = best
+        stats["wb_ambiguous_points"] = ambiguous
     if fp16_map:
         bound = fp16_output_bound(I, p, a, rtol)
         worst = (d / bound).max()

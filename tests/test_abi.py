@@ -31,11 +31,11 @@ def test_library_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(hzd.SYMBOLS), "binding and header disagree"
-    assert L.hzd_abi_version() == hzd.ABI_VERSION == 3
+    assert L.hzd_abi_version() == hzd.ABI_VERSION == 4
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(hzd.hzd_params) == 4 * 18
+    assert ctypes.sizeof(hzd.hzd_params) == 4 * 19
     assert ctypes.sizeof(hzd.hzd_frame) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(hzd.hzd_frame_aux) == 5 * 8
 
@@ -71,7 +71,8 @@ def call_frame(L, p: hzd.Params, w=64, h=48, src=FAKE_SRC, dst=FAKE_DST, sp=None
     ("t0", 0.0, hzd.HZD_E_INVAL), ("t0", 1.5, hzd.HZD_E_INVAL), ("top_frac", 0.0, hzd.HZD_E_INVAL),
     ("top_frac", 1.01, hzd.HZD_E_INVAL), ("alpha", 0.0, hzd.HZD_E_INVAL), ("gamma", 0.0, hzd.HZD_E_INVAL),
     ("mode", 3, hzd.HZD_E_INVAL), ("tx", 2, hzd.HZD_E_INVAL), ("precision", 5, hzd.HZD_E_INVAL),
-    ("color_balance", 2, hzd.HZD_E_INVAL),
+    ("color_balance", 3, hzd.HZD_E_INVAL),
+    ("color_balance", -1, hzd.HZD_E_INVAL),
 ])
 def test_param_validation(L, field, value, status):
     p = hzd.Params()
@@ -104,6 +105,18 @@ def test_frame_validation(L):
     assert L.hzd_dehaze_frame(None, None, None, None, 0, None) == hzd.HZD_E_INVAL
     pc = p.c()
     assert L.hzd_dehaze_batch(ctypes.byref(pc), None, 0, None, None, 0, None) == hzd.HZD_E_INVAL
+
+
+def test_percentile_balance_validation(L):
+    assert call_frame(L, hzd.Params(color_balance=2, wb_percentile=0.5)) == hzd.HZD_E_INVAL
+    assert call_frame(L, hzd.Params(color_balance=2, wb_percentile=-0.01)) == hzd.HZD_E_INVAL
+    # offline with a binary16 t map would move the codes the percentiles are taken on
+    assert call_frame(L, hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=2,
+                                    precision=hzd.PREC_FP16)) == hzd.HZD_E_UNSUPPORTED
+    assert "FP32" in hzd.last_error()
+    # the percentile range is checked only when the balance uses it
+    assert call_frame(L, hzd.Params(color_balance=1, wb_percentile=0.9), ws_bytes=10) == hzd.HZD_E_NOMEM
+    assert hzd.Params.preset(hzd.PRESET_REALTIME).wb_percentile == pytest.approx(0.02)
 
 
 def test_noalloc_rejects_before_device_work(L):
