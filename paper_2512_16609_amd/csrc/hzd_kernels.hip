@@ -277,29 +277,59 @@ __global__ __launch_bounds__(256) void k_resize(ResizeBatch rb) {
 }
 
 // ------------------------------------------------------------------ k_dark
-// One 64x32 output tile per block.  The (64+2h) x (32+2h) region is staged in
-// LDS as two planes of packed 16-bit pairs: (R | B << 16) and (G | 255 << 16),
-// so each v_pk_min_u16 handles two channels.  Out-of-frame cells hold 255 (a
+// One 64x32 output tile per block.  The (64+2h) x (32+2h) region goes to LDS
+// as two planes of packed 16-bit pairs, (R | B << 16) and (G | 255 << 16), so
+// each v_pk_min_u16 handles two channels; out-of-frame cells hold 255 (a
 // clipped window).  Vertical van Herk per column segment, then horizontal van
-// Herk per row segment, both in registers.  One LDS buffer serves as the byte
-// stage, the two planes and, in place, the vertical-pass output (each step
-// reads into registers, then a barrier, then writes), so that 5 blocks fit
-// on a CU at h = 7 (30.1 KB) and a 1080p frame's tiles run in one round.
+// Herk per row segment, both in registers.
+//
+// The region is read as groups of 4 consecutive cells of one row: 12 bytes
+// of the frame, covered by 3 or 4 aligned dwords (an aligned dword that holds
+// a byte of the row lies in the same page as that byte), shifted into place
+// with alignbyte and split into the two planes with one v_perm_b32 per plane
+// and pixel.  Groups that touch the frame border take a per-cell path.  The
+// outputs are packed with v_perm_b32 as well: per pixel [R, G, B, 0], then 4
+// pixels into 3 dwords of E.
+namespace dk {
+typedef __attribute__((address_space(1))) const uint32_t gu32;   // global memory: global_load, not flat
+
+// v_perm_b32(hi, lo, sel): result byte i = byte sel[i] of the pair {hi, lo}
+// (0-3 from lo, 4-7 from hi), 0x0C gives 0x00 and 0x0D gives 0xFF.
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+// bytes b = R0 G0 B0 R1 | G1 B1 R2 G2 | B2 R3 G3 B3 -> the planes of 4 cells
+__device__ __forceinline__ void split4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t rb[4], uint32_t g[4]) {
+  rb[0] = perm(b0, b0, 0x0C020C00u);  // R0 | B0 << 16
+  g[0] = perm(b0, b0, 0x0C0D0C01u);   // G0 | FF << 16
+  rb[1] = perm(b1, b0, 0x0C050C03u);  // R1 (b0.3) | B1 (b1.1) << 16
+  g[1] = perm(b1, b0, 0x0C0D0C04u);   // G1 (b1.0)
+  rb[2] = perm(b2, b1, 0x0C040C02u);  // R2 (b1.2) | B2 (b2.0) << 16
+  g[2] = perm(b2, b1, 0x0C0D0C03u);   // G2 (b1.3)
+  rb[3] = perm(b2, b2, 0x0C030C01u);  // R3 (b2.1) | B3 (b2.3) << 16
+  g[3] = perm(b2, b2, 0x0C0D0C02u);   // G3 (b2.2)
+}
+}  // namespace dk
+
 template <int HP, bool WRITE_E>
 __global__ __launch_bounds__(256) void k_dark(Batch b) {
   constexpr int TW = kDarkTW, TH = kDarkTH;
   constexpr int RW = TW + 2 * HP, RH = TH + 2 * HP, WIN = 2 * HP + 1;
-  // plane rows are RWP = RW + 1 dwords apart (an odd stride), so the 32
+  // plane rows are RWP = RW | 1 dwords apart (an odd stride), so the 32
   // lanes of a half-wave in the horizontal pass (8 rows x 4 segments 8
   // columns apart) read 32 distinct banks
   constexpr int RWP = RW | 1;
-  constexpr int SROW = (3 * RW + 3) / 4 + 2;   // dwords of one staged region row (+ slack)
-  __shared__ uint32_t s_pl[2][RH][RWP];
+  constexpr int GPR = (RW + 3) / 4;            // 4-cell groups per region row
+  // The staged region uses rows of RWA = RW rounded up to 4 dwords, so that
+  // a group's 4 cells go to LDS as one 16-byte write; the vertical pass
+  // writes its output rows in place with the odd stride RWP, which the
+  // horizontal pass reads (all its inputs are in registers by then).
+  constexpr int RWA = (RW + 3) & ~3;
+  constexpr int PLN = ((RH * RWA > TH * RWP ? RH * RWA : TH * RWP) + 3) & ~3;   // dwords per plane
+  __shared__ __align__(16) uint32_t s_pl[2][PLN];
   __shared__ uint32_t s_hist[256];
-  static_assert(RH * SROW <= 2 * RH * RWP, "byte stage does not fit");
-  uint32_t(&s_rb)[RH][RWP] = s_pl[0];
-  uint32_t(&s_g)[RH][RWP] = s_pl[1];
-  uint32_t* s_stage = &s_pl[0][0][0];
+  uint32_t(&s_rb)[TH][RWP] = *reinterpret_cast<uint32_t(*)[TH][RWP]>(&s_pl[0][0]);
+  uint32_t(&s_g)[TH][RWP] = *reinterpret_cast<uint32_t(*)[TH][RWP]>(&s_pl[1][0]);
 
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
@@ -309,63 +339,68 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   const int tiles_x = (W + TW - 1) / TW;
   const int x0 = (tile % tiles_x) * TW, y0 = (tile / tiles_x) * TH;
   const int tid = threadIdx.x;
-  const int xs = max(x0 - HP, 0), xe = min(x0 + TW + HP, W);
 
-  // stage each in-frame region row's bytes [3 xs, 3 xe) with aligned dword
-  // loads (a dword holding at least one byte of the row never crosses a page)
   s_hist[tid] = 0u;
   {
-    // every load of the block is issued before any LDS write waits on one
-    constexpr int NL = (RH * SROW + 255) / 256;
-    uint32_t v[NL];
+    // thread t < GPR * RPI takes group column gi = t % GPR of region rows
+    // t / GPR, t / GPR + RPI, ...: its column, bounds and LDS offsets stay
+    // fixed and its row address advances by RPI pitches; every load of the
+    // block is issued before any cell is formed
+    constexpr int RPI = 256 / GPR;                 // region rows per iteration
+    constexpr int NIT = (RH + RPI - 1) / RPI;
+    const bool act = tid < GPR * RPI;
+    const int gi = tid % GPR, r_off = tid / GPR;
+    const int xa = x0 - HP + 4 * gi;
+    const bool colin = act && xa >= 0 && xa + 3 < W;   // all 4 cells inside the frame's columns
+    const int64_t step = (int64_t)RPI * fd.src_pitch;
+    const uint8_t* rowp = fd.src + (int64_t)(y0 - HP + r_off) * fd.src_pitch + 3 * xa;
+    // Loads are unconditional, so that none is waited for before its use (a
+    // group not wholly inside the frame reads the dword that holds the
+    // frame's first byte, four times, and is redone per cell below).
+    uint32_t w[NIT][4], sh[NIT];
+    bool ok[NIT];
+    const uint8_t* rp = rowp;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int i = tid + 256 * k;
-      const int rr = i / SROW, j = i - rr * SROW;
-      const int y = y0 - HP + rr;
-      v[k] = 0u;
-      if (i < RH * SROW && y >= 0 && y < H) {
-        const uintptr_t addr = (uintptr_t)(fd.src + (int64_t)y * fd.src_pitch + 3 * xs);
-        const uintptr_t a0 = addr & ~(uintptr_t)3;
-        const int nd = (int)((addr + 3 * (xe - xs) - a0 + 3) >> 2);
-        if (j < nd) v[k] = *reinterpret_cast<const uint32_t*>(a0 + 4 * (uintptr_t)j);
+    for (int k = 0; k < NIT; ++k) {
+      const int rr = r_off + RPI * k, y = y0 - HP + rr;
+      ok[k] = colin && rr < RH && y >= 0 && y < H;
+      const uintptr_t a = ok[k] ? (uintptr_t)rp : (uintptr_t)fd.src;
+      rp += step;
+      const uintptr_t a0 = a & ~(uintptr_t)3;
+      sh[k] = (uint32_t)(a & 3);
+      const uintptr_t o = ok[k] ? 4 : 0;
+      const dk::gu32* q = reinterpret_cast<const dk::gu32*>(a0);
+      w[k][0] = q[0];
+      w[k][1] = *reinterpret_cast<const dk::gu32*>(a0 + o);
+      w[k][2] = *reinterpret_cast<const dk::gu32*>(a0 + 2 * o);
+      // the 4th dword only when the 12 bytes reach into it (it then holds byte a + 11)
+      w[k][3] = *reinterpret_cast<const dk::gu32*>(a0 + (sh[k] ? 3 * o : 2 * o));
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int rr = r_off + RPI * k, y = y0 - HP + rr;
+      // the cells from the loaded bytes, formed unconditionally (the loads stay
+      // ahead of this loop); groups not wholly inside the frame redo them per cell
+      uint32_t rb[4], g[4];
+      dk::split4(__builtin_amdgcn_alignbyte(w[k][1], w[k][0], sh[k]), __builtin_amdgcn_alignbyte(w[k][2], w[k][1], sh[k]),
+                 __builtin_amdgcn_alignbyte(w[k][3], w[k][2], sh[k]), rb, g);
+      if (!act || rr >= RH) continue;
+      if (!ok[k]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int x = xa + j;
+          rb[j] = 0x00FF00FFu;
+          g[j] = 0x00FF00FFu;
+          if (y >= 0 && y < H && x >= 0 && x < W) {
+            const uint8_t* p = fd.src + (int64_t)y * fd.src_pitch + 3 * (int64_t)x;
+            rb[j] = (uint32_t)p[0] | ((uint32_t)p[2] << 16);
+            g[j] = (uint32_t)p[1] | 0x00FF0000u;
+          }
+        }
       }
-    }
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int i = tid + 256 * k;
-      if (i < RH * SROW) s_stage[i] = v[k];
-    }
-  }
-  __syncthreads();
-  // unpack into two planes of 16-bit pairs; out-of-frame cells hold 255
-  uint32_t rbv[(RH * RW + 255) / 256], gv[(RH * RW + 255) / 256];
-#pragma unroll
-  for (int k = 0; k < (RH * RW + 255) / 256; ++k) {
-    const int i = tid + 256 * k;
-    rbv[k] = 0x00FF00FFu;
-    gv[k] = 0x00FF00FFu;
-    if (i < RH * RW) {
-      const int rr = i / RW, cc = i - rr * RW;
-      const int y = y0 - HP + rr, x = x0 - HP + cc;
-      if (y >= 0 && y < H && x >= xs && x < xe) {
-        const uintptr_t addr = (uintptr_t)(fd.src + (int64_t)y * fd.src_pitch + 3 * xs);
-        const int off = (int)(addr & 3) + 3 * (x - xs);
-        const uint32_t w0 = s_stage[rr * SROW + (off >> 2)], w1 = s_stage[rr * SROW + (off >> 2) + 1];
-        const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(off & 3));
-        rbv[k] = (v & 0xFFu) | ((v & 0x00FF0000u));
-        gv[k] = ((v >> 8) & 0xFFu) | 0x00FF0000u;
-      }
-    }
-  }
-  __syncthreads();  // the planes overwrite the byte stage
-#pragma unroll
-  for (int k = 0; k < (RH * RW + 255) / 256; ++k) {
-    const int i = tid + 256 * k;
-    if (i < RH * RW) {
-      const int rr = i / RW, cc = i - rr * RW;
-      s_rb[rr][cc] = rbv[k];
-      s_g[rr][cc] = gv[k];
+      // cells beyond RW land in the row's padding (RWA >= 4 GPR)
+      *reinterpret_cast<uint4*>(&s_pl[0][rr * RWA + 4 * gi]) = make_uint4(rb[0], rb[1], rb[2], rb[3]);
+      *reinterpret_cast<uint4*>(&s_pl[1][rr * RWA + 4 * gi]) = make_uint4(g[0], g[1], g[2], g[3]);
     }
   }
   __syncthreads();
@@ -382,8 +417,8 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
       uint32_t vrb[L], vg[L];
 #pragma unroll
       for (int i = 0; i < L; ++i) {
-        vrb[i] = s_rb[r0 + i][cc];
-        vg[i] = s_g[r0 + i][cc];
+        vrb[i] = s_pl[0][(r0 + i) * RWA + cc];
+        vg[i] = s_pl[1][(r0 + i) * RWA + cc];
       }
       sliding_min<L, WIN, SEG>(vrb, orb);
       sliding_min<L, WIN, SEG>(vg, og);
@@ -415,36 +450,32 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
     const int y = y0 + r, xb = x0 + c0;
     if (y < H && xb < W) {
       const int nx = min(HS, W - xb);
-      uint32_t d[HS];
-      uint64_t dpack = 0, e0 = 0, e1 = 0, e2 = 0;
+      uint32_t px[HS], d[HS];
 #pragma unroll
       for (int i = 0; i < HS; ++i) {
-        const uint32_t er = orb[i] & 0xFFu, eb = (orb[i] >> 16) & 0xFFu, eg = og[i] & 0xFFu;
-        d[i] = min(min(er, eg), eb);
-        dpack |= (uint64_t)d[i] << (8 * i);
-        const uint64_t rgb = (uint64_t)(er | (eg << 8) | (eb << 16));
-        const int bit = 24 * i;  // 8 pixels x 24 bits = 192 bits in e0|e1|e2
-        if (bit < 64) e0 |= rgb << bit;
-        if (bit + 24 > 64 && bit < 128) e1 |= (bit >= 64) ? rgb << (bit - 64) : rgb >> (64 - bit);
-        if (bit + 24 > 128) e2 |= (bit >= 128) ? rgb << (bit - 128) : rgb >> (128 - bit);
+        px[i] = dk::perm(og[i], orb[i], 0x0C020400u);   // [E^R, E^G, E^B, 0]
+        const uint32_t m = pkmin(orb[i], og[i]);         // (min(R, G), min(B, 255))
+        d[i] = min(m & 0xFFFFu, m >> 16);
       }
       uint8_t* Drow = fd.D + (int64_t)y * fd.D_pitch + xb;
       uint8_t* Erow = fd.E + (int64_t)y * fd.E_pitch + 3 * xb;
       if (nx == HS) {
-        *reinterpret_cast<uint64_t*>(Drow) = dpack;
+        const uint32_t dlo = d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24);
+        const uint32_t dhi = d[4] | (d[5] << 8) | (d[6] << 16) | (d[7] << 24);
+        *reinterpret_cast<uint2*>(Drow) = make_uint2(dlo, dhi);
         if (WRITE_E) {
-          uint64_t* e = reinterpret_cast<uint64_t*>(Erow);
-          e[0] = e0;
-          e[1] = e1;
-          e[2] = e2;
+          uint2* e = reinterpret_cast<uint2*>(Erow);
+          e[0] = make_uint2(dk::perm(px[1], px[0], 0x04020100u), dk::perm(px[2], px[1], 0x05040201u));
+          e[1] = make_uint2(dk::perm(px[3], px[2], 0x06050402u), dk::perm(px[5], px[4], 0x04020100u));
+          e[2] = make_uint2(dk::perm(px[6], px[5], 0x05040201u), dk::perm(px[7], px[6], 0x06050402u));
         }
       } else {
         for (int i = 0; i < nx; ++i) {
           Drow[i] = (uint8_t)d[i];
           if (WRITE_E) {
-            Erow[3 * i + 0] = (uint8_t)(orb[i] & 0xFFu);
-            Erow[3 * i + 1] = (uint8_t)(og[i] & 0xFFu);
-            Erow[3 * i + 2] = (uint8_t)((orb[i] >> 16) & 0xFFu);
+            Erow[3 * i + 0] = (uint8_t)(px[i] & 0xFFu);
+            Erow[3 * i + 1] = (uint8_t)((px[i] >> 8) & 0xFFu);
+            Erow[3 * i + 2] = (uint8_t)((px[i] >> 16) & 0xFFu);
           }
         }
       }
@@ -454,13 +485,20 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
       }
       // histogram with run-length aggregation (D is locally smooth)
       uint32_t cur = d[0], cnt = 1;
-      for (int i = 1; i < nx; ++i) {
-        if (d[i] == cur) {
-          ++cnt;
-        } else {
-          atomicAdd(&s_hist[cur], cnt);
+      if (nx == HS) {
+#pragma unroll
+        for (int i = 1; i < HS; ++i) {
+          const bool same = d[i] == cur;
+          if (!same) atomicAdd(&s_hist[cur], cnt);
+          cnt = same ? cnt + 1 : 1;
           cur = d[i];
-          cnt = 1;
+        }
+      } else {
+        for (int i = 1; i < nx; ++i) {
+          const bool same = d[i] == cur;
+          if (!same) atomicAdd(&s_hist[cur], cnt);
+          cnt = same ? cnt + 1 : 1;
+          cur = d[i];
         }
       }
       atomicAdd(&s_hist[cur], cnt);
