@@ -1060,6 +1060,7 @@ __device__ __forceinline__ GfTile gf_tile(const FrameDev& fd, int tile) {
 }
 
 constexpr int kRpi = 4;          // rows per barrier phase in the guided-filter strip kernels
+static_assert(kRpi == 4, "one wave of the 256-thread block per row of a phase");
 static_assert(kGfRowsMax <= 256, "per-row table filled by one pass of the block's threads");
 
 // Per output row of the block: the clipped window height ch and 1/ch (one
@@ -1267,18 +1268,18 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
 
-  // output items of this thread in a phase: item i = tid + 256 j is row
-  // i / SW, column i % SW of the phase (SW = 64 NI), so every wave gets the
-  // same share of the FP64 work
+  // output items of this thread in a phase: wave w owns row w of the phase,
+  // lane l its columns l + 64 j (SW = 64 NI), so a wave's items read only the
+  // scans it made itself (no barrier between scan and items) and every wave
+  // gets the same share of the FP64 work
   constexpr int SWc = 64 * NI;
-  int iu[NI], ic[NI], iclo[NI], ichi[NI];
+  const int lane = tid & 63;
+  int ic[NI], iclo[NI], ichi[NI];
   double icw[NI], cwd[NI];
   bool iok[NI];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    const int i = tid + 256 * j;
-    iu[j] = i / SWc;
-    ic[j] = i - iu[j] * SWc;
+    ic[j] = lane + 64 * j;
     const int x = g.x0 + ic[j];
     iok[j] = x < W;
     const int lo = max(x - r, 0), hi = min(x + r, W - 1);
@@ -1309,11 +1310,12 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
       s_q[u][3][qt] = sLP;
     }
     __syncthreads();
-    wave_prefix256_rows<unsigned long long, kRpi>(&s_q[0][wv][0], 4 * kGfCols);
-    __syncthreads();
+    // wave wv prefix-sums the four quantities of row wv (independent DPP scans)
+    wave_prefix256_rows<unsigned long long, 4>(&s_q[wv][0][0], kGfCols);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      const int u = iu[j], y = yb + u;
+      const int u = wv, y = yb + u;
       if (iok[j] && y < g.y1) {
         const int clo = iclo[j], chi = qsw(ichi[j]), cl = qsw(max(clo - 1, 0));
         // box sums as differences of two prefixes; S_L < 2^32, so 32-bit wrap-around is exact
@@ -1502,9 +1504,10 @@ __device__ __forceinline__ void adaptive_gamma(const FrameDev& fd, ReconConsts& 
 template <int NI, int PHASE, bool FP16, bool AUX>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   // two buffers, alternating by phase: a phase's scan and output read one
-  // while the next phase's column sums go to the other, so a phase needs no
-  // closing barrier (a buffer is rewritten two phases later, after every wave
-  // has passed the next phase's first barrier and so finished this output)
+  // while the next phase's column sums go to the other, so a phase needs only
+  // the barrier after its column sums (a buffer is rewritten two phases
+  // later, after every wave has passed the next phase's barrier and so
+  // finished this output; each wave scans and reads only its own row)
   __shared__ long long s_q[2][kRpi][2][kGfCols];
   __shared__ double2 s_rows[kGfRowsMax];
   __shared__ unsigned long long s_red[4];
@@ -1563,18 +1566,17 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   };
   auto enters = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn + r < H; };
   auto leaves = [&](int yn) { return yn > g.y0 && yn < g.y1 && yn - r - 1 >= 0; };
-  // output items of this thread in a phase: item i = tid + 256 j is row
-  // i / SW, column i % SW of the phase (SW = 64 NI)
-  constexpr int SWc = 64 * NI;
-  int iu[NI], ic[NI], iclo[NI], ichi[NI], ixc[NI];
+  // output items of this thread in a phase: wave w owns row w of the phase,
+  // lane l its columns l + 64 j (SW = 64 NI); a wave's items read only the
+  // scans it made itself
+  const int lane = tid & 63;
+  int ic[NI], iclo[NI], ichi[NI], ixc[NI];
   double icw_s[NI];
   bool iok[NI];
   const double inv_s = (double)fd.ab_inv_scale;
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    const int i = tid + 256 * j;
-    iu[j] = i / SWc;
-    ic[j] = i - iu[j] * SWc;
+    ic[j] = lane + 64 * j;
     const int x = g.x0 + ic[j];
     iok[j] = x < W;
     ixc[j] = min(x, W - 1);
@@ -1599,7 +1601,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
 #pragma unroll
-  for (int j = 0; j < NI; ++j) fetch_px(g.y0 + iu[j], ixc[j], pRG[j], pB[j]);
+  for (int j = 0; j < NI; ++j) fetch_px(g.y0 + wv, ixc[j], pRG[j], pB[j]);
 
   const double t0 = (double)fd.t0;
   unsigned long long acc[3] = {0ull, 0ull, 0ull};
@@ -1624,15 +1626,15 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     for (int j = 0; j < NI; ++j) {
       curRG[j] = pRG[j];
       curB[j] = pB[j];
-      fetch_px(yb + kRpi + iu[j], ixc[j], pRG[j], pB[j]);
+      fetch_px(yb + kRpi + wv, ixc[j], pRG[j], pB[j]);
     }
     __syncthreads();
-    // 2 quantities x kRpi rows of scans over the 4 waves
-    wave_prefix256_rows<long long, kRpi / 2>(&q[wv >> 1][wv & 1][0], 2 * 2 * kGfCols);
-    __syncthreads();
+    // wave wv prefix-sums the two quantities of row wv
+    wave_prefix256_rows<long long, 2>(&q[wv][0][0], kGfCols);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      const int u = iu[j], y = yb + u;
+      const int u = wv, y = yb + u;
       if (iok[j] && y < g.y1) {
         const int clo = iclo[j], chi = qsw(ichi[j]), cl = qsw(max(clo - 1, 0)), x = g.x0 + ic[j];
         const double qa = i64_to_f64(q[u][0][chi] - (clo > 0 ? q[u][0][cl] : 0ll));
