@@ -62,13 +62,25 @@ typedef enum { HZD_MODE_REALTIME = 0, HZD_MODE_OFFLINE = 1 } hzd_mode;
  *                pointwise expression printed as Eq. (4). */
 typedef enum { HZD_TX_HE = 0, HZD_TX_PAPER = 1 } hzd_tx;
 
-/* Precision of the stored transmission map.  The only floating-point map
- * that crosses memory is the refined t of offline mode with colour balance
- * (between the guided filter and the balanced reconstruction).  FP16 stores
- * it as binary16, halving its traffic, and the colour-balance sums use the
- * same rounded values.  Everywhere else t never leaves registers and is
- * binary32 with either setting.  J and the gamma of Eq. (8) are always formed
- * in binary32. */
+/* Precision of the stored transmission map, and the output bound of each.
+ * The only floating-point map that crosses memory is the refined t of offline
+ * mode with a balance (color_balance 1) or the adaptive gamma, between the
+ * guided filter and the reconstruction that needs the frame-wide sums.  J and
+ * the gamma of Eq. (8) are always formed in binary32.
+ *   HZD_PREC_FP32  t binary32 everywhere.  Output within 1 LSB of the FP64
+ *                  reading of the method in every mode; t within 1e-5
+ *                  relative.
+ *   HZD_PREC_FP16  that map is stored as binary16 (half its traffic; the sums
+ *                  use the same rounded values); everywhere else t never
+ *                  leaves registers, so the results equal FP32's bit for bit.
+ *                  For the stored map t is within 1e-3 relative, and the
+ *                  output within the bound that the binary16 rounding
+ *                  (2^-11 relative) implies through Eqs. (7)-(8) and the
+ *                  gains: 1 LSB on the test frames for gamma <= 1.2 (the
+ *                  default), up to 2 LSB at gamma 1.8, 4 at 2.2 and 12 at 3.0,
+ *                  the error concentrating next to black, where Eq. (8) is
+ *                  steepest.  Offline percentile white balance (color_balance
+ *                  2) is refused at FP16 (HZD_E_UNSUPPORTED). */
 typedef enum { HZD_PREC_FP32 = 0, HZD_PREC_FP16 = 1 } hzd_prec;
 
 typedef enum {
@@ -90,7 +102,13 @@ typedef enum {
  *   gamma          gamma of Eq. (8), [0.1, 10]
  *   gf_radius      guided-filter box radius r (OFFLINE), 1..64
  *   gf_eps         guided-filter regulariser (OFFLINE), [1e-8, 1]; the guide is
- *                  the BT.601 luma of the hazy input scaled to [0, 1]
+ *                  the BT.601 luma of the hazy input scaled to [0, 1].  The
+ *                  filter's a and b are kept in fixed point between its two
+ *                  stages: int32 with k = floor(log2((2^31 - 1) / B))
+ *                  fractional bits, B = 1 + 1 / (4 sqrt(gf_eps)), while 2^-k
+ *                  <= 1e-6 t0, else int64 (workspace 16 instead of 8 bytes
+ *                  per pixel for that map), so the rounding moves t by at
+ *                  most a tenth of its tolerance
  *   color_balance  the balance stage of Sec. IV-E, on the gamma-corrected image:
  *                  0 = none; 1 = gray-world gains g_c = mean(mu) / mu_c, where
  *                  mu_c is the channel mean (1 when mu_c = 0), clamped to 255;

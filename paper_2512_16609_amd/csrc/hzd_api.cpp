@@ -123,6 +123,18 @@ int validate_frame(const hzd_frame* f, const hzd_params& p, int idx) {
 static size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 static int a16(int v) { return (v + 15) & ~15; }
 
+AbFixed ab_fixed_point(float eps, float t0, int radius) {
+  const double B = 1.0 + 0.25 / std::sqrt((double)eps);
+  AbFixed f;
+  f.bits = std::min(30, (int)std::floor(std::log2(2147483647.0 / B)));
+  f.wide = std::ldexp(1.0, -f.bits) > 1e-6 * (double)t0;
+  if (f.wide) {
+    const double n = (2.0 * radius + 1.0) * (2.0 * radius + 1.0);
+    f.bits = std::min(52, (int)std::floor(std::log2(9.2e18 / (B * n))));
+  }
+  return f;
+}
+
 GroupKey group_key(const hzd_params& p) {
   GroupKey g;
   g.mode = p.mode;
@@ -133,6 +145,7 @@ GroupKey group_key(const hzd_params& p) {
   g.radius = p.mode == HZD_MODE_OFFLINE ? p.gf_radius : 0;
   g.resize = p.resize_width != 0;
   g.gadapt = p.gamma_adaptive;
+  g.ab64 = p.mode == HZD_MODE_OFFLINE ? (int)ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).wide : 0;
   return g;
 }
 
@@ -153,7 +166,7 @@ size_t frame_ws_bytes(const hzd_params& p, int Win, int Hin) {
   s += a256((size_t)H * sizeof(RowSel));               // per-row selection records
   if (offline) {
     s += a256((size_t)W * H * 8);                      // LP
-    s += a256((size_t)W * H * 8);                      // AB
+    s += a256((size_t)W * H * (ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).wide ? 16 : 8));   // AB
     const size_t nch = (size_t)((H + 7) / 8);
     s += a256(nch * W * 8) + a256(nch * W * 16) + a256(nch * W * 16);  // 8-row chunk sums
     if (p.color_balance || p.gamma_adaptive) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
@@ -319,8 +332,8 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   if (offline) {
     d.LP = reinterpret_cast<uint2*>(ws + off);
     off += a256((size_t)W * H * 8);
-    d.AB = reinterpret_cast<int2*>(ws + off);
-    off += a256((size_t)W * H * 8);
+    d.AB = ws + off;
+    off += a256((size_t)W * H * (ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).wide ? 16 : 8));
     const size_t nch = (size_t)((H + 7) / 8);
     d.S8a = reinterpret_cast<uint2*>(ws + off);
     off += a256(nch * W * 8);
@@ -352,9 +365,7 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
 
   d.eps = p.gf_eps;
   if (offline) {
-    // |a| <= 1 / (4 sqrt(eps)) for p in [0,1]; |b| <= 1 + |a|; scale 2^k keeps both in int32
-    const double B = 1.0 + 0.25 / std::sqrt((double)p.gf_eps);
-    const int k = std::min(30, (int)std::floor(std::log2(2147483647.0 / B)));
+    const int k = ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).bits;
     d.ab_scale = std::ldexp(1.0f, k);
     d.ab_inv_scale = std::ldexp(1.0f, -k);
   }

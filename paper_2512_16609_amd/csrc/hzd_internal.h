@@ -51,7 +51,7 @@ struct FrameDev {
   uint8_t* E;        // per-channel erosions (packed RGB8), pitch E_pitch
   RowSel* rowsel;    // per row: selection counts and sums (one record per row)
   uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
-  int2* AB;          // offline: guided-filter a, b in fixed point (pitch W)
+  void* AB;          // offline: guided-filter a, b in fixed point, int2 or longlong2 (GroupKey.ab64), pitch W
   uint2* S8a;        // offline: per column and aligned 8-row chunk, sums of {L, P}
   ulonglong2* S8b;   // offline: per column and chunk, sums of {L^2, L*P}
   longlong2* S8ab;   // offline: per column and chunk, sums of {a, b} (fixed point)
@@ -112,8 +112,23 @@ struct ResizeBatch {
 
 // Group-wide kernel switches (identical for all frames of one launch).
 struct GroupKey {
-  int32_t mode, half_patch, tx, cb, fp16, radius, resize, gadapt;
+  int32_t mode, half_patch, tx, cb, fp16, radius, resize, gadapt, ab64;
 };
+
+// Fixed-point storage of the guided filter's a and b (Eq. (6)): a value v is
+// kept as rint(v 2^k).  |a| <= 1 / (4 sqrt(eps)) for a guide and an input in
+// [0, 1], and |b| <= 1 + |a|, so with B = 1 + 1 / (4 sqrt(eps)) int32 holds
+// k = floor(log2((2^31 - 1) / B)) fractional bits.  The rounding moves the
+// refined t by at most 2^-k (the box means of a and b each by 2^-(k+1), and
+// the guide is at most 1).  That must stay far inside the 1e-5 relative
+// tolerance of t >= t0: int32 is used while 2^-k <= 1e-6 t0, otherwise int64
+// with k = floor(log2((2^63 - 1) / (B (2r+1)^2))), which keeps the stage-2 box
+// sums of up to (2r+1)^2 values inside int64 (ab_fixed_point).
+struct AbFixed {
+  bool wide;   // int64 storage
+  int bits;    // k
+};
+AbFixed ab_fixed_point(float eps, float t0, int radius);
 
 // Compute units of the current device (cached per device; 256 if the query fails).
 int device_cu_count();

@@ -1182,6 +1182,21 @@ __device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
   }
 }
 
+// Storage of the fixed-point a, b (see AbFixed): int32 pairs, or int64 pairs
+// when the int32 rounding would move t by more than 1e-6 t0.
+template <bool AB64> struct AbStore {
+  using V = int2;
+  using E = int;
+  static constexpr double lim = 2147483647.0;
+  __device__ static V make(double a, double b) { return make_int2((int)a, (int)b); }
+};
+template <> struct AbStore<true> {
+  using V = longlong2;
+  using E = long long;
+  static constexpr double lim = 4.0e18;
+  __device__ static V make(double a, double b) { return make_longlong2((long long)a, (long long)b); }
+};
+
 // Eq. (6), stage 1 (He et al. 2013 box form).  Each thread keeps exact u64
 // vertical window sums of L, L^2, P, L*P for its column, sliding down the
 // rows.  Rows are handled kRpi at a time: the window sums of kRpi rows go to
@@ -1193,8 +1208,9 @@ __device__ __forceinline__ void wave_prefix256_rows(T* base, int stride) {
 // and cov are formed in FP64; a and b leave as int32 fixed point with the
 // frame's scale, and their 8-row chunk sums per column (for stage 2's initial
 // windows) are merged in LDS.
-template <int NI>
+template <int NI, bool AB64>
 __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
+  using AB = AbStore<AB64>;
   __shared__ unsigned long long s_q[kRpi][4][kGfCols];
   __shared__ double2 s_rows[kGfRowsMax];
   __shared__ unsigned long long s_ch[2][64 * NI];  // a, b sums of each output column's current 8-row chunk
@@ -1295,7 +1311,7 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
   //   b = mean(t) - a mean(G) = (kP / n) (S_P - (a kG / kP) S_L)
   const double kG = 1.0 / 255000.0, kP = 1.0 / 268435456.0;
   const double eps_n = (double)fd.eps / (kG * kG);
-  const double s = (double)fd.ab_scale, lim = 2147483647.0;
+  const double s = (double)fd.ab_scale, lim = AB::lim;
   const double sa_k = s * kP / kG, sb_k = s * kP;
   for (int yb = g.y0; yb < g.y1; yb += kRpi) {
 #pragma unroll
@@ -1333,10 +1349,10 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
         const double ia = fmin(fmax(__builtin_rint(a2 * sa_k), -lim), lim);
         const double ib = fmin(fmax(__builtin_rint(fma(-a2, SL, SP) * (inv_n * sb_k)), -lim), lim);
         const int x = g.x0 + ic[j];
-        fd.AB[y * W + x] = make_int2((int)ia, (int)ib);
+        reinterpret_cast<typename AB::V*>(fd.AB)[(int64_t)y * W + x] = AB::make(ia, ib);
         // the column's sums of a, b over its aligned 8-row chunk (for stage 2's window)
-        atomicAdd(&s_ch[0][ic[j]], (unsigned long long)(long long)(int)ia);
-        atomicAdd(&s_ch[1][ic[j]], (unsigned long long)(long long)(int)ib);
+        atomicAdd(&s_ch[0][ic[j]], (unsigned long long)(long long)(typename AB::E)ia);
+        atomicAdd(&s_ch[1][ic[j]], (unsigned long long)(long long)(typename AB::E)ib);
       }
     }
     __syncthreads();
@@ -1501,8 +1517,9 @@ __device__ __forceinline__ void adaptive_gamma(const FrameDev& fd, ReconConsts& 
 // output.  PHASE 1: store the refined t and the colour-balance sums.  PHASE 2:
 // store the refined t and the luma sums of J (adaptive gamma).  AUX: some
 // frame of the launch asks for its t or J maps.
-template <int NI, int PHASE, bool FP16, bool AUX>
+template <int NI, int PHASE, bool FP16, bool AUX, bool AB64>
 __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
+  using ABV = typename AbStore<AB64>::V;
   // two buffers, alternating by phase: a phase's scan and output read one
   // while the next phase's column sums go to the other, so a phase needs only
   // the barrier after its column sums (a buffer is rewritten two phases
@@ -1521,7 +1538,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   const int tid = threadIdx.x, wv = tid >> 6;
   // this thread's column; threads outside the frame read the nearest edge
   // column, whose sums land in prefix entries no in-frame box uses
-  const int2* col = fd.AB + min(max(g.xl, 0), W - 1);
+  const ABV* col = reinterpret_cast<const ABV*>(fd.AB) + min(max(g.xl, 0), W - 1);
   gf_row_table(g, s_rows);
   const ReconConsts rc = recon_consts(fd);
   const bool wb = PHASE == 1 && (fd.flags & kFdWbPercentile);   // block-uniform
@@ -1533,12 +1550,12 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     // the rows outside whole chunks, head then tail, kEdgeBatch per round trip
     const int nhead = w.head_end - w.ya, nedge = nhead + (w.yb + 1 - w.tail_beg);
     for (int e0 = 0; e0 < nedge; e0 += kEdgeBatch) {
-      int2 ev[kEdgeBatch];
+      ABV ev[kEdgeBatch];
 #pragma unroll
       for (int i = 0; i < kEdgeBatch; ++i) {
         const int e = e0 + i;
         const int yr = e < nhead ? w.ya + e : w.tail_beg + (e - nhead);
-        ev[i] = (e < nedge) ? col[yr * W] : make_int2(0, 0);
+        ev[i] = (e < nedge) ? col[(int64_t)yr * W] : ABV{0, 0};
       }
 #pragma unroll
       for (int i = 0; i < kEdgeBatch; ++i) {
@@ -1560,7 +1577,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   }
   // unconditional loads (rows and columns clamped into the frame): the number
   // of loads in flight is static, so a prefetch is waited for only at its use
-  auto fetch = [&](int yn, int2& vin, int2& vout) {
+  auto fetch = [&](int yn, ABV& vin, ABV& vout) {
     vin = col[min(yn + r, H - 1) * W];  // offsets < W*H < 2^31
     vout = col[min(max(yn - r - 1, 0), H - 1) * W];
   };
@@ -1596,7 +1613,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
     rg = v;
     bl = p[2];
   };
-  int2 pin[kRpi], pout[kRpi];
+  ABV pin[kRpi], pout[kRpi];
   uint32_t pRG[NI], pB[NI];
 #pragma unroll
   for (int u = 0; u < kRpi; ++u) fetch(g.y0 + u, pin[u], pout[u]);
@@ -1867,22 +1884,26 @@ bool any_aux_maps(const Batch& b) {
   return false;
 }
 
-template <int NI, int PHASE>
+template <int NI, int PHASE, bool AB64>
 hipError_t gf_q_n(const Batch& b, int nblk, bool fp16, bool aux, hipStream_t s) {
   if (fp16) {
-    if (aux) hipLaunchKernelGGL((k_gf_q<NI, PHASE, true, true>), dim3(nblk), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_gf_q<NI, PHASE, true, false>), dim3(nblk), dim3(256), 0, s, b);
+    if (aux) hipLaunchKernelGGL((k_gf_q<NI, PHASE, true, true, AB64>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<NI, PHASE, true, false, AB64>), dim3(nblk), dim3(256), 0, s, b);
   } else {
-    if (aux) hipLaunchKernelGGL((k_gf_q<NI, PHASE, false, true>), dim3(nblk), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_gf_q<NI, PHASE, false, false>), dim3(nblk), dim3(256), 0, s, b);
+    if (aux) hipLaunchKernelGGL((k_gf_q<NI, PHASE, false, true, AB64>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_q<NI, PHASE, false, false, AB64>), dim3(nblk), dim3(256), 0, s, b);
   }
   return hipGetLastError();
 }
 
 template <int PHASE>
-hipError_t gf_q_p(const Batch& b, int nblk, int radius, bool fp16, bool aux, hipStream_t s) {
-  if (gf_strip(radius) == 192) return gf_q_n<3, PHASE>(b, nblk, fp16, aux, s);
-  return gf_q_n<2, PHASE>(b, nblk, fp16, aux, s);
+hipError_t gf_q_p(const Batch& b, int nblk, int radius, bool fp16, bool aux, bool ab64, hipStream_t s) {
+  if (ab64) {
+    if (gf_strip(radius) == 192) return gf_q_n<3, PHASE, true>(b, nblk, fp16, aux, s);
+    return gf_q_n<2, PHASE, true>(b, nblk, fp16, aux, s);
+  }
+  if (gf_strip(radius) == 192) return gf_q_n<3, PHASE, false>(b, nblk, fp16, aux, s);
+  return gf_q_n<2, PHASE, false>(b, nblk, fp16, aux, s);
 }
 
 }  // namespace
@@ -1943,17 +1964,22 @@ hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s) {
 
 hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
-  if (gf_strip(g.radius) == 192) hipLaunchKernelGGL(k_gf_ab<3>, dim3(nblk), dim3(256), 0, s, b);
-  else hipLaunchKernelGGL(k_gf_ab<2>, dim3(nblk), dim3(256), 0, s, b);
+  if (g.ab64) {
+    if (gf_strip(g.radius) == 192) hipLaunchKernelGGL((k_gf_ab<3, true>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_ab<2, true>), dim3(nblk), dim3(256), 0, s, b);
+  } else {
+    if (gf_strip(g.radius) == 192) hipLaunchKernelGGL((k_gf_ab<3, false>), dim3(nblk), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_gf_ab<2, false>), dim3(nblk), dim3(256), 0, s, b);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) { return gf_blocks(f.W, f.H, f.radius, f.gf_rows); });
   const bool aux = any_aux_maps(b);
-  if (g.gadapt) return gf_q_p<2>(b, nblk, g.radius, g.fp16, aux, s);
-  if (g.cb) return gf_q_p<1>(b, nblk, g.radius, g.fp16, aux, s);
-  return gf_q_p<0>(b, nblk, g.radius, g.fp16, aux, s);
+  if (g.gadapt) return gf_q_p<2>(b, nblk, g.radius, g.fp16, aux, g.ab64, s);
+  if (g.cb) return gf_q_p<1>(b, nblk, g.radius, g.fp16, aux, g.ab64, s);
+  return gf_q_p<0>(b, nblk, g.radius, g.fp16, aux, g.ab64, s);
 }
 
 namespace {

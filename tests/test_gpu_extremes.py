@@ -43,3 +43,29 @@ def test_largest_patch_and_radius_on_small_frames():
         I = np.random.default_rng(w).integers(0, 256, (h, w, 3), dtype=np.uint8)
         p = hzd.Params(mode=hzd.MODE_OFFLINE, patch=31, gf_radius=64, color_balance=1)
         compare(I, p, run_gpu(I, p), label=f"patch 31 r 64 {w}x{h}")
+
+
+@pytest.mark.parametrize("eps,t0", [(1e-8, 0.01), (1e-8, 0.1), (1e-5, 0.005), (1e-3, 0.002)])
+def test_small_eps_and_t0_take_the_int64_a_b(eps, t0):
+    """Where int32 a, b would move t by more than 1e-6 t0 the library stores them as
+    int64: a bright flat frame (t = t0 everywhere, b = t0) and a hazy frame stay within
+    the 1e-5 tolerance of the oracle's t."""
+    flat = np.full((60, 90, 3), 250, dtype=np.uint8)
+    for I in (flat, _frame(240, 160, 73)):
+        p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=20, gf_eps=eps, t0=t0, color_balance=1)
+        s = compare(I, p, run_gpu(I, p), label=f"eps {eps} t0 {t0}")
+        assert s["t_rel_max"] <= 2e-6, s
+
+
+def test_int64_a_b_do_not_depend_on_the_tile_height():
+    I = _frame(320, 200, 74)
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=25, gf_eps=1e-8, t0=0.01)
+    outs = []
+    for rows in (8, 24, 64):
+        hzd.tile_config_set(320, 200, rows)
+        try:
+            outs.append(run_gpu(I, p))
+        finally:
+            hzd.tile_config_set(320, 200, None)
+    for o in outs[1:]:
+        assert np.array_equal(o["out"], outs[0]["out"]) and np.array_equal(o["t"], outs[0]["t"])

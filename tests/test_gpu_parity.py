@@ -400,3 +400,24 @@ def test_random_large_frames(case):
     w, h = int(rng.integers(300, 1200)), int(rng.integers(200, 800))
     I = make_frame(w, h, 5100 + case, beta=float(rng.uniform(0.5, 2.0))).I
     compare(I, p, run_gpu(I, p), label=f"large {case} {w}x{h} {p}")
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.0, 1.2, 1.8, 2.2, 3.0])
+def test_fp16_t_map_output_bound_per_gamma(gamma):
+    """Offline mode with colour balance at FP16 precision stores the refined t as
+    binary16: the output is held to the bound derived from that rounding (asserted
+    element by element by compare), and the largest LSB difference is reported per
+    gamma.  FP32 on the same frames stays within 1 LSB."""
+    worst = 0
+    for (w, h, seed, dark) in [(640, 480, 80, 1.0), (640, 480, 81, 0.4), (320, 240, 82, 0.25)]:
+        I = make_frame(w, h, seed).I
+        if dark != 1.0:
+            I = (I * dark).astype(np.uint8)
+        for prec in (hzd.PREC_FP16, hzd.PREC_FP32):
+            p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1, gamma=gamma, precision=prec)
+            s = compare(I, p, run_gpu(I, p), label=f"gamma {gamma} prec {prec} {w}x{h} dark {dark}")
+            if prec == hzd.PREC_FP16:
+                worst = max(worst, s["lsb_max"])
+            else:
+                assert s["lsb_max"] <= 1
+    print(f"FP16 t map, gamma {gamma}: largest output difference {worst} LSB")
