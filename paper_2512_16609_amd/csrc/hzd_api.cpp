@@ -164,6 +164,7 @@ size_t frame_ws_bytes(const hzd_params& p, int Win, int Hin) {
   s += a256((size_t)H * a16(W));                       // D
   if (needE) s += a256((size_t)H * a16(3 * W));        // E
   s += a256((size_t)H * sizeof(RowSel));               // per-row selection records
+  if (select_one_fits(W, H)) s += a256((size_t)dark_tiles(W, H) * 256 * 2);   // per-tile histograms
   if (offline) {
     s += a256((size_t)W * H * 8);                      // LP
     s += a256((size_t)W * H * (ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).wide ? 16 : 8));   // AB
@@ -329,6 +330,10 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   }
   d.rowsel = reinterpret_cast<RowSel*>(ws + off);
   off += a256((size_t)H * sizeof(RowSel));
+  if (select_one_fits(W, H)) {
+    d.hpart = reinterpret_cast<uint16_t*>(ws + off);
+    off += a256((size_t)dark_tiles(W, H) * 256 * 2);
+  }
   if (offline) {
     d.LP = reinterpret_cast<uint2*>(ws + off);
     off += a256((size_t)W * H * 8);
@@ -367,7 +372,6 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
   if (offline) {
     const int k = ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).bits;
     d.ab_scale = std::ldexp(1.0f, k);
-    d.ab_inv_scale = std::ldexp(1.0f, -k);
   }
   d.gf_rows = tile_config_for(W, H).gf_rows;
   d.A_state = fr.airlight_state;
@@ -439,10 +443,22 @@ int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStrea
   // an empty event pair measures what bracketing itself costs
   if (prof) (void)stage(prof, "event_pair", s, [] { return hipSuccess; });
   if (g.resize && (rc = stage(prof, "resize", s, [&] { return launch_resize(*rz, s); })) != HZD_OK) return rc;
-  if ((rc = stage(prof, "init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
   const bool he = g.tx == HZD_TX_HE;
-  if ((rc = stage(prof, "dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
-  if ((rc = stage(prof, "select", s, [&] { return launch_select(b, s); })) != HZD_OK) return rc;
+  // Small frames take the one-block selection: it builds the histogram from D
+  // and zeroes the later passes' sums, so neither the init kernel nor the
+  // histogram atomics of k_dark are needed.
+  bool one = true;
+  for (int i = 0; i < b.n; ++i) one = one && select_one_fits(b.f[i].W, b.f[i].H);
+  if (one) {
+    Batch bo = b;
+    for (int i = 0; i < bo.n; ++i) bo.f[i].flags |= kFdNoHist;
+    if ((rc = stage(prof, "dark", s, [&] { return launch_dark(bo, g, he, s); })) != HZD_OK) return rc;
+    if ((rc = stage(prof, "select", s, [&] { return launch_select_one(bo, s); })) != HZD_OK) return rc;
+  } else {
+    if ((rc = stage(prof, "init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
+    if ((rc = stage(prof, "dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
+    if ((rc = stage(prof, "select", s, [&] { return launch_select(b, s); })) != HZD_OK) return rc;
+  }
   if (g.mode == HZD_MODE_OFFLINE) {
     if ((rc = stage(prof, "gf_prep", s, [&] { return launch_gf_prep(b, g, s); })) != HZD_OK) return rc;
     if ((rc = stage(prof, "gf_ab", s, [&] { return launch_gf_ab(b, g, s); })) != HZD_OK) return rc;

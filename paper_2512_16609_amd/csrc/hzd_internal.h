@@ -50,6 +50,7 @@ struct FrameDev {
   uint8_t* D;        // dark channel, pitch D_pitch
   uint8_t* E;        // per-channel erosions (packed RGB8), pitch E_pitch
   RowSel* rowsel;    // per row: selection counts and sums (one record per row)
+  uint16_t* hpart;   // small frames: each k_dark tile's 256-bin histogram of D (the one-block selection sums them)
   uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
   void* AB;          // offline: guided-filter a, b in fixed point, int2 or longlong2 (GroupKey.ab64), pitch W
   uint2* S8a;        // offline: per column and aligned 8-row chunk, sums of {L, P}
@@ -68,7 +69,7 @@ struct FrameDev {
   int32_t radius;
   float omega, t0, alpha, inv_gamma, gamma_log_bias;  // gamma_log_bias = log2(255) (1 - 1/gamma)
   float eps;
-  float ab_scale, ab_inv_scale;                      // fixed-point scale of a, b
+  float ab_scale;                                    // fixed-point scale 2^k of a, b
   int32_t gf_rows;   // output rows per guided-filter block
   float ema;         // temporal airlight weight lam (0 = none)
   float gamma_target;  // tau of the adaptive gamma
@@ -82,6 +83,7 @@ constexpr uint32_t kFdAligned = 2u;         // src, dst and both pitches are mul
 constexpr uint32_t kFdEmaFirst = 4u;        // the stream's first frame: ignore the stored airlight
 constexpr uint32_t kFdGammaAdaptive = 8u;   // per-frame gamma from the luma sums of J
 constexpr uint32_t kFdWbPercentile = 16u;   // balance by percentile stretch (else gray-world)
+constexpr uint32_t kFdNoHist = 32u;         // k_dark skips the histogram (the one-block selection builds it)
 
 struct Batch {
   int32_t n;
@@ -138,6 +140,15 @@ hipError_t launch_resize(ResizeBatch r, hipStream_t s);
 hipError_t launch_init(Batch b, hipStream_t s);
 hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s);
 hipError_t launch_select(Batch b, hipStream_t s);        // two kernels: rows, then one block per frame
+// One block per frame for small frames (select_one_fits); the frames' k_dark
+// launch skips its histogram (kFdNoHist) and the init kernel is not needed.
+hipError_t launch_select_one(Batch b, hipStream_t s);
+constexpr int kOneVecMax = 8;    // 16-byte D vectors per thread of the one-block selection
+__host__ __device__ inline int dark_tiles(int W, int H) { return ((W + 63) / 64) * ((H + 31) / 32); }   // k_dark's 64 x 32 tiles
+inline bool select_one_fits(int W, int H) {
+  const int vpr = ((W + 15) & ~15) / 16;
+  return W <= 1024 && H <= 2048 && (long long)H * vpr <= 1024LL * kOneVecMax && dark_tiles(W, H) <= 160;
+}
 hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s);
 hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s);
 hipError_t launch_gf_q(Batch b, const GroupKey& g, hipStream_t s);

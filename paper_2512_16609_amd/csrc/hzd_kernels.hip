@@ -26,6 +26,9 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstddef>
+
 #include "hzd_internal.h"
 
 namespace hzd {
@@ -506,7 +509,11 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   }
   __syncthreads();
   const uint32_t hv = s_hist[tid];
-  if (hv) atomicAdd(&fd.st->hist[tile % kHistSlots][tid], hv);
+  if (fd.flags & kFdNoHist) {
+    fd.hpart[tile * 256 + tid] = (uint16_t)hv;   // <= 2048: the tile's histogram, for the one-block selection
+  } else if (hv) {
+    atomicAdd(&fd.st->hist[tile % kHistSlots][tid], hv);
+  }
 }
 
 // ------------------------------------------------ k_select_rows, k_select_final
@@ -521,6 +528,65 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
 // k_select_final: one block per frame scans the row records, finds the row
 // holding the cut, finds the cutoff pixel inside it with a block-wide scan of
 // per-lane tie counts, and forms A^c = alpha * S^c / K from exact integer sums.
+
+// The end of Eq. (3) for one frame, by one thread: A^c = alpha S^c / K from the
+// exact integer sums (in double; optionally averaged with the stream's stored
+// airlight: (lam A_prev) + ((1 - lam) Ahat), each operation rounded on its
+// own), then the frame's state, the stream state and the aux outputs.
+// status: 0 = consistent, 1 = the counts disagree (A formed, not trusted).
+__device__ void store_airlight(const FrameDev& fd, uint32_t K, uint32_t vstar, int32_t cutoff,
+                               const unsigned long long S[3], int32_t status) {
+  FrameState* st = fd.st;
+  const double a = (double)fd.alpha;
+  float* ast = fd.A_state;
+  const bool blend = ast && fd.ema > 0.0f && !(fd.flags & kFdEmaFirst) && __float_as_uint(ast[3]) != 0u;
+  const double lam = (double)fd.ema;
+  for (int ch = 0; ch < 3; ++ch) {
+    double Ad = a * (double)S[ch] / (double)K;
+    if (blend) Ad = __dadd_rn(__dmul_rn(lam, (double)ast[ch]), __dmul_rn(__dsub_rn(1.0, lam), Ad));
+    const float A = (float)Ad;
+    st->A[ch] = A;
+    if (fd.A_out) fd.A_out[ch] = A;
+  }
+  if (ast) {
+    const uint32_t seen = blend ? __float_as_uint(ast[3]) : 0u;
+    for (int ch = 0; ch < 3; ++ch) ast[ch] = st->A[ch];
+    ast[3] = __uint_as_float(seen < 0xFFFFFFFFu ? seen + 1u : seen);
+  }
+  st->sel[0] = (int32_t)K;
+  st->sel[1] = (int32_t)vstar;
+  st->sel[2] = cutoff;
+  st->sel[3] = status;
+  if (fd.sel_out) {
+    fd.sel_out[0] = (int32_t)K;
+    fd.sel_out[1] = (int32_t)vstar;
+    fd.sel_out[2] = cutoff;
+    fd.sel_out[3] = status;
+    __threadfence_system();   // sel_out may be host memory read when the stream completes
+  }
+}
+
+// No cut row exists (the per-row counts hold fewer ties than the histogram):
+// A is set to 0 and the frame flagged with status 2 instead of reading a row
+// that is not there; the stream's stored airlight is left as it was.
+__device__ void store_no_cut(const FrameDev& fd, uint32_t K, uint32_t vstar) {
+  FrameState* st = fd.st;
+  for (int ch = 0; ch < 3; ++ch) {
+    st->A[ch] = 0.0f;
+    if (fd.A_out) fd.A_out[ch] = 0.0f;
+  }
+  st->sel[0] = (int32_t)K;
+  st->sel[1] = (int32_t)vstar;
+  st->sel[2] = -1;
+  st->sel[3] = 2;
+  if (fd.sel_out) {
+    fd.sel_out[0] = (int32_t)K;
+    fd.sel_out[1] = (int32_t)vstar;
+    fd.sel_out[2] = -1;
+    fd.sel_out[3] = 2;
+    __threadfence_system();
+  }
+}
 
 // vstar and #{D > vstar} from the slotted histogram; thread t < 256 holds the
 // count of value 255 - t, so an inclusive scan gives #{D >= 255 - t}.
@@ -748,27 +814,7 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
   const int rstar = s_misc[2];
   const uint32_t before = (uint32_t)s_misc[3];
   if (rstar < 0) {
-    // inconsistent counts (the row records hold fewer ties than the histogram):
-    // no cut row exists.  A is set to 0 and the frame is flagged (status 2)
-    // instead of reading a row that is not there; the stream's stored airlight
-    // is left as it was.
-    if (tid == 0) {
-      for (int ch = 0; ch < 3; ++ch) {
-        st->A[ch] = 0.0f;
-        if (fd.A_out) fd.A_out[ch] = 0.0f;
-      }
-      st->sel[0] = (int32_t)K;
-      st->sel[1] = (int32_t)vstar;
-      st->sel[2] = -1;
-      st->sel[3] = 2;
-      if (fd.sel_out) {
-        fd.sel_out[0] = (int32_t)K;
-        fd.sel_out[1] = (int32_t)vstar;
-        fd.sel_out[2] = -1;
-        fd.sel_out[3] = 2;
-        __threadfence_system();   // sel_out may be host memory read when the stream completes
-      }
-    }
+    if (tid == 0) store_no_cut(fd, K, vstar);
     return;
   }
   if (rb <= rstar) {
@@ -851,37 +897,245 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     for (int w = 0; w < kFinW; ++w)
       for (int i = 0; i < 5; ++i) S[i] += s_red[w][i];
     const int cx = (int)S[4] - 1;
-    const int32_t cutoff = rstar * W + cx;
-    const double a = (double)fd.alpha;
-    // temporal average with the stream's stored airlight: (lam A_prev) +
-    // ((1 - lam) Ahat) in double, each operation rounded on its own
-    float* ast = fd.A_state;
-    const bool blend = ast && fd.ema > 0.0f && !(fd.flags & kFdEmaFirst) && __float_as_uint(ast[3]) != 0u;
-    const double lam = (double)fd.ema;
-    for (int ch = 0; ch < 3; ++ch) {
-      double Ad = a * (double)S[ch] / (double)K;
-      if (blend) Ad = __dadd_rn(__dmul_rn(lam, (double)ast[ch]), __dmul_rn(__dsub_rn(1.0, lam), Ad));
-      const float A = (float)Ad;
-      st->A[ch] = A;
-      if (fd.A_out) fd.A_out[ch] = A;
-    }
-    if (ast) {
-      const uint32_t seen = blend ? __float_as_uint(ast[3]) : 0u;
-      for (int ch = 0; ch < 3; ++ch) ast[ch] = st->A[ch];
-      ast[3] = __uint_as_float(seen < 0xFFFFFFFFu ? seen + 1u : seen);
-    }
-    st->sel[0] = (int32_t)K;
-    st->sel[1] = (int32_t)vstar;
-    st->sel[2] = cutoff;
     // consistency: the rows' count over D > vstar must equal the histogram's
-    st->sel[3] = (S[3] == (unsigned long long)cnt_gt && cx >= 0) ? 0 : 1;
-    if (fd.sel_out) {
-      fd.sel_out[0] = (int32_t)K;
-      fd.sel_out[1] = (int32_t)vstar;
-      fd.sel_out[2] = cutoff;
-      fd.sel_out[3] = st->sel[3];
-      __threadfence_system();   // sel_out may be host memory read when the stream completes
+    store_airlight(fd, K, vstar, rstar * W + cx, S, (S[3] == (unsigned long long)cnt_gt && cx >= 0) ? 0 : 1);
+  }
+}
+
+// ------------------------------------------------------------ k_select_one
+// Eq. (3) for a small frame in one 1024-thread block: the block reads D once
+// into registers (thread t holds the 16-byte vectors t, t + 1024, ... of the
+// padded rows) and takes every step from them.
+//   1. the 256-bin histogram of D (the sum of k_dark's per-tile histograms)
+//      -> vstar and #{D > vstar}
+//   2. ties per row (LDS atomics) -> block scan over rows -> the cut row, and
+//      the cut row's vectors in LDS -> one wave scans their tie counts and
+//      finds the cut pixel (the need-th tie in raster order)
+//   3. the set {D > vstar} U {D == vstar, index <= cutoff}: exact sums of I
+//      over it, gathered only where a vector holds members
+// and A = alpha S / K.  It also zeroes the frame state's sums for the later
+// passes (colour balance, luma, white balance); with the per-tile histograms
+// written whole by k_dark, nothing of the frame's state needs zeroing before
+// the frame, so the init kernel is not run.  Used when W <= 1024
+// (one vector per lane covers a row of the cut row scan), H <= kOneRows and
+// the vectors fit kOneVec per thread.
+constexpr int kOneT = 1024, kOneW = kOneT / 64;
+constexpr int kOneRows = 2048;
+constexpr int kOneTileLoads = 40;   // per-tile histogram loads per thread in flight
+constexpr int kOneTiles = 4 * kOneTileLoads;   // k_dark tiles of a frame on this path (<= 145 by select_one_fits)
+
+template <int NVT>
+__global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_tmax[kOneTiles];  // the largest D of each k_dark tile
+  __shared__ uint32_t s_tc[kOneRows];     // ties per row
+  __shared__ uint4 s_D[NVT * kOneT];      // D, for the scan of the cut row
+  __shared__ int s_misc[4];
+  __shared__ unsigned long long s_red[kOneW][4];
+  const FrameDev& fd = b.f[blockIdx.x];
+  FrameState* st = fd.st;
+  const int W = fd.W, H = fd.H;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int vpr = fd.D_pitch >> 4;        // 16-byte vectors per row (<= 64)
+  const int NV = H * vpr;
+  const uint32_t K = (uint32_t)fd.K;
+  const int tiles_x = (W + 63) / 64, nt = dark_tiles(W, H);
+
+  for (int i = tid; i < H; i += kOneT) s_tc[i] = 0u;
+  if (tid < 256) s_hist[tid] = 0u;
+  if (tid < kOneTiles) s_tmax[tid] = 0u;
+  // every load is issued before the first barrier: thread t holds the D
+  // vectors t, t + 1024, ... and bin t % 256 of the tiles t / 256, t / 256 + 4,
+  // ... of the per-tile histograms k_dark wrote (at most kOneTiles tiles)
+  uint4 dv[NVT];
+  int vy[NVT], vx[NVT];
+#pragma unroll
+  for (int i = 0; i < NVT; ++i) {
+    const int v = tid + kOneT * i;
+    vy[i] = v / vpr;
+    vx[i] = (v - vy[i] * vpr) * 16;
+    dv[i] = v < NV ? *reinterpret_cast<const uint4*>(fd.D + (int64_t)vy[i] * fd.D_pitch + vx[i])
+                   : make_uint4(0u, 0u, 0u, 0u);
+    if (v >= NV) vy[i] = -1;
+  }
+  const int bin = tid & 255, q = tid >> 8;
+  uint32_t hv[kOneTileLoads];
+#pragma unroll
+  for (int u = 0; u < kOneTileLoads; ++u) {
+    const int tt = q + 4 * u;
+    hv[u] = tt < nt ? fd.hpart[tt * 256 + bin] : 0u;
+  }
+  // the frame state's sums of the later passes start at zero
+  {
+    uint32_t* z = reinterpret_cast<uint32_t*>(&st->cb[0][0]);
+    constexpr int nz = (int)((sizeof(FrameState) - offsetof(FrameState, cb)) / 4);
+    for (int i = tid; i < nz; i += kOneT) z[i] = 0u;
+  }
+  auto dbyte = [&](int i, int j) { return (((&dv[i].x)[j >> 2]) >> (8 * (j & 3))) & 0xFFu; };
+  __syncthreads();   // LDS zeroed
+  {
+    uint32_t hsum = 0;
+#pragma unroll
+    for (int u = 0; u < kOneTileLoads; ++u) {
+      hsum += hv[u];
+      if (hv[u]) atomicMax(&s_tmax[q + 4 * u], (uint32_t)bin);
     }
+    if (hsum) atomicAdd(&s_hist[bin], hsum);
+  }
+#pragma unroll
+  for (int i = 0; i < NVT; ++i)
+    if (vy[i] >= 0) s_D[tid + kOneT * i] = dv[i];
+  __syncthreads();   // histogram and tile maxima complete
+
+  // 1. vstar and #{D > vstar}: wave 0 scans the bins from the top, 4 per lane
+  if (wv == 0) {
+    uint32_t c[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = s_hist[255 - 4 * lane - k];
+      sum += c[k];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    uint32_t run = incl - sum;   // #{D > 255 - 4 lane}
+    if (run < K && K <= incl) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (run < K && K <= run + c[k]) {
+          s_misc[0] = 255 - 4 * lane - k;
+          s_misc[1] = (int)run;
+        }
+        run += c[k];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t vstar = (uint32_t)s_misc[0], cnt_gt = (uint32_t)s_misc[1];
+  const uint32_t need = K - cnt_gt;   // >= 1
+  // a vector whose tile holds no D >= vstar has no tie and no member of the set
+  auto hot = [&](int i) { return vy[i] >= 0 && s_tmax[(vy[i] >> 5) * tiles_x + (vx[i] >> 6)] >= vstar; };
+
+  // 2. ties per row
+#pragma unroll
+  for (int i = 0; i < NVT; ++i) {
+    if (!hot(i)) continue;
+    const int n = min(16, W - vx[i]);
+    uint32_t m = 0u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < n && dbyte(i, j) == vstar) m |= 1u << j;
+    if (m) atomicAdd(&s_tc[vy[i]], (uint32_t)__popc(m));
+  }
+  __syncthreads();
+  // the cut row and the cut pixel, by wave 0: lane l sums rows [32 l, 32 l + 32),
+  // a wave scan finds the lane, then the row, holding the need-th tie; then
+  // lane l takes vector l of that row (vpr <= 64) and a second scan finds the pixel
+  if (wv == 0) {
+    constexpr int RPL = kOneRows / 64;
+    uint32_t t = 0;
+#pragma unroll 8
+    for (int k = 0; k < RPL; ++k) {
+      const int y = RPL * lane + k;
+      t += y < H ? s_tc[y] : 0u;
+    }
+    const uint32_t incl = wave_incl_scan(t);
+    uint32_t cum = incl - t;
+    int ycut = -1;
+    uint32_t before = 0;
+    if (cum < need && need <= incl) {
+      for (int k = 0; k < RPL; ++k) {
+        const int y = RPL * lane + k;
+        const uint32_t c = y < H ? s_tc[y] : 0u;
+        if (cum + c >= need) {
+          ycut = y;
+          before = cum;
+          break;
+        }
+        cum += c;
+      }
+    }
+    // the lane that found the row broadcasts it (-1 everywhere if none did)
+    const uint64_t who = __ballot(ycut >= 0);
+    if (who) {
+      const int src = __ffsll((long long)who) - 1;
+      ycut = __shfl(ycut, src, 64);
+      before = __shfl(before, src, 64);
+      const uint32_t kcut = need - before;   // the cut is the kcut-th tie of row ycut
+      uint32_t m = 0u;
+      if (lane < vpr) {
+        const uint4 c = s_D[ycut * vpr + lane];
+        const int n = min(16, W - 16 * lane);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const uint32_t d = (((&c.x)[j >> 2]) >> (8 * (j & 3))) & 0xFFu;
+          if (j < n && d == vstar) m |= 1u << j;
+        }
+      }
+      const uint32_t cnt = (uint32_t)__popc(m);
+      const uint32_t ci = wave_incl_scan(cnt), ce = ci - cnt;
+      if (ce < kcut && kcut <= ci) {
+        for (uint32_t k = ce + 1; k < kcut; ++k) m &= m - 1;   // drop the ties before the cut
+        s_misc[2] = ycut * W + 16 * lane + (__ffs(m) - 1);
+      }
+    } else if (lane == 0) {
+      s_misc[2] = -1;
+    }
+  }
+  __syncthreads();
+  const int cutoff = s_misc[2];
+  if (cutoff < 0) {
+    if (tid == 0) store_no_cut(fd, K, vstar);
+    return;
+  }
+
+  // 3. exact sums of I over the set
+  unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+  for (int i = 0; i < NVT; ++i) {
+    if (!hot(i)) continue;
+    const int n = min(16, W - vx[i]);
+    const int base = vy[i] * W + vx[i];
+    uint32_t mem = 0u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t d = dbyte(i, j);
+      if (j < n && (d > vstar || (d == vstar && base + j <= cutoff))) mem |= 1u << j;
+    }
+    if (!mem) continue;
+    const uint8_t* Irow = fd.src + (int64_t)vy[i] * fd.src_pitch + 3 * vx[i];
+    acc[3] += (unsigned long long)__popc(mem);
+    if ((fd.flags & kFdAligned) && n == 16) {   // the vector's 16 pixels in 12 dword loads
+      uint32_t iw[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) iw[q] = reinterpret_cast<const uint32_t*>(Irow)[q];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if ((mem >> j) & 1u) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[c] += (iw[(3 * j + c) >> 2] >> (8 * ((3 * j + c) & 3))) & 0xFFu;
+        }
+      }
+    } else {
+      while (mem) {
+        const int j = __ffs(mem) - 1;
+        mem &= mem - 1;
+        acc[0] += Irow[3 * j];
+        acc[1] += Irow[3 * j + 1];
+        acc[2] += Irow[3 * j + 2];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const unsigned long long x = wave_sum(acc[c]);
+    if (lane == 0) s_red[wv][c] = x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long S[4] = {0, 0, 0, 0};
+    for (int w = 0; w < kOneW; ++w)
+      for (int c = 0; c < 4; ++c) S[c] += s_red[w][c];
+    // consistency: the set has exactly K members
+    store_airlight(fd, K, vstar, cutoff, S, S[3] == (unsigned long long)K ? 0 : 1);
   }
 }
 
@@ -1590,7 +1844,7 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   int ic[NI], iclo[NI], ichi[NI], ixc[NI];
   double icw_s[NI];
   bool iok[NI];
-  const double inv_s = (double)fd.ab_inv_scale;
+  const double inv_s = 1.0 / (double)fd.ab_scale;   // exact: the scale is a power of two
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     ic[j] = lane + 64 * j;
@@ -1942,6 +2196,13 @@ hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s) 
     case 15: return dark_hp<15>(b, nblk, write_E, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_select_one(Batch b, hipStream_t s) {
+  for (int i = 0; i < b.n; ++i)
+    if (!select_one_fits(b.f[i].W, b.f[i].H)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_select_one<kOneVecMax>), dim3(b.n), dim3(kOneT), 0, s, b);
+  return hipGetLastError();
 }
 
 hipError_t launch_select(Batch b, hipStream_t s) {
