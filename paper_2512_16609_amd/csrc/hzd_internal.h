@@ -145,9 +145,10 @@ hipError_t launch_select(Batch b, hipStream_t s);        // two kernels: rows, t
 hipError_t launch_select_one(Batch b, hipStream_t s);
 constexpr int kOneVecMax = 8;    // 16-byte D vectors per thread of the one-block selection
 __host__ __device__ inline int dark_tiles(int W, int H) { return ((W + 63) / 64) * ((H + 31) / 32); }   // k_dark's 64 x 32 tiles
+// The one-block selection numbers D's vectors tile by tile (128 slots per
+// k_dark tile) and gives each of its 1024 threads kOneVecMax slots.
 inline bool select_one_fits(int W, int H) {
-  const int vpr = ((W + 15) & ~15) / 16;
-  return W <= 1024 && H <= 2048 && (long long)H * vpr <= 1024LL * kOneVecMax && dark_tiles(W, H) <= 160;
+  return W <= 1024 && H <= 2048 && dark_tiles(W, H) * 128 <= 1024 * kOneVecMax;
 }
 hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s);
 hipError_t launch_gf_ab(Batch b, const GroupKey& g, hipStream_t s);

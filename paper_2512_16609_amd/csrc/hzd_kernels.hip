@@ -903,60 +903,60 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
 }
 
 // ------------------------------------------------------------ k_select_one
-// Eq. (3) for a small frame in one 1024-thread block: the block reads D once
-// into registers (thread t holds the 16-byte vectors t, t + 1024, ... of the
-// padded rows) and takes every step from them.
-//   1. the 256-bin histogram of D (the sum of k_dark's per-tile histograms)
-//      -> vstar and #{D > vstar}
-//   2. ties per row (LDS atomics) -> block scan over rows -> the cut row, and
-//      the cut row's vectors in LDS -> one wave scans their tie counts and
-//      finds the cut pixel (the need-th tie in raster order)
-//   3. the set {D > vstar} U {D == vstar, index <= cutoff}: exact sums of I
-//      over it, gathered only where a vector holds members
-// and A = alpha S / K.  It also zeroes the frame state's sums for the later
-// passes (colour balance, luma, white balance); with the per-tile histograms
-// written whole by k_dark, nothing of the frame's state needs zeroing before
-// the frame, so the init kernel is not run.  Used when W <= 1024
-// (one vector per lane covers a row of the cut row scan), H <= kOneRows and
-// the vectors fit kOneVec per thread.
+// Eq. (3) for a small frame in one 1024-thread block.  D is read once: its
+// 16-byte vectors are numbered tile by tile (k_dark's 64x32 tiles, 128 vector
+// slots each: 32 rows x 4 vectors), and thread t holds the slots t, t + 1024,
+// ..., so a wave holds half of one tile.  The block
+//   1. sums the per-tile 256-bin histograms k_dark wrote -> vstar and
+//      #{D > vstar}, and each tile's largest D;
+//   2. counts the ties per row, in the tiles whose largest D reaches vstar
+//      (a wave-uniform test: every other wave skips); wave 0 scans the rows
+//      for the one holding the need-th tie, and the ties of that row (kept in
+//      LDS) for the cut pixel;
+//   3. sums I exactly over {D > vstar} U {D == vstar, index <= cutoff}, again
+//      only in those tiles;
+// and forms A = alpha S / K.  It also zeroes the frame state's sums for the
+// later passes (colour balance, luma, white balance); with the per-tile
+// histograms written whole by k_dark, nothing of the frame's state needs
+// zeroing before the frame, so the init kernel is not run.  Used when W <=
+// 1024 (the cut row is one vector per lane of a wave) and the frame has at
+// most kOneTiles tiles (select_one_fits).
 constexpr int kOneT = 1024, kOneW = kOneT / 64;
 constexpr int kOneRows = 2048;
-constexpr int kOneTileLoads = 40;   // per-tile histogram loads per thread in flight
-constexpr int kOneTiles = 4 * kOneTileLoads;   // k_dark tiles of a frame on this path (<= 145 by select_one_fits)
+constexpr int kOneTileLoads = 16;                 // per-tile histogram loads per thread
+constexpr int kOneTiles = 4 * kOneTileLoads;      // tiles of a frame on this path (64)
+static_assert(kOneTiles * 128 == kOneT * kOneVecMax, "every vector slot of every tile has a thread");
 
 template <int NVT>
 __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_tmax[kOneTiles];  // the largest D of each k_dark tile
   __shared__ uint32_t s_tc[kOneRows];     // ties per row
-  __shared__ uint4 s_D[NVT * kOneT];      // D, for the scan of the cut row
+  __shared__ uint4 s_D[NVT * kOneT];      // D by slot, for the scan of the cut row
   __shared__ int s_misc[4];
   __shared__ unsigned long long s_red[kOneW][4];
   const FrameDev& fd = b.f[blockIdx.x];
   FrameState* st = fd.st;
   const int W = fd.W, H = fd.H;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int vpr = fd.D_pitch >> 4;        // 16-byte vectors per row (<= 64)
-  const int NV = H * vpr;
   const uint32_t K = (uint32_t)fd.K;
   const int tiles_x = (W + 63) / 64, nt = dark_tiles(W, H);
 
   for (int i = tid; i < H; i += kOneT) s_tc[i] = 0u;
   if (tid < 256) s_hist[tid] = 0u;
   if (tid < kOneTiles) s_tmax[tid] = 0u;
-  // every load is issued before the first barrier: thread t holds the D
-  // vectors t, t + 1024, ... and bin t % 256 of the tiles t / 256, t / 256 + 4,
-  // ... of the per-tile histograms k_dark wrote (at most kOneTiles tiles)
+  // every load is issued before the first barrier
   uint4 dv[NVT];
-  int vy[NVT], vx[NVT];
+  int vy[NVT], vx[NVT];   // vy < 0: no vector in this slot
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
-    const int v = tid + kOneT * i;
-    vy[i] = v / vpr;
-    vx[i] = (v - vy[i] * vpr) * 16;
-    dv[i] = v < NV ? *reinterpret_cast<const uint4*>(fd.D + (int64_t)vy[i] * fd.D_pitch + vx[i])
-                   : make_uint4(0u, 0u, 0u, 0u);
-    if (v >= NV) vy[i] = -1;
+    const int slot = tid + kOneT * i, tile = slot >> 7, l = slot & 127;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    vy[i] = ty * 32 + (l >> 2);
+    vx[i] = tx * 64 + (l & 3) * 16;
+    const bool ok = tile < nt && vy[i] < H && vx[i] < W;
+    dv[i] = ok ? *reinterpret_cast<const uint4*>(fd.D + (int64_t)vy[i] * fd.D_pitch + vx[i]) : make_uint4(0u, 0u, 0u, 0u);
+    if (!ok) vy[i] = -1;
   }
   const int bin = tid & 255, q = tid >> 8;
   uint32_t hv[kOneTileLoads];
@@ -974,17 +974,19 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   auto dbyte = [&](int i, int j) { return (((&dv[i].x)[j >> 2]) >> (8 * (j & 3))) & 0xFFu; };
   __syncthreads();   // LDS zeroed
   {
+    // a wave holds 64 consecutive bins of the same tiles: the highest of its
+    // nonzero bins per tile comes from one ballot, and one lane records it
     uint32_t hsum = 0;
 #pragma unroll
     for (int u = 0; u < kOneTileLoads; ++u) {
       hsum += hv[u];
-      if (hv[u]) atomicMax(&s_tmax[q + 4 * u], (uint32_t)bin);
+      const uint64_t nz = __ballot(hv[u] != 0u);
+      if (nz && lane == 0) atomicMax(&s_tmax[q + 4 * u], (uint32_t)((bin & ~63) + 63 - __clzll((long long)nz)));
     }
     if (hsum) atomicAdd(&s_hist[bin], hsum);
   }
 #pragma unroll
-  for (int i = 0; i < NVT; ++i)
-    if (vy[i] >= 0) s_D[tid + kOneT * i] = dv[i];
+  for (int i = 0; i < NVT; ++i) s_D[tid + kOneT * i] = dv[i];
   __syncthreads();   // histogram and tile maxima complete
 
   // 1. vstar and #{D > vstar}: wave 0 scans the bins from the top, 4 per lane
@@ -1011,24 +1013,32 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   __syncthreads();
   const uint32_t vstar = (uint32_t)s_misc[0], cnt_gt = (uint32_t)s_misc[1];
   const uint32_t need = K - cnt_gt;   // >= 1
-  // a vector whose tile holds no D >= vstar has no tie and no member of the set
-  auto hot = [&](int i) { return vy[i] >= 0 && s_tmax[(vy[i] >> 5) * tiles_x + (vx[i] >> 6)] >= vstar; };
+  // the slots of a wave lie in one tile: whether it can hold ties or members
+  // of the set is wave-uniform
+  bool hot[NVT];
+#pragma unroll
+  for (int i = 0; i < NVT; ++i) {
+    const int tile = (tid + kOneT * i) >> 7;
+    hot[i] = tile < nt && s_tmax[tile] >= vstar;
+  }
 
   // 2. ties per row
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
-    if (!hot(i)) continue;
-    const int n = min(16, W - vx[i]);
+    if (!hot[i]) continue;
     uint32_t m = 0u;
+    if (vy[i] >= 0) {
+      const int n = min(16, W - vx[i]);
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (j < n && dbyte(i, j) == vstar) m |= 1u << j;
+      for (int j = 0; j < 16; ++j)
+        if (j < n && dbyte(i, j) == vstar) m |= 1u << j;
+    }
     if (m) atomicAdd(&s_tc[vy[i]], (uint32_t)__popc(m));
   }
   __syncthreads();
   // the cut row and the cut pixel, by wave 0: lane l sums rows [32 l, 32 l + 32),
   // a wave scan finds the lane, then the row, holding the need-th tie; then
-  // lane l takes vector l of that row (vpr <= 64) and a second scan finds the pixel
+  // lane l takes vector l of that row (W <= 1024) and a second scan finds the pixel
   if (wv == 0) {
     constexpr int RPL = kOneRows / 64;
     uint32_t t = 0;
@@ -1061,8 +1071,9 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
       before = __shfl(before, src, 64);
       const uint32_t kcut = need - before;   // the cut is the kcut-th tie of row ycut
       uint32_t m = 0u;
-      if (lane < vpr) {
-        const uint4 c = s_D[ycut * vpr + lane];
+      if (16 * lane < W) {
+        const int tile = (ycut >> 5) * tiles_x + (lane >> 2);
+        const uint4 c = s_D[tile * 128 + (ycut & 31) * 4 + (lane & 3)];
         const int n = min(16, W - 16 * lane);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -1087,41 +1098,30 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     return;
   }
 
-  // 3. exact sums of I over the set
+  // 3. exact sums of I over the set (its members are few: K of them)
   unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
-    if (!hot(i)) continue;
-    const int n = min(16, W - vx[i]);
-    const int base = vy[i] * W + vx[i];
+    if (!hot[i]) continue;
     uint32_t mem = 0u;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const uint32_t d = dbyte(i, j);
-      if (j < n && (d > vstar || (d == vstar && base + j <= cutoff))) mem |= 1u << j;
-    }
-    if (!mem) continue;
-    const uint8_t* Irow = fd.src + (int64_t)vy[i] * fd.src_pitch + 3 * vx[i];
-    acc[3] += (unsigned long long)__popc(mem);
-    if ((fd.flags & kFdAligned) && n == 16) {   // the vector's 16 pixels in 12 dword loads
-      uint32_t iw[12];
-#pragma unroll
-      for (int q = 0; q < 12; ++q) iw[q] = reinterpret_cast<const uint32_t*>(Irow)[q];
+    if (vy[i] >= 0) {
+      const int n = min(16, W - vx[i]);
+      const int base = vy[i] * W + vx[i];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        if ((mem >> j) & 1u) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[c] += (iw[(3 * j + c) >> 2] >> (8 * ((3 * j + c) & 3))) & 0xFFu;
-        }
+        const uint32_t d = dbyte(i, j);
+        if (j < n && (d > vstar || (d == vstar && base + j <= cutoff))) mem |= 1u << j;
       }
-    } else {
-      while (mem) {
-        const int j = __ffs(mem) - 1;
-        mem &= mem - 1;
-        acc[0] += Irow[3 * j];
-        acc[1] += Irow[3 * j + 1];
-        acc[2] += Irow[3 * j + 2];
-      }
+    }
+    if (!__any(mem != 0u)) continue;
+    const uint8_t* Irow = fd.src + (int64_t)max(vy[i], 0) * fd.src_pitch + 3 * vx[i];
+    acc[3] += (unsigned long long)__popc(mem);
+    while (mem) {
+      const int j = __ffs(mem) - 1;
+      mem &= mem - 1;
+      acc[0] += Irow[3 * j];
+      acc[1] += Irow[3 * j + 1];
+      acc[2] += Irow[3 * j + 2];
     }
   }
 #pragma unroll
