@@ -169,7 +169,7 @@ size_t frame_ws_bytes(const hzd_params& p, int Win, int Hin) {
     s += a256((size_t)W * H * 8);                      // LP
     s += a256((size_t)W * H * (ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).wide ? 16 : 8));   // AB
     const size_t nch = (size_t)((H + 7) / 8);
-    s += a256(nch * W * 8) + a256(nch * W * 16) + a256(nch * W * 16);  // 8-row chunk sums
+    s += a256(nch * W * 16) + a256(nch * W * 16) + a256(nch * W * 16);  // 8-row chunk sums
     if (p.color_balance || p.gamma_adaptive) s += a256((size_t)W * H * (p.precision == HZD_PREC_FP16 ? 2 : 4));
   }
   return s;
@@ -340,9 +340,9 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
     d.AB = ws + off;
     off += a256((size_t)W * H * (ab_fixed_point(p.gf_eps, p.t0, p.gf_radius).wide ? 16 : 8));
     const size_t nch = (size_t)((H + 7) / 8);
-    d.S8a = reinterpret_cast<uint2*>(ws + off);
-    off += a256(nch * W * 8);
-    d.S8b = reinterpret_cast<ulonglong2*>(ws + off);
+    d.PGa = reinterpret_cast<ulonglong2*>(ws + off);
+    off += a256(nch * W * 16);
+    d.PGb = reinterpret_cast<ulonglong2*>(ws + off);
     off += a256(nch * W * 16);
     d.S8ab = reinterpret_cast<longlong2*>(ws + off);
     off += a256(nch * W * 16);

@@ -53,8 +53,8 @@ struct FrameDev {
   uint16_t* hpart;   // small frames: each k_dark tile's 256-bin histogram of D (the one-block selection sums them)
   uint2* LP;         // offline: {luma*1000, t * 2^28} per pixel (pitch W)
   void* AB;          // offline: guided-filter a, b in fixed point, int2 or longlong2 (GroupKey.ab64), pitch W
-  uint2* S8a;        // offline: per column and aligned 8-row chunk, sums of {L, P}
-  ulonglong2* S8b;   // offline: per column and chunk, sums of {L^2, L*P}
+  ulonglong2* PGa;   // offline: per column and aligned 8-row chunk, sums of {L, P} over the chunk's group of 8 up to it
+  ulonglong2* PGb;   // offline: the same for {L^2, L*P}
   longlong2* S8ab;   // offline: per column and chunk, sums of {a, b} (fixed point)
   void* tmap;        // offline + colour balance: refined t (float or half, pitch W)
   float* A_out;

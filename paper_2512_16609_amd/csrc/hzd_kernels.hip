@@ -35,8 +35,9 @@ namespace hzd {
 
 // guided-filter column chunk sums (initial windows) and strip loop shape
 constexpr int kChunk = 8;                                      // rows per chunk sum
-constexpr int kEdgeBatch = 12;                                 // head/tail rows of a window loaded per round trip
-constexpr int kChunkBatch = 8;                                 // chunk sums loaded per round trip
+constexpr int kGroupChunks = 8;                                // chunks per prefix group of the guided filter's L, P sums
+constexpr int kEdgeBatch = 16;                                 // head/tail rows of a window loaded per round trip
+static_assert((2 * kMaxRadius + 1) / kChunk <= 2 * kGroupChunks, "a window's whole chunks span at most three groups");
 constexpr int kSelVec = 4;                                     // 16-byte D vectors per lane loaded at once
 
 // ------------------------------------------------------------------ helpers
@@ -82,12 +83,6 @@ __device__ __forceinline__ void sliding_min(const uint32_t (&v)[L], uint32_t (&o
   for (int i = 0; i < S; ++i) o[i] = pkmin(h[i], g[i + WIN - 1]);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // DPP move with zero for lanes whose source is outside the row or whose row
 // is masked off.
@@ -123,6 +118,23 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   v = dpp_add<0x142, 0xA>(v);
   v = dpp_add<0x143, 0xC>(v);
   return v;
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane: the DPP scan, then
+// lane 63's value read into scalar registers.  Integer types; the whole wave
+// must be active.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
+  const T s = wave_incl_scan(v);
+  if constexpr (sizeof(T) == 8) {
+    const unsigned long long u = (unsigned long long)s;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
+    return (T)(((unsigned long long)hi << 32) | lo);
+  } else {
+    return (T)__builtin_amdgcn_readlane((uint32_t)s, 63);
+  }
 }
 
 // Sum over a 256-thread block in a fixed order; every thread gets the total.
@@ -588,19 +600,6 @@ __device__ void store_no_cut(const FrameDev& fd, uint32_t K, uint32_t vstar) {
   }
 }
 
-// vstar and #{D > vstar} from the slotted histogram; thread t < 256 holds the
-// count of value 255 - t, so an inclusive scan gives #{D >= 255 - t}.
-template <int NW>
-__device__ __forceinline__ uint32_t hist_count(const FrameState* st) {
-  uint32_t c = 0;
-  const int tid = threadIdx.x;
-  if (NW * 64 <= 256 || tid < 256) {
-#pragma unroll
-    for (int k = 0; k < kHistSlots; ++k) c += st->hist[k][255 - tid];
-  }
-  return c;
-}
-
 // Inclusive scan over a block of NW waves; also returns the block total.
 template <int NW, typename T>
 __device__ __forceinline__ T block_scan_total(T v, T* s_tmp, T& total) {
@@ -620,25 +619,42 @@ __device__ __forceinline__ T block_scan_total(T v, T* s_tmp, T& total) {
   return x + add;
 }
 
-// From the per-thread histogram counts: vstar and #{D > vstar} (block-uniform).
-template <int NW>
-__device__ __forceinline__ void find_vstar(uint32_t c, uint32_t K, uint32_t* s_tmp, int* s_out,
-                                           uint32_t& vstar, uint32_t& cnt_gt) {
-  uint32_t tot;
-  const uint32_t incl = block_scan_total<NW>(c, s_tmp, tot);
-  if (incl >= K && incl - c < K) {  // exactly one thread: counts are >= 0 and K <= W*H
-    s_out[0] = 255 - (int)threadIdx.x;
-    s_out[1] = (int)(incl - c);
+// vstar and #{D > vstar} from the slotted histogram, in one wave with no LDS
+// and no barrier: lane l sums bins 4(63 - l) .. 4(63 - l) + 3 over the slots,
+// so the lanes in order, and each lane's bins from the top, hold the counts by
+// descending value; an inclusive scan gives #{D >= v}, and vstar is the first
+// v from the top at which it reaches K.  A histogram that never reaches K
+// (inconsistent state) gives vstar 0, which the final consistency test flags.
+__device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt) {
+  const int lane = threadIdx.x & 63;
+  const int b0 = 4 * (63 - lane);
+  uint4 c = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+  for (int k = 0; k < kHistSlots; ++k) {
+    const uint4 h = *reinterpret_cast<const uint4*>(&st->hist[k][b0]);
+    c.x += h.x; c.y += h.y; c.z += h.z; c.w += h.w;
   }
-  __syncthreads();
-  vstar = (uint32_t)s_out[0];
-  cnt_gt = (uint32_t)s_out[1];
+  // in-lane counts of D >= b0 + 3, b0 + 2, b0 + 1, b0
+  const uint32_t l3 = c.w, l2 = l3 + c.z, l1 = l2 + c.y, l0 = l1 + c.x;
+  const uint32_t incl = wave_incl_scan(l0);
+  const unsigned long long hit = __ballot(incl >= K);
+  const int L = hit ? __ffsll((long long)hit) - 1 : 63;
+  const uint32_t ex = __builtin_amdgcn_readlane(incl - l0, L);   // #{D > 4(63 - L) + 3}
+  const uint32_t a3 = __builtin_amdgcn_readlane(l3, L), a2 = __builtin_amdgcn_readlane(l2, L),
+                 a1 = __builtin_amdgcn_readlane(l1, L);
+  const uint32_t top = 4u * (uint32_t)(63 - L);
+  if (ex + a3 >= K) {
+    vstar = top + 3; cnt_gt = ex;
+  } else if (ex + a2 >= K) {
+    vstar = top + 2; cnt_gt = ex + a3;
+  } else if (ex + a1 >= K) {
+    vstar = top + 1; cnt_gt = ex + a2;
+  } else {
+    vstar = top; cnt_gt = ex + a1;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
-  __shared__ uint32_t s_u32[4];
-  __shared__ int s_misc[2];
-
   const int blk = blockIdx.x;
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
@@ -662,7 +678,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   };
   load_d(0);
   uint32_t vstar, cnt_gt;
-  find_vstar<4>(hist_count<4>(fd.st), (uint32_t)fd.K, s_u32, s_misc, vstar, cnt_gt);
+  wave_vstar(fd.st, (uint32_t)fd.K, vstar, cnt_gt);
   (void)cnt_gt;
   if (!row_ok) return;
   unsigned long long gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;
@@ -728,116 +744,130 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
 
 constexpr int kFinT = 512;             // threads of the final selection block
 constexpr int kFinW = kFinT / 64;
-constexpr int kFinRows = 4;            // row records per round trip per thread; kept in registers when H <= kFinT * kFinRows
+constexpr int kFinRows = 5;            // sweeps of kFinT rows per round (one round when H <= 2560)
 
+// The end of Eq. (3) for one frame, in one block.  Rows are dealt round-robin,
+// row = base + t + kFinT u for sweep u of a round, so a wave loads consecutive
+// records.  Per round of kFinRows sweeps:
+//   1. the records (with, in the first round, vstar and #{D > vstar} from the
+//      histogram) in one round trip; the tie counts go to LDS with the tie
+//      total of every wave of every sweep;
+//   2. after one barrier every wave finds, from those totals and one scan of
+//      the 64 tie counts of the wave holding it, the row that holds the
+//      need-th tie in raster order (need = K - #{D > vstar}) and the ties
+//      before it;
+// then 3. the cut row's D and I in one round trip, and an exclusive scan of
+// the per-thread tie counts that gives each thread its share of the row's
+// first need - (ties before) ties; 4. one block sum of the sums over
+// D > vstar, the tie sums of the rows before the cut row and the cut row's
+// share, from which thread 0 forms A.
 __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
-  __shared__ uint32_t s_u32[kFinW];
+  __shared__ uint32_t s_ties[kFinRows][kFinT];   // tie counts of the round's rows, by sweep and thread
+  __shared__ uint32_t s_tw[kFinRows][kFinW];     // tie total of each wave of each sweep
+  __shared__ uint32_t s_cnt[kFinW];
   __shared__ unsigned long long s_red[kFinW][5];
-  __shared__ int s_misc[4];
 
   const FrameDev& fd = b.f[blockIdx.x];  // one block per frame
-  FrameState* st = fd.st;
   const int W = fd.W, H = fd.H;
   const uint32_t K = (uint32_t)fd.K;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
 
-  // this thread's rows [ra, rb): counts and sums of the records, loaded kFinRows at a time
-  const int per = (H + kFinT - 1) / kFinT;
-  const int ra = min(H, tid * per), rb = min(H, ra + per);
-  const uint32_t hc = hist_count<kFinW>(st);
-  uint32_t ties = 0, above = 0;
-  unsigned long long ts[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
-  uint32_t rt[kFinRows] = {0u, 0u, 0u, 0u};  // the first kFinRows rows' tie counts and sums
-  unsigned long long rsum[kFinRows][3];
-  for (int y0 = ra; y0 < rb; y0 += kFinRows) {
-    RowSel r[kFinRows];
-#pragma unroll
-    for (int u = 0; u < kFinRows; ++u)
-      if (y0 + u < rb) r[u] = fd.rowsel[y0 + u];
+  RowSel r[kFinRows];
+  auto load_round = [&](int base) {
 #pragma unroll
     for (int u = 0; u < kFinRows; ++u) {
-      if (y0 + u >= rb) continue;
-      if (y0 == ra) {
-        rt[u] = r[u].ties;
+      const int y = base + tid + kFinT * u;
+      if (y < H) {
+        r[u] = fd.rowsel[y];
+      } else {
+        r[u].ties = 0u;
+        r[u].above = 0u;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rsum[u][c] = r[u].tsum[c];
+        for (int c = 0; c < 3; ++c) r[u].tsum[c] = r[u].gsum[c] = 0ull;
       }
-      ties += r[u].ties;
-      above += r[u].above;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) { ts[c] += r[u].tsum[c]; gs[c] += r[u].gsum[c]; }
     }
-  }
+  };
+  load_round(0);
   uint32_t vstar, cnt_gt;
-  find_vstar<kFinW>(hc, K, s_u32, s_misc, vstar, cnt_gt);
+  wave_vstar(fd.st, K, vstar, cnt_gt);
   const uint32_t need = K - cnt_gt;  // >= 1
 
-  // the row holding the need-th tie in raster order
-  if (tid == 0) {
-    s_misc[2] = -1;
-    s_misc[3] = 0;
-  }
-  uint32_t ttot;
-  const uint32_t rincl = block_scan_total<kFinW>(ties, s_u32, ttot);
-  const uint32_t rexcl = rincl - ties;
-  unsigned long long part[3] = {0, 0, 0};  // this thread's tie sums over rows before the cut row
-  if (rexcl < need && need <= rincl) {
-    uint32_t cum = rexcl;
-    if (rb - ra <= kFinRows) {  // from registers
+  int rstar = -1;          // the cut row (block-uniform once found)
+  uint32_t before = 0;     // ties in the rows before it
+  uint32_t carry = 0;      // ties in earlier rounds
+  unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};   // S^c so far, #{D > vstar}
+  for (int base = 0; base < H; base += kFinT * kFinRows) {
+    if (base > 0) {
+      __syncthreads();  // s_ties and s_tw are rewritten
+      load_round(base);
+    }
 #pragma unroll
-      for (int u = 0; u < kFinRows; ++u) {
-        if (ra + u >= rb) break;
-        if (cum + rt[u] >= need) {
-          s_misc[2] = ra + u;
-          s_misc[3] = (int)cum;
-          break;
+    for (int u = 0; u < kFinRows; ++u) {
+      s_ties[u][tid] = r[u].ties;
+      const uint32_t wt = wave_sum(r[u].ties);
+      if (lane == 0) s_tw[u][wv] = wt;
+    }
+    __syncthreads();
+    if (rstar < 0) {
+      uint32_t cum = carry;
+      int us = -1, ws = -1;
+      for (int u = 0; u < kFinRows && us < 0; ++u) {
+        for (int w = 0; w < kFinW; ++w) {
+          const uint32_t c = s_tw[u][w];
+          if (cum + c >= need) {
+            us = u;
+            ws = w;
+            break;
+          }
+          cum += c;
         }
-        cum += rt[u];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) part[c] += rsum[u][c];
       }
-    } else {
-      for (int yy = ra; yy < rb; ++yy) {
-        const RowSel r = fd.rowsel[yy];
-        if (cum + r.ties >= need) {
-          s_misc[2] = yy;
-          s_misc[3] = (int)cum;
-          break;
-        }
-        cum += r.ties;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) part[c] += r.tsum[c];
+      if (us >= 0) {  // block-uniform; that wave's 64 rows hold the need-th tie
+        const uint32_t tl = s_ties[us][64 * ws + lane];
+        const uint32_t incl = wave_incl_scan(tl);
+        const int L = __ffsll((long long)__ballot(cum + incl >= need)) - 1;
+        before = cum + __builtin_amdgcn_readlane(incl - tl, L);
+        rstar = base + 64 * ws + L + kFinT * us;
       }
     }
+    // sums over D > vstar (every row) and tie sums of the rows before the cut row
+#pragma unroll
+    for (int u = 0; u < kFinRows; ++u) {
+      const int y = base + tid + kFinT * u;
+      const bool tb = rstar < 0 || y < rstar;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += r[u].gsum[c] + (tb ? r[u].tsum[c] : 0ull);
+      acc[3] += r[u].above;
+    }
+    for (int u = 0; u < kFinRows; ++u)
+      for (int w = 0; w < kFinW; ++w) carry += s_tw[u][w];
   }
-  __syncthreads();
-  const int rstar = s_misc[2];
-  const uint32_t before = (uint32_t)s_misc[3];
-  if (rstar < 0) {
+  if (rstar < 0) {  // fewer ties in the records than the histogram promises
     if (tid == 0) store_no_cut(fd, K, vstar);
     return;
   }
-  if (rb <= rstar) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) part[c] = ts[c];
-  }
 
-  // the cut row: the first (need - before) ties in raster order.  Thread t
-  // owns bytes [16 t, 16 t + 16) of each kFinT*16-pixel segment, so thread
-  // order is raster order inside a segment; an exclusive block scan of the
-  // per-thread tie counts says how many of its ties each thread takes.
+  // 3. the first k = need - before ties of the cut row.  Thread t owns pixels
+  // [16 t, 16 t + 16) of each kFinT*16-pixel segment, so thread order is
+  // raster order inside a segment.  I is loaded with D, before the thread
+  // knows whether it takes any of its ties.
   const uint32_t k = need - before;
   const uint8_t* Drow = fd.D + (int64_t)rstar * fd.D_pitch;
   const uint8_t* Irow = fd.src + (int64_t)rstar * fd.src_pitch;
   uint32_t run = 0;  // ties in earlier segments (block-uniform)
-  unsigned long long cs[3] = {0, 0, 0};
   int cut_x = -1;
   for (int seg = 0; seg < W && run < k; seg += 16 * kFinT) {
     const int x0 = seg + 16 * tid;
-    uint32_t dw[4] = {0u, 0u, 0u, 0u};
+    const bool vec = (fd.flags & kFdAligned) && x0 + 16 <= W;
+    uint32_t dw[4] = {0u, 0u, 0u, 0u}, iw[12] = {};
     if (x0 < W) {
       const uint4 dv = *reinterpret_cast<const uint4*>(Drow + x0);  // rows are padded to 16 bytes
       dw[0] = dv.x; dw[1] = dv.y; dw[2] = dv.z; dw[3] = dv.w;
+    }
+    if (vec) {
+      const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow + 3 * x0);
+#pragma unroll
+      for (int j = 0; j < 12; ++j) iw[j] = q4[j];
     }
     uint32_t mask = 0;
 #pragma unroll
@@ -846,46 +876,33 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
       if (x0 + j < W && d == vstar) mask |= 1u << j;
     }
     const uint32_t cnt = (uint32_t)__popc(mask);
-    uint32_t seg_total;
-    const uint32_t ex = block_scan_total<kFinW>(cnt, s_u32, seg_total) - cnt;
+    const uint32_t ci = wave_incl_scan(cnt);
+    if (lane == 63) s_cnt[wv] = ci;
+    __syncthreads();
+    uint32_t ex = ci - cnt, seg_total = 0;
+    for (int w = 0; w < kFinW; ++w) {
+      const uint32_t c = s_cnt[w];
+      if (w < wv) ex += c;
+      seg_total += c;
+    }
     const uint32_t avail = (run + ex < k) ? min(cnt, k - run - ex) : 0u;
-    if (avail) {
-      uint32_t iw[12];
-      const bool vec = (fd.flags & kFdAligned) && x0 + 16 <= W;
-      if (vec) {
-        const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow + 3 * x0);
+    uint32_t m = mask;
+    for (uint32_t i = 0; i < avail; ++i) {
+      const int j = __ffs(m) - 1;
+      m &= m - 1;
 #pragma unroll
-        for (int j = 0; j < 12; ++j) iw[j] = q4[j];
+      for (int c = 0; c < 3; ++c) {
+        const int byte = 3 * j + c;
+        acc[c] += vec ? (iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu : (uint32_t)Irow[3 * (x0 + j) + c];
       }
-      uint32_t m = mask;
-      for (uint32_t i = 0; i < avail; ++i) {
-        const int j = __ffs(m) - 1;
-        m &= m - 1;
-        uint32_t px[3];
-        if (vec) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int byte = 3 * j + c;
-            px[c] = (iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu;
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) px[c] = Irow[3 * (x0 + j) + c];
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) cs[c] += px[c];
-        if (run + ex + i + 1 == k) cut_x = x0 + j;
-      }
+      if (run + ex + i + 1 == k) cut_x = x0 + j;
     }
     run += seg_total;
+    if (seg + 16 * kFinT < W && run < k) __syncthreads();  // s_cnt is rewritten by the next segment
   }
 
-  // S^c = sum over D > vstar (all rows) + ties of rows before the cut row + the cut row's share
-  unsigned long long v[5];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) v[c] = gs[c] + part[c] + cs[c];
-  v[3] = above;
-  v[4] = (unsigned long long)(cut_x + 1);  // 0 = none; at most one thread holds the cut
+  // 4. the block's sums
+  const unsigned long long v[5] = {acc[0], acc[1], acc[2], acc[3], (unsigned long long)(cut_x + 1)};  // one thread holds the cut
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     const unsigned long long x = wave_sum(v[i]);
@@ -1186,28 +1203,34 @@ __device__ __forceinline__ ReconConsts recon_consts(const FrameDev& fd) {
 // Offline mode, after the airlight: per pixel, the guide as an exact integer
 // L = 299 R + 587 G + 114 B (= 255000 * BT.601 luma in [0,1]) and the coarse
 // t of Eqs. (4)-(5) in fixed point P = rint(t * 2^28) (exact for t >= 1/16).
-// A block covers 8 rows x 256 columns (one column per thread) and also writes
-// each column's exact sums of L, P, L^2, L*P over its aligned 8-row chunk,
-// which give the guided-filter kernels their initial windows cheaply.
+// A block covers 64 columns x one group of kGroupChunks aligned 8-row chunks;
+// wave w takes chunk w, lane l one column.  Besides the LP map it writes, per
+// column and chunk, the exact sums of L, P, L^2, L*P over the chunks of its
+// group up to and including this one (a prefix inside the group), from which
+// the guided-filter kernels form a window's whole-chunk sums with at most
+// four loads.
 template <int TX>
-__global__ __launch_bounds__(256) void k_gf_prep(Batch b) {
+__global__ __launch_bounds__(64 * kGroupChunks) void k_gf_prep(Batch b) {
+  __shared__ unsigned long long s_c[4][kGroupChunks][64];   // chunk sums of L, P, L^2, L*P
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
   const int tile = blk - b.tile0[f];
   const int W = fd.W, H = fd.H;
-  const int cblocks = (W + kGfCols - 1) / kGfCols;
-  const int ch = tile / cblocks;
-  const int x = (tile - ch * cblocks) * kGfCols + (int)threadIdx.x;
-  if (x >= W) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cblocks = (W + 63) / 64;
+  const int grp = tile / cblocks;
+  const int x = (tile - grp * cblocks) * 64 + lane;
+  const int ch = grp * kGroupChunks + wv;
+  const int y0 = ch * kChunk, n = max(0, min(kChunk, H - y0));
+  const bool ok = x < W && n > 0;
   const TxConsts k = tx_consts(fd);
-  const int y0 = ch * kChunk, n = min(kChunk, H - y0);
   uint32_t rgb[kChunk], e[kChunk];
 #pragma unroll
   for (int i = 0; i < kChunk; ++i) {
     rgb[i] = 0u;
     e[i] = 0u;
-    if (i < n) {
+    if (ok && i < n) {
       const uint8_t* ip = fd.src + (int64_t)(y0 + i) * fd.src_pitch + 3 * x;
       rgb[i] = (uint32_t)ip[0] | ((uint32_t)ip[1] << 8) | ((uint32_t)ip[2] << 16);
       if (TX == TSRC_HE) {
@@ -1216,11 +1239,11 @@ __global__ __launch_bounds__(256) void k_gf_prep(Batch b) {
       }
     }
   }
-  uint32_t sL = 0, sP = 0;
-  unsigned long long sLL = 0, sLP = 0;
+  uint32_t sL = 0;
+  unsigned long long sP = 0, sLL = 0, sLP = 0;
 #pragma unroll
   for (int i = 0; i < kChunk; ++i) {
-    if (i < n) {
+    if (ok && i < n) {
       const uint32_t r = rgb[i] & 0xFFu, g = (rgb[i] >> 8) & 0xFFu, bl = (rgb[i] >> 16) & 0xFFu;
       float t;
       if (TX == TSRC_HE) {
@@ -1237,8 +1260,19 @@ __global__ __launch_bounds__(256) void k_gf_prep(Batch b) {
       sLP += (unsigned long long)L * P;
     }
   }
-  fd.S8a[(int64_t)ch * W + x] = make_uint2(sL, sP);
-  fd.S8b[(int64_t)ch * W + x] = make_ulonglong2(sLL, sLP);
+  s_c[0][wv][lane] = sL;
+  s_c[1][wv][lane] = sP;
+  s_c[2][wv][lane] = sLL;
+  s_c[3][wv][lane] = sLP;
+  __syncthreads();
+  if (!ok) return;
+  unsigned long long v[4] = {0ull, 0ull, 0ull, 0ull};
+  for (int c = 0; c <= wv; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] += s_c[q][c][lane];
+  }
+  fd.PGa[(int64_t)ch * W + x] = make_ulonglong2(v[0], v[1]);
+  fd.PGb[(int64_t)ch * W + x] = make_ulonglong2(v[2], v[3]);
 }
 
 // Rows [ya, yb] of one column as: head rows, whole aligned 8-row chunks
@@ -1488,10 +1522,34 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
     const unsigned long long L = v.x, P = v.y;
     sL -= L; sLL -= L * L; sP -= P; sLP -= L * P;
   };
-  if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
+  if (g.colin) {  // the initial window from head rows, whole 8-row chunks and tail rows
     const WindowSplit w = split_window(max(0, g.y0 - r), min(H - 1, g.y0 + r), H);
-    // the rows outside whole chunks, head then tail, kEdgeBatch per round trip
     const int nhead = w.head_end - w.ya, nedge = nhead + (w.yb + 1 - w.tail_beg);
+    // chunks c0..c1 from the prefixes inside their groups: + PG[c1]
+    // - PG[c0 - 1] (when c0 does not start its group) + the last prefix of
+    // every group before c1's.  A window of at most 2 kMaxRadius + 1 rows
+    // spans at most three groups.  All of it, and the first kEdgeBatch edge
+    // rows, is loaded in one round trip.
+    const int c1 = w.c0 + w.nch - 1;
+    const int g0 = w.c0 / kGroupChunks, g1 = c1 / kGroupChunks;
+    const bool sub0 = w.nch > 0 && (w.c0 % kGroupChunks) != 0;
+    const int64_t xl = g.xl;
+    ulonglong2 pa[4], pb[4];   // + PG[c1], - PG[c0 - 1], + the ends of groups g0 and g0 + 1
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int c = -1;
+      if (w.nch > 0) {
+        if (i == 0) c = c1;
+        else if (i == 1) c = sub0 ? w.c0 - 1 : -1;
+        else if (g0 + (i - 2) < g1) c = (g0 + (i - 2)) * kGroupChunks + kGroupChunks - 1;
+      }
+      pa[i] = make_ulonglong2(0ull, 0ull);
+      pb[i] = make_ulonglong2(0ull, 0ull);
+      if (c >= 0) {
+        pa[i] = fd.PGa[(int64_t)c * W + xl];
+        pb[i] = fd.PGb[(int64_t)c * W + xl];
+      }
+    }
     for (int e0 = 0; e0 < nedge; e0 += kEdgeBatch) {
       uint2 ev[kEdgeBatch];
 #pragma unroll
@@ -1503,26 +1561,11 @@ __global__ __launch_bounds__(256) void k_gf_ab(Batch b) {
 #pragma unroll
       for (int i = 0; i < kEdgeBatch; ++i) add(ev[i]);
     }
-    for (int c = 0; c < w.nch; c += kChunkBatch) {
-      uint2 ca[kChunkBatch];
-      ulonglong2 cb[kChunkBatch];
-#pragma unroll
-      for (int i = 0; i < kChunkBatch; ++i) {
-        ca[i] = make_uint2(0u, 0u);
-        cb[i] = make_ulonglong2(0ull, 0ull);
-        if (c + i < w.nch) {
-          ca[i] = fd.S8a[(w.c0 + c + i) * W + g.xl];
-          cb[i] = fd.S8b[(w.c0 + c + i) * W + g.xl];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < kChunkBatch; ++i) {
-        sL += ca[i].x;
-        sP += ca[i].y;
-        sLL += cb[i].x;
-        sLP += cb[i].y;
-      }
-    }
+    // entries not loaded are zero; modular u64 arithmetic keeps the sums exact
+    sL += pa[0].x + pa[2].x + pa[3].x - pa[1].x;
+    sP += pa[0].y + pa[2].y + pa[3].y - pa[1].y;
+    sLL += pb[0].x + pb[2].x + pb[3].x - pb[1].x;
+    sLP += pb[0].y + pb[2].y + pb[3].y - pb[1].y;
   }
   // entering/leaving rows of output row yn.  The loads are unconditional
   // (rows clamped into the frame) so that the number of loads in flight is
@@ -1801,8 +1844,14 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
   long long sa = 0, sb = 0;
   if (g.colin) {  // the initial window from head rows, 8-row chunk sums and tail rows
     const WindowSplit w = split_window(max(0, g.y0 - r), min(H - 1, g.y0 + r), H);
-    // the rows outside whole chunks, head then tail, kEdgeBatch per round trip
     const int nhead = w.head_end - w.ya, nedge = nhead + (w.yb + 1 - w.tail_beg);
+    // the chunk sums (all of a window's, with int32 a, b) and the first
+    // kEdgeBatch edge rows in one round trip
+    constexpr int kQC = AB64 ? 8 : 2 * kGroupChunks;
+    longlong2 cs[kQC];
+#pragma unroll
+    for (int i = 0; i < kQC; ++i)
+      cs[i] = (i < w.nch) ? fd.S8ab[(int64_t)(w.c0 + i) * W + g.xl] : make_longlong2(0ll, 0ll);
     for (int e0 = 0; e0 < nedge; e0 += kEdgeBatch) {
       ABV ev[kEdgeBatch];
 #pragma unroll
@@ -1817,13 +1866,17 @@ __global__ __launch_bounds__(256) void k_gf_q(Batch b) {
         sb += ev[i].y;
       }
     }
-    for (int c = 0; c < w.nch; c += kChunkBatch) {
-      longlong2 cs[kChunkBatch];
 #pragma unroll
-      for (int i = 0; i < kChunkBatch; ++i)
-        cs[i] = (c + i < w.nch) ? fd.S8ab[(w.c0 + c + i) * W + g.xl] : make_longlong2(0ll, 0ll);
+    for (int i = 0; i < kQC; ++i) {
+      sa += cs[i].x;
+      sb += cs[i].y;
+    }
+    for (int c = kQC; c < w.nch; c += kQC) {
 #pragma unroll
-      for (int i = 0; i < kChunkBatch; ++i) {
+      for (int i = 0; i < kQC; ++i)
+        cs[i] = (c + i < w.nch) ? fd.S8ab[(int64_t)(w.c0 + c + i) * W + g.xl] : make_longlong2(0ll, 0ll);
+#pragma unroll
+      for (int i = 0; i < kQC; ++i) {
         sa += cs[i].x;
         sb += cs[i].y;
       }
@@ -1995,22 +2048,8 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
   const int per_row = (W + kReconPx - 1) / kReconPx;
   const int y = tile / per_row;
   const int xb = (tile - y * per_row) * kReconPx + 4 * (int)threadIdx.x;
-  const TxConsts k = tx_consts(fd);
-  ReconConsts rc = recon_consts(fd);
-  if (PHASE != 3 && (fd.flags & kFdGammaAdaptive)) adaptive_gamma(fd, rc, s_gam);   // uniform per block
-  const bool wb = (PHASE == 1 || PHASE == 2) && (fd.flags & kFdWbPercentile);   // block-uniform
-  float gain[3] = {1.f, 1.f, 1.f};
-  WbConsts wbc;
-  if (PHASE == 2) {
-    if (wb) wbc = wb_points(fd, s_wtmp, s_wpts);
-    else cb_gains(fd, gain, s_red);
-  }
-  if (PHASE == 1 && wb) {
-    wb_hist_zero(s_wbh);
-    __syncthreads();
-  }
-  unsigned long long acc[3] = {0ull, 0ull, 0ull};
-
+  // the pixels' loads go out first: the frame-wide constants below (gains,
+  // points, adaptive gamma) take a round trip and a barrier of their own
   constexpr int NG = 2;
   int x0[NG], nx[NG];
   uint32_t iw[NG][3], ew[NG][3];
@@ -2027,14 +2066,43 @@ __global__ __launch_bounds__(256) void k_recon(Batch b) {
       if (TSRC == TSRC_HE) load_rgb12(fd.E + (int64_t)y * fd.E_pitch + 3 * x0[q], nx[q], true, ew[q]);
       if (TSRC == TSRC_TMAP) {
         const int64_t pi = (int64_t)y * W + x0[q];
+        if (nx[q] == 4 && (pi & 3) == 0) {  // one 16- (8-) byte load
+          if (FP16) {
+            const uint2 h = *reinterpret_cast<const uint2*>(reinterpret_cast<const __half*>(fd.tmap) + pi);
+            tm[q][0] = __half2float(__ushort_as_half((unsigned short)(h.x & 0xFFFFu)));
+            tm[q][1] = __half2float(__ushort_as_half((unsigned short)(h.x >> 16)));
+            tm[q][2] = __half2float(__ushort_as_half((unsigned short)(h.y & 0xFFFFu)));
+            tm[q][3] = __half2float(__ushort_as_half((unsigned short)(h.y >> 16)));
+          } else {
+            const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(fd.tmap) + pi);
+            tm[q][0] = v.x; tm[q][1] = v.y; tm[q][2] = v.z; tm[q][3] = v.w;
+          }
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < nx[q])
-            tm[q][i] = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi + i])
-                            : reinterpret_cast<const float*>(fd.tmap)[pi + i];
+          for (int i = 0; i < 4; ++i)
+            if (i < nx[q])
+              tm[q][i] = FP16 ? __half2float(reinterpret_cast<const __half*>(fd.tmap)[pi + i])
+                              : reinterpret_cast<const float*>(fd.tmap)[pi + i];
+        }
       }
     }
   }
+
+  const TxConsts k = tx_consts(fd);
+  ReconConsts rc = recon_consts(fd);
+  if (PHASE != 3 && (fd.flags & kFdGammaAdaptive)) adaptive_gamma(fd, rc, s_gam);   // uniform per block
+  const bool wb = (PHASE == 1 || PHASE == 2) && (fd.flags & kFdWbPercentile);   // block-uniform
+  float gain[3] = {1.f, 1.f, 1.f};
+  WbConsts wbc;
+  if (PHASE == 2) {
+    if (wb) wbc = wb_points(fd, s_wtmp, s_wpts);
+    else cb_gains(fd, gain, s_red);
+  }
+  if (PHASE == 1 && wb) {
+    wb_hist_zero(s_wbh);
+    __syncthreads();
+  }
+  unsigned long long acc[3] = {0ull, 0ull, 0ull};
 
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
@@ -2216,10 +2284,12 @@ hipError_t launch_select(Batch b, hipStream_t s) {
 
 hipError_t launch_gf_prep(Batch b, const GroupKey& g, hipStream_t s) {
   const int nblk = fill_tiles(b, [](const FrameDev& f) {
-    return ((f.W + kGfCols - 1) / kGfCols) * ((f.H + 7) / 8);
+    const int nch = (f.H + kChunk - 1) / kChunk;
+    return ((f.W + 63) / 64) * ((nch + kGroupChunks - 1) / kGroupChunks);
   });
-  if (g.tx == HZD_TX_HE) hipLaunchKernelGGL((k_gf_prep<TSRC_HE>), dim3(nblk), dim3(256), 0, s, b);
-  else hipLaunchKernelGGL((k_gf_prep<TSRC_PAPER>), dim3(nblk), dim3(256), 0, s, b);
+  constexpr int nt = 64 * kGroupChunks;
+  if (g.tx == HZD_TX_HE) hipLaunchKernelGGL((k_gf_prep<TSRC_HE>), dim3(nblk), dim3(nt), 0, s, b);
+  else hipLaunchKernelGGL((k_gf_prep<TSRC_PAPER>), dim3(nblk), dim3(nt), 0, s, b);
   return hipGetLastError();
 }
 
