@@ -182,7 +182,8 @@ typedef struct hzd_params {
 } hzd_params;
 
 /* One frame: device pointers and geometry (see the conventions above).
- * width, height (>= 1, width * height < 2^31) are the input size; dst and
+ * width, height (>= 1, width * height < 2^31, width < 2^24; wider frames
+ * return HZD_E_UNSUPPORTED) are the input size; dst and
  * the aux outputs have the output size, which is the input size unless the
  * frame's params resize it.  src and dst must not overlap.
  * params: NULL = the params given to the call; in a batch, a per-frame

@@ -93,6 +93,7 @@ int validate_size(const hzd_params& p, int W, int H, int idx) {
   if (W < 1 || H < 1) return fail(HZD_E_INVAL, "frame %d: size %dx%d", idx, W, H);
   if ((int64_t)W * (int64_t)H >= (int64_t(1) << 31))
     return fail(HZD_E_INVAL, "frame %d: width*height >= 2^31", idx);
+  if (W > kMaxWidth) return fail(HZD_E_UNSUPPORTED, "frame %d: width %d beyond %d", idx, W, kMaxWidth);
   if (p.resize_width != 0 && (W > kResizeMaxIn || H > kResizeMaxIn))
     return fail(HZD_E_UNSUPPORTED, "frame %d: resize input %dx%d beyond %d per side", idx, W, H, kResizeMaxIn);
   return HZD_OK;

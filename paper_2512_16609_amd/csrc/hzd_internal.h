@@ -32,13 +32,16 @@ struct FrameState {
 static_assert(sizeof(FrameState) <= 40960, "FrameState too large");
 
 // Per-row record of the airlight selection pass: the row's pixels with
-// D == vstar (ties) and D > vstar, counted and summed per channel.
+// D == vstar (ties) and D > vstar, counted and summed per channel.  A row's
+// sums stay below W * 255 < 2^32 (frames are at most kMaxWidth wide).
+constexpr int kMaxWidth = (1 << 24) - 1;
 struct RowSel {
-  uint32_t ties, above, pad0, pad1;
-  unsigned long long tsum[3];
-  unsigned long long gsum[3];
+  uint32_t ties, above;
+  uint32_t tsum[3];
+  uint32_t gsum[3];
 };
-static_assert(sizeof(RowSel) == 64, "RowSel layout");
+static_assert(sizeof(RowSel) == 32, "RowSel layout");
+static_assert((unsigned long long)kMaxWidth * 255ull < (1ull << 32), "a row's sums fit 32 bits");
 
 // Everything one frame needs on the device, passed by value in kernel arguments.
 struct FrameDev {

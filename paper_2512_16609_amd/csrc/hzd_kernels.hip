@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   wave_vstar(fd.st, (uint32_t)fd.K, vstar, cnt_gt);
   (void)cnt_gt;
   if (!row_ok) return;
-  unsigned long long gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;
+  uint32_t gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;   // < W * 255 < 2^32
   uint32_t gN = 0, tN = 0;
   const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
   for (int seg = 0; seg < W; seg += 1024 * kSelVec) {
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   if (gN) { gR = wave_sum(gR); gG = wave_sum(gG); gB = wave_sum(gB); }
   if (lane == 0) {
     RowSel r;
-    r.ties = tN; r.above = gN; r.pad0 = 0; r.pad1 = 0;
+    r.ties = tN; r.above = gN;
     r.tsum[0] = tR; r.tsum[1] = tG; r.tsum[2] = tB;
     r.gsum[0] = gR; r.gsum[1] = gG; r.gsum[2] = gB;
     fd.rowsel[y] = r;
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
         r[u].ties = 0u;
         r[u].above = 0u;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r[u].tsum[c] = r[u].gsum[c] = 0ull;
+        for (int c = 0; c < 3; ++c) r[u].tsum[c] = r[u].gsum[c] = 0u;
       }
     }
   };
@@ -808,21 +808,16 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
       if (lane == 0) s_tw[u][wv] = wt;
     }
     __syncthreads();
+    // the round's wave totals in raster order, one per lane (sweep-major)
+    static_assert(kFinRows * kFinW <= 64, "one lane per wave total");
+    const uint32_t tw = lane < kFinRows * kFinW ? (&s_tw[0][0])[lane] : 0u;
+    const uint32_t twi = wave_incl_scan(tw);
     if (rstar < 0) {
-      uint32_t cum = carry;
-      int us = -1, ws = -1;
-      for (int u = 0; u < kFinRows && us < 0; ++u) {
-        for (int w = 0; w < kFinW; ++w) {
-          const uint32_t c = s_tw[u][w];
-          if (cum + c >= need) {
-            us = u;
-            ws = w;
-            break;
-          }
-          cum += c;
-        }
-      }
-      if (us >= 0) {  // block-uniform; that wave's 64 rows hold the need-th tie
+      const unsigned long long hit = __ballot(carry + twi >= need);
+      if (hit) {  // block-uniform; the wave total at lane J holds the need-th tie
+        const int J = __ffsll((long long)hit) - 1;
+        const int us = J / kFinW, ws = J % kFinW;
+        const uint32_t cum = carry + __builtin_amdgcn_readlane(twi - tw, J);
         const uint32_t tl = s_ties[us][64 * ws + lane];
         const uint32_t incl = wave_incl_scan(tl);
         const int L = __ffsll((long long)__ballot(cum + incl >= need)) - 1;
@@ -836,11 +831,10 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
       const int y = base + tid + kFinT * u;
       const bool tb = rstar < 0 || y < rstar;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] += r[u].gsum[c] + (tb ? r[u].tsum[c] : 0ull);
+      for (int c = 0; c < 3; ++c) acc[c] += (unsigned long long)r[u].gsum[c] + (tb ? r[u].tsum[c] : 0u);
       acc[3] += r[u].above;
     }
-    for (int u = 0; u < kFinRows; ++u)
-      for (int w = 0; w < kFinW; ++w) carry += s_tw[u][w];
+    carry += __builtin_amdgcn_readlane(twi, 63);
   }
   if (rstar < 0) {  // fewer ties in the records than the histogram promises
     if (tid == 0) store_no_cut(fd, K, vstar);

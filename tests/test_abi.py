@@ -96,6 +96,7 @@ def test_frame_validation(L):
     assert call_frame(L, p, w=0) == hzd.HZD_E_INVAL
     assert call_frame(L, p, h=-3) == hzd.HZD_E_INVAL
     assert call_frame(L, p, w=65536, h=32768) == hzd.HZD_E_INVAL        # W*H >= 2^31
+    assert call_frame(L, p, w=1 << 24, h=1) == hzd.HZD_E_UNSUPPORTED    # a row's sums must fit 32 bits
     assert call_frame(L, p, sp=100) == hzd.HZD_E_INVAL                  # pitch < 3W
     assert call_frame(L, p, src=0) == hzd.HZD_E_INVAL                   # NULL src
     assert call_frame(L, p, dst=FAKE_SRC + 100) == hzd.HZD_E_INVAL      # overlap
