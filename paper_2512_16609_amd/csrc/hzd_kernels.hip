@@ -1052,26 +1052,25 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   // lane l takes vector l of that row (W <= 1024) and a second scan finds the pixel
   if (wv == 0) {
     constexpr int RPL = kOneRows / 64;
-    uint32_t t = 0;
-#pragma unroll 8
+    uint32_t tc[RPL], t = 0;   // the lane's rows' tie counts stay in registers for the search
+#pragma unroll
     for (int k = 0; k < RPL; ++k) {
       const int y = RPL * lane + k;
-      t += y < H ? s_tc[y] : 0u;
+      tc[k] = y < H ? s_tc[y] : 0u;
+      t += tc[k];
     }
     const uint32_t incl = wave_incl_scan(t);
     uint32_t cum = incl - t;
     int ycut = -1;
     uint32_t before = 0;
     if (cum < need && need <= incl) {
+#pragma unroll
       for (int k = 0; k < RPL; ++k) {
-        const int y = RPL * lane + k;
-        const uint32_t c = y < H ? s_tc[y] : 0u;
-        if (cum + c >= need) {
-          ycut = y;
+        if (ycut < 0 && cum + tc[k] >= need) {
+          ycut = RPL * lane + k;
           before = cum;
-          break;
         }
-        cum += c;
+        if (ycut < 0) cum += tc[k];
       }
     }
     // the lane that found the row broadcasts it (-1 everywhere if none did)
@@ -1127,12 +1126,27 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     if (!__any(mem != 0u)) continue;
     const uint8_t* Irow = fd.src + (int64_t)max(vy[i], 0) * fd.src_pitch + 3 * vx[i];
     acc[3] += (unsigned long long)__popc(mem);
-    while (mem) {
-      const int j = __ffs(mem) - 1;
-      mem &= mem - 1;
-      acc[0] += Irow[3 * j];
-      acc[1] += Irow[3 * j + 1];
-      acc[2] += Irow[3 * j + 2];
+    if (!mem) continue;
+    // the lane's 16 pixels in one round trip when the rows are dword aligned
+    if ((fd.flags & kFdAligned) && vx[i] + 16 <= W) {
+      uint32_t iw[12];
+      const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow);
+#pragma unroll
+      for (int j = 0; j < 12; ++j) iw[j] = q4[j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (!((mem >> j) & 1u)) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += (iw[(3 * j + c) >> 2] >> (8 * ((3 * j + c) & 3))) & 0xFFu;
+      }
+    } else {
+      while (mem) {
+        const int j = __ffs(mem) - 1;
+        mem &= mem - 1;
+        acc[0] += Irow[3 * j];
+        acc[1] += Irow[3 * j + 1];
+        acc[2] += Irow[3 * j + 2];
+      }
     }
   }
 #pragma unroll
