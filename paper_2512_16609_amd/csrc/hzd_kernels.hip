@@ -619,21 +619,13 @@ __device__ __forceinline__ T block_scan_total(T v, T* s_tmp, T& total) {
   return x + add;
 }
 
-// vstar and #{D > vstar} from the slotted histogram, in one wave with no LDS
-// and no barrier: lane l sums bins 4(63 - l) .. 4(63 - l) + 3 over the slots,
-// so the lanes in order, and each lane's bins from the top, hold the counts by
-// descending value; an inclusive scan gives #{D >= v}, and vstar is the first
-// v from the top at which it reaches K.  A histogram that never reaches K
-// (inconsistent state) gives vstar 0, which the final consistency test flags.
-__device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt) {
-  const int lane = threadIdx.x & 63;
-  const int b0 = 4 * (63 - lane);
-  uint4 c = make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-  for (int k = 0; k < kHistSlots; ++k) {
-    const uint4 h = *reinterpret_cast<const uint4*>(&st->hist[k][b0]);
-    c.x += h.x; c.y += h.y; c.z += h.z; c.w += h.w;
-  }
+// vstar and #{D > vstar} in one wave from per-lane bin counts: lane l holds
+// the counts of bins 4(63 - l) .. 4(63 - l) + 3 in c.x .. c.w, so the lanes in
+// order, and each lane's bins from the top, hold the counts by descending
+// value; an inclusive scan gives #{D >= v}, and vstar is the first v from the
+// top at which it reaches K.  Counts that never reach K (an inconsistent
+// state) give vstar 0, which the final consistency test flags.
+__device__ __forceinline__ void vstar_from_lane_counts(uint4 c, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt) {
   // in-lane counts of D >= b0 + 3, b0 + 2, b0 + 1, b0
   const uint32_t l3 = c.w, l2 = l3 + c.z, l1 = l2 + c.y, l0 = l1 + c.x;
   const uint32_t incl = wave_incl_scan(l0);
@@ -652,6 +644,18 @@ __device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uin
   } else {
     vstar = top; cnt_gt = ex + a1;
   }
+}
+
+// The same from the frame's slotted histogram, with no LDS and no barrier.
+__device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt) {
+  const int b0 = 4 * (63 - (int)(threadIdx.x & 63));
+  uint4 c = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+  for (int k = 0; k < kHistSlots; ++k) {
+    const uint4 h = *reinterpret_cast<const uint4*>(&st->hist[k][b0]);
+    c.x += h.x; c.y += h.y; c.z += h.z; c.w += h.w;
+  }
+  vstar_from_lane_counts(c, K, vstar, cnt_gt);
 }
 
 __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
@@ -917,33 +921,39 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
 // Eq. (3) for a small frame in one 1024-thread block.  D is read once: its
 // 16-byte vectors are numbered tile by tile (k_dark's 64x32 tiles, 128 vector
 // slots each: 32 rows x 4 vectors), and thread t holds the slots t, t + 1024,
-// ..., so a wave holds half of one tile.  The block
-//   1. sums the per-tile 256-bin histograms k_dark wrote -> vstar and
-//      #{D > vstar}, and each tile's largest D;
-//   2. counts the ties per row, in the tiles whose largest D reaches vstar
-//      (a wave-uniform test: every other wave skips); wave 0 scans the rows
-//      for the one holding the need-th tie, and the ties of that row (kept in
-//      LDS) for the cut pixel;
-//   3. sums I exactly over {D > vstar} U {D == vstar, index <= cutoff}, again
-//      only in those tiles;
-// and forms A = alpha S / K.  It also zeroes the frame state's sums for the
-// later passes (colour balance, luma, white balance); with the per-tile
-// histograms written whole by k_dark, nothing of the frame's state needs
-// zeroing before the frame, so the init kernel is not run.  Used when W <=
-// 1024 (the cut row is one vector per lane of a wave) and the frame has at
-// most kOneTiles tiles (select_one_fits).
+// ..., so a wave holds half of one tile.  Thread t also loads bin t % 256 of
+// the per-tile histograms k_dark wrote, for every fourth tile.  After one
+// barrier (LDS holds each quarter's histogram sums and each tile's largest D,
+// written without atomics), every wave
+//   1. forms vstar and #{D > vstar} itself, and which tiles can hold members
+//      of the set (largest D >= vstar: a wave-uniform test);
+//   2. counts the ties per row in those tiles and sums I over their pixels
+//      with D > vstar, which belong to the set whatever the cut;
+// then, after a barrier, wave 0 scans the rows for the one holding the
+// need-th tie and that row's ties (in LDS) for the cut pixel; after another,
+// the ties up to the cut are summed, and thread 0 forms A = alpha S / K.  The
+// kernel also zeroes the frame state's sums for the later passes (colour
+// balance, luma, white balance); with the per-tile histograms written whole
+// by k_dark, nothing of the frame's state needs zeroing before the frame, so
+// the init kernel is not run.  Used when W <= 1024 (the cut row is one vector
+// per lane of a wave) and the frame has at most kOneTiles tiles
+// (select_one_fits).
 constexpr int kOneT = 1024, kOneW = kOneT / 64;
 constexpr int kOneRows = 2048;
 constexpr int kOneTileLoads = 16;                 // per-tile histogram loads per thread
 constexpr int kOneTiles = 4 * kOneTileLoads;      // tiles of a frame on this path (64)
 static_assert(kOneTiles * 128 == kOneT * kOneVecMax, "every vector slot of every tile has a thread");
 
+// Row y's tie count sits at y + y / 32, so that the 64 lanes of a wave that
+// read rows 32 l + k hit distinct LDS banks.
+__device__ __forceinline__ int one_row_slot(int y) { return y + (y >> 5); }
+
 template <int NVT>
 __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
-  __shared__ uint32_t s_hist[256];
-  __shared__ uint32_t s_tmax[kOneTiles];  // the largest D of each k_dark tile
-  __shared__ uint32_t s_tc[kOneRows];     // ties per row
-  __shared__ uint4 s_D[NVT * kOneT];      // D by slot, for the scan of the cut row
+  __shared__ uint4 s_h4[4][64];                  // [tile quarter q][bins 4i .. 4i + 3]: histogram sums over the quarter's tiles
+  __shared__ uint32_t s_tm4[4][kOneTiles];       // [bin quarter][tile]: 1 + the quarter's largest nonzero bin of the tile (0: none)
+  __shared__ uint32_t s_tc[kOneRows + kOneRows / 32];   // ties per row (one_row_slot)
+  __shared__ uint4 s_D[NVT * kOneT];             // D by slot, for the scan of the cut row
   __shared__ int s_misc[4];
   __shared__ unsigned long long s_red[kOneW][4];
   const FrameDev& fd = b.f[blockIdx.x];
@@ -953,9 +963,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   const uint32_t K = (uint32_t)fd.K;
   const int tiles_x = (W + 63) / 64, nt = dark_tiles(W, H);
 
-  for (int i = tid; i < H; i += kOneT) s_tc[i] = 0u;
-  if (tid < 256) s_hist[tid] = 0u;
-  if (tid < kOneTiles) s_tmax[tid] = 0u;
+  for (int i = tid; i < one_row_slot(H - 1) + 1; i += kOneT) s_tc[i] = 0u;
   // every load is issued before the first barrier
   uint4 dv[NVT];
   int vy[NVT], vx[NVT];   // vy < 0: no vector in this slot
@@ -983,68 +991,90 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     for (int i = tid; i < nz; i += kOneT) z[i] = 0u;
   }
   auto dbyte = [&](int i, int j) { return (((&dv[i].x)[j >> 2]) >> (8 * (j & 3))) & 0xFFu; };
-  __syncthreads();   // LDS zeroed
   {
     // a wave holds 64 consecutive bins of the same tiles: the highest of its
-    // nonzero bins per tile comes from one ballot, and one lane records it
+    // nonzero bins per tile comes from one ballot
     uint32_t hsum = 0;
 #pragma unroll
     for (int u = 0; u < kOneTileLoads; ++u) {
       hsum += hv[u];
-      const uint64_t nz = __ballot(hv[u] != 0u);
-      if (nz && lane == 0) atomicMax(&s_tmax[q + 4 * u], (uint32_t)((bin & ~63) + 63 - __clzll((long long)nz)));
+      const uint64_t nzb = __ballot(hv[u] != 0u);
+      if (lane == 0) s_tm4[bin >> 6][q + 4 * u] = nzb ? (uint32_t)((bin & ~63) + 64 - __clzll((long long)nzb)) : 0u;
     }
-    if (hsum) atomicAdd(&s_hist[bin], hsum);
+    reinterpret_cast<uint32_t*>(&s_h4[q][0])[bin] = hsum;
   }
 #pragma unroll
   for (int i = 0; i < NVT; ++i) s_D[tid + kOneT * i] = dv[i];
-  __syncthreads();   // histogram and tile maxima complete
+  __syncthreads();   // histogram quarters, tile maxima, D and the zeroed row counts in LDS
 
-  // 1. vstar and #{D > vstar}: wave 0 scans the bins from the top, 4 per lane
-  if (wv == 0) {
-    uint32_t c[4], sum = 0;
+  // 1. vstar and #{D > vstar}, in every wave
+  uint32_t vstar, cnt_gt;
+  {
+    uint4 c = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      c[k] = s_hist[255 - 4 * lane - k];
-      sum += c[k];
+      const uint4 h = s_h4[k][63 - lane];
+      c.x += h.x; c.y += h.y; c.z += h.z; c.w += h.w;
     }
-    const uint32_t incl = wave_incl_scan(sum);
-    uint32_t run = incl - sum;   // #{D > 255 - 4 lane}
-    if (run < K && K <= incl) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (run < K && K <= run + c[k]) {
-          s_misc[0] = 255 - 4 * lane - k;
-          s_misc[1] = (int)run;
-        }
-        run += c[k];
-      }
-    }
+    vstar_from_lane_counts(c, K, vstar, cnt_gt);
   }
-  __syncthreads();
-  const uint32_t vstar = (uint32_t)s_misc[0], cnt_gt = (uint32_t)s_misc[1];
   const uint32_t need = K - cnt_gt;   // >= 1
   // the slots of a wave lie in one tile: whether it can hold ties or members
-  // of the set is wave-uniform
+  // of the set is wave-uniform (a tile's largest D is >= vstar iff one of its
+  // bin quarters has a nonzero bin >= vstar)
   bool hot[NVT];
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
     const int tile = (tid + kOneT * i) >> 7;
-    hot[i] = tile < nt && s_tmax[tile] >= vstar;
+    hot[i] = false;
+    if (tile < nt) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hot[i] |= s_tm4[k][tile] > vstar;
+    }
   }
 
-  // 2. ties per row
+  // 2. ties per row; I summed over the pixels with D > vstar
+  unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};   // S^c, members
+  auto sum_members = [&](int i, uint32_t mem) {
+    const uint8_t* Irow = fd.src + (int64_t)max(vy[i], 0) * fd.src_pitch + 3 * vx[i];
+    acc[3] += (unsigned long long)__popc(mem);
+    if (!mem) return;
+    if ((fd.flags & kFdAligned) && vx[i] + 16 <= W) {  // the lane's 16 pixels in one round trip
+      uint32_t iw[12];
+      const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow);
+#pragma unroll
+      for (int j = 0; j < 12; ++j) iw[j] = q4[j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (!((mem >> j) & 1u)) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += (iw[(3 * j + c) >> 2] >> (8 * ((3 * j + c) & 3))) & 0xFFu;
+      }
+    } else {
+      while (mem) {
+        const int j = __ffs(mem) - 1;
+        mem &= mem - 1;
+        acc[0] += Irow[3 * j];
+        acc[1] += Irow[3 * j + 1];
+        acc[2] += Irow[3 * j + 2];
+      }
+    }
+  };
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
     if (!hot[i]) continue;
-    uint32_t m = 0u;
+    uint32_t mt = 0u, mg = 0u;
     if (vy[i] >= 0) {
       const int n = min(16, W - vx[i]);
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j < n && dbyte(i, j) == vstar) m |= 1u << j;
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t d = dbyte(i, j);
+        if (j < n && d == vstar) mt |= 1u << j;
+        if (j < n && d > vstar) mg |= 1u << j;
+      }
     }
-    if (m) atomicAdd(&s_tc[vy[i]], (uint32_t)__popc(m));
+    if (mt) atomicAdd(&s_tc[one_row_slot(vy[i])], (uint32_t)__popc(mt));
+    if (__any(mg != 0u)) sum_members(i, mg);
   }
   __syncthreads();
   // the cut row and the cut pixel, by wave 0: lane l sums rows [32 l, 32 l + 32),
@@ -1056,7 +1086,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
       const int y = RPL * lane + k;
-      tc[k] = y < H ? s_tc[y] : 0u;
+      tc[k] = y < H ? s_tc[one_row_slot(y)] : 0u;
       t += tc[k];
     }
     const uint32_t incl = wave_incl_scan(t);
@@ -1077,8 +1107,8 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     const uint64_t who = __ballot(ycut >= 0);
     if (who) {
       const int src = __ffsll((long long)who) - 1;
-      ycut = __shfl(ycut, src, 64);
-      before = __shfl(before, src, 64);
+      ycut = __builtin_amdgcn_readlane(ycut, src);
+      before = __builtin_amdgcn_readlane(before, src);
       const uint32_t kcut = need - before;   // the cut is the kcut-th tie of row ycut
       uint32_t m = 0u;
       if (16 * lane < W) {
@@ -1108,8 +1138,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     return;
   }
 
-  // 3. exact sums of I over the set (its members are few: K of them)
-  unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};
+  // 3. the ties up to the cut
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
     if (!hot[i]) continue;
@@ -1118,36 +1147,10 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
       const int n = min(16, W - vx[i]);
       const int base = vy[i] * W + vx[i];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const uint32_t d = dbyte(i, j);
-        if (j < n && (d > vstar || (d == vstar && base + j <= cutoff))) mem |= 1u << j;
-      }
+      for (int j = 0; j < 16; ++j)
+        if (j < n && dbyte(i, j) == vstar && base + j <= cutoff) mem |= 1u << j;
     }
-    if (!__any(mem != 0u)) continue;
-    const uint8_t* Irow = fd.src + (int64_t)max(vy[i], 0) * fd.src_pitch + 3 * vx[i];
-    acc[3] += (unsigned long long)__popc(mem);
-    if (!mem) continue;
-    // the lane's 16 pixels in one round trip when the rows are dword aligned
-    if ((fd.flags & kFdAligned) && vx[i] + 16 <= W) {
-      uint32_t iw[12];
-      const uint32_t* q4 = reinterpret_cast<const uint32_t*>(Irow);
-#pragma unroll
-      for (int j = 0; j < 12; ++j) iw[j] = q4[j];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (!((mem >> j) & 1u)) continue;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += (iw[(3 * j + c) >> 2] >> (8 * ((3 * j + c) & 3))) & 0xFFu;
-      }
-    } else {
-      while (mem) {
-        const int j = __ffs(mem) - 1;
-        mem &= mem - 1;
-        acc[0] += Irow[3 * j];
-        acc[1] += Irow[3 * j + 1];
-        acc[2] += Irow[3 * j + 2];
-      }
-    }
+    if (__any(mem != 0u)) sum_members(i, mem);
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
