@@ -963,7 +963,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   const uint32_t K = (uint32_t)fd.K;
   const int tiles_x = (W + 63) / 64, nt = dark_tiles(W, H);
 
-  for (int i = tid; i < one_row_slot(H - 1) + 1; i += kOneT) s_tc[i] = 0u;
+  for (int i = tid; i < kOneRows + kOneRows / 32; i += kOneT) s_tc[i] = 0u;
   // every load is issued before the first barrier
   uint4 dv[NVT];
   int vy[NVT], vx[NVT];   // vy < 0: no vector in this slot
@@ -1033,7 +1033,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     }
   }
 
-  // 2. ties per row; I summed over the pixels with D > vstar
+  // 2. ties per row
   unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};   // S^c, members
   auto sum_members = [&](int i, uint32_t mem) {
     const uint8_t* Irow = fd.src + (int64_t)max(vy[i], 0) * fd.src_pitch + 3 * vx[i];
@@ -1060,23 +1060,30 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
       }
     }
   };
+  // member masks of the slots: D > vstar, and ties (D == vstar)
+  uint32_t mg[NVT], mt[NVT];
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
-    if (!hot[i]) continue;
-    uint32_t mt = 0u, mg = 0u;
-    if (vy[i] >= 0) {
-      const int n = min(16, W - vx[i]);
+    mt[i] = mg[i] = 0u;
+    if (!hot[i] || vy[i] < 0) continue;
+    const int n = min(16, W - vx[i]);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const uint32_t d = dbyte(i, j);
-        if (j < n && d == vstar) mt |= 1u << j;
-        if (j < n && d > vstar) mg |= 1u << j;
-      }
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t d = dbyte(i, j);
+      if (j < n && d == vstar) mt[i] |= 1u << j;
+      if (j < n && d > vstar) mg[i] |= 1u << j;
     }
-    if (mt) atomicAdd(&s_tc[one_row_slot(vy[i])], (uint32_t)__popc(mt));
-    if (__any(mg != 0u)) sum_members(i, mg);
+    if (mt[i]) atomicAdd(&s_tc[one_row_slot(vy[i])], (uint32_t)__popc(mt[i]));
   }
   __syncthreads();
+  // while wave 0 finds the cut, the other waves sum I over their pixels with
+  // D > vstar, which belong to the set whatever the cut (wave 0 adds its own
+  // with its ties below)
+  if (wv != 0) {
+#pragma unroll
+    for (int i = 0; i < NVT; ++i)
+      if (hot[i] && __any(mg[i] != 0u)) sum_members(i, mg[i]);
+  }
   // the cut row and the cut pixel, by wave 0: lane l sums rows [32 l, 32 l + 32),
   // a wave scan finds the lane, then the row, holding the need-th tie; then
   // lane l takes vector l of that row (W <= 1024) and a second scan finds the pixel
@@ -1085,8 +1092,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     uint32_t tc[RPL], t = 0;   // the lane's rows' tie counts stay in registers for the search
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
-      const int y = RPL * lane + k;
-      tc[k] = y < H ? s_tc[one_row_slot(y)] : 0u;
+      tc[k] = s_tc[one_row_slot(RPL * lane + k)];   // zero past the last row
       t += tc[k];
     }
     const uint32_t incl = wave_incl_scan(t);
@@ -1138,17 +1144,15 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
     return;
   }
 
-  // 3. the ties up to the cut
+  // 3. the ties up to the cut (and wave 0's pixels with D > vstar)
 #pragma unroll
   for (int i = 0; i < NVT; ++i) {
     if (!hot[i]) continue;
-    uint32_t mem = 0u;
-    if (vy[i] >= 0) {
-      const int n = min(16, W - vx[i]);
+    uint32_t mem = wv == 0 ? mg[i] : 0u;
+    if (mt[i]) {
       const int base = vy[i] * W + vx[i];
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j < n && dbyte(i, j) == vstar && base + j <= cutoff) mem |= 1u << j;
+      const int last = cutoff - base;   // ties at j <= last are members
+      mem |= last >= 15 ? mt[i] : (last < 0 ? 0u : mt[i] & ((2u << last) - 1u));
     }
     if (__any(mem != 0u)) sum_members(i, mem);
   }
