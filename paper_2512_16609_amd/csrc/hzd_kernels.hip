@@ -178,10 +178,14 @@ __device__ __forceinline__ uint32_t rne_u8(float v) {
 __device__ __forceinline__ float round_half(float t) { return __half2float(__float2half_rn(t)); }
 
 // ------------------------------------------------------------------ k_init
+// The white-balance histograms (the larger part of the state) are zeroed only
+// for frames that use them.  16-byte stores.
 __global__ __launch_bounds__(256) void k_init(Batch b) {
   const FrameDev& fd = b.f[blockIdx.x];
-  uint32_t* s = reinterpret_cast<uint32_t*>(fd.st);
-  for (int i = threadIdx.x; i < (int)(sizeof(FrameState) / 4); i += 256) s[i] = 0u;
+  static_assert(offsetof(FrameState, wbh) % 16 == 0 && sizeof(FrameState) % 16 == 0, "16-byte stores");
+  const int n16 = (int)(((fd.flags & kFdWbPercentile) ? sizeof(FrameState) : offsetof(FrameState, wbh)) / 16);
+  uint4* s = reinterpret_cast<uint4*>(fd.st);
+  for (int i = threadIdx.x; i < n16; i += 256) s[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // ------------------------------------------------------------------ k_resize
