@@ -672,7 +672,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
 
   // one row per wave; each lane reads 16 consecutive bytes of D per step.
   // The first segment's D does not depend on vstar: it is loaded before the
-  // histogram scan, so the two round trips overlap.
+  // histogram is read, so the two round trips overlap.
   const int y = tile * 4 + wv;
   const bool row_ok = y < H;
   const uint8_t* Drow = fd.D + (int64_t)min(y, H - 1) * fd.D_pitch;
@@ -685,9 +685,16 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
     }
   };
   load_d(0);
-  uint32_t vstar, cnt_gt;
-  wave_vstar(fd.st, (uint32_t)fd.K, vstar, cnt_gt);
-  (void)cnt_gt;
+  // wave 0 forms vstar from the histogram and shares it (one histogram read
+  // per block instead of per wave; the barrier wait overlaps the D loads)
+  __shared__ uint32_t s_vstar;
+  if (wv == 0) {
+    uint32_t v, cnt_gt;
+    wave_vstar(fd.st, (uint32_t)fd.K, v, cnt_gt);
+    if (lane == 0) s_vstar = v;
+  }
+  __syncthreads();
+  const uint32_t vstar = s_vstar;
   if (!row_ok) return;
   uint32_t gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;   // < W * 255 < 2^32
   uint32_t gN = 0, tN = 0;
@@ -700,6 +707,17 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
       if (base >= W) continue;
       const uint4 dv = dvs[q];  // rows are padded to 16 bytes
       const uint32_t dw[4] = {dv.x, dv.y, dv.z, dv.w};
+      // most vectors hold no byte >= vstar: test all 16 at once first.  In
+      // 16-bit halves, byte + (256 - vstar) carries into bit 8 iff byte >= vstar
+      // (padding bytes past the row may pass; the exact test below drops them)
+      {
+        const uint32_t kk = (256u - vstar) * 0x00010001u;
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          any |= ((dw[i] & 0x00FF00FFu) + kk) | (((dw[i] >> 8) & 0x00FF00FFu) + kk);
+        if (!(any & 0x01000100u)) continue;
+      }
       const int nx = min(16, W - base);
       uint32_t cand = 0;  // pixels with D >= vstar
 #pragma unroll
