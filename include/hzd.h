@@ -268,7 +268,8 @@ int hzd_dehaze_batch(const hzd_params* params, const hzd_frame* frames, int32_t 
  * computation as hzd_dehaze_frame, with the workspace taken from a static
  * device array of HZD_NOALLOC_SCRATCH_BYTES that the library holds on each
  * device it runs on until the process ends.  The frame's hzd_workspace_size
- * must not exceed that size (a 1920x1080 offline frame fits; a 3840x2160
+ * must not exceed that size (a 1920x1080 offline frame with int32 a, b fits in
+ * 59.4 MiB; with int64 a, b (small gf_eps or t0) it needs 75.2 MiB; a 3840x2160
  * offline frame does not): larger requests return HZD_E_NOMEM before any
  * device work.  hip_stream must belong to the current device (HZD_E_INVAL
  * otherwise).  The call allocates nothing: no hipMalloc/hipFree, no graph,

@@ -131,6 +131,12 @@ def test_noalloc_rejects_before_device_work(L):
     po = hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1)
     assert hzd.workspace_size(po, [(2160, 3840)]) > hzd.NOALLOC_SCRATCH_BYTES
     assert hzd.workspace_size(po, [(1080, 1920)]) <= hzd.NOALLOC_SCRATCH_BYTES
+    # int64 a, b (small eps and t0) double the a, b map: a 1080p offline frame no longer fits
+    p64 = hzd.Params(mode=hzd.MODE_OFFLINE, color_balance=1, gf_eps=1e-8, t0=0.01)
+    assert hzd.workspace_size(p64, [(1080, 1920)]) > hzd.NOALLOC_SCRATCH_BYTES
+    pc64 = p64.c()
+    f64 = hzd.hzd_frame(FAKE_SRC, 3 * 1920, FAKE_DST, 3 * 1920, 1920, 1080, None, None)
+    assert L.hzd_dehaze_frame_noalloc(ctypes.byref(pc64), ctypes.byref(f64), None, None) == hzd.HZD_E_NOMEM
     pc = po.c()
     f = hzd.hzd_frame(FAKE_SRC, 3 * 3840, FAKE_DST, 3 * 3840, 3840, 2160, None, None)
     assert L.hzd_dehaze_frame_noalloc(ctypes.byref(pc), ctypes.byref(f), None, None) == hzd.HZD_E_NOMEM
