@@ -924,8 +924,10 @@ def main():
     sets = []
     for _ in range(max(1, args.rotate)):
         src = src0.clone()
-        dst = torch.empty_like(src)
-        ws = hzd.alloc_workspace(ws_bytes, dev)
+        # every buffer is written once here, so that no set's first touch (page mapping)
+        # falls into the timed region when the warmup is shorter than the rotation
+        dst = torch.zeros_like(src)
+        ws = hzd.alloc_workspace(ws_bytes, dev).zero_()
         sets.append((src, dst, ws))
     working_set = sum(s.numel() + d.numel() + w.numel() for s, d, w in sets)
     # a stream of its own: the library replays captured graphs on any stream but the null stream
