@@ -15,7 +15,9 @@ constexpr int kMaxHalfPatch = 15;
 constexpr int kMaxRadius = 64;  // guided-filter radius supported by the 256-column strip kernels
 
 // Per-frame device state at the start of each frame's workspace.  Zeroed by the
-// init kernel at the start of every pipeline.  Sums that many blocks merge
+// init kernel at the start of a frame's pipeline (the white-balance histograms
+// only for frames that use them); frames of the one-block selection skip the
+// init kernel, and that selection zeroes the later sums itself.  Sums that many blocks merge
 // with integer atomics are spread over slots (block index mod slots), which
 // keeps same-address contention low; integer sums make the slot choice
 // irrelevant to the result.

@@ -5,7 +5,9 @@
 // frame from the per-launch block prefix in the kernel arguments):
 //   k_resize   Sec. V step 1 (optional): bilinear resampling to the working
 //              size in exact integers; the later stages read the copy
-//   k_init     zero each frame's state (histogram, colour-balance and luma sums)
+//   k_init     zero each frame's state (histogram, colour-balance and luma sums,
+//              white-balance histograms when used); frames of the one-block
+//              selection skip it
 //   k_dark     Eq. (2): channel minimum + patch erosion on LDS tiles with halo;
 //              writes D (u8), optionally the per-channel erosions E, and a
 //              256-bin histogram of D
@@ -13,7 +15,10 @@
 //              exact sums of the ties and of the pixels above vstar
 //   k_select_final  Eq. (3): the tie cut in raster order, A from exact sums
 //              (optionally averaged with the stream's previous airlight)
-//   k_gf_prep  offline: per-pixel luma and coarse t (Eqs. (4)-(5)) in fixed point
+//   k_select_one    Eq. (3) for small frames in one block, from per-tile
+//              histograms written by k_dark
+//   k_gf_prep  offline: per-pixel luma and coarse t (Eqs. (4)-(5)) in fixed point,
+//              with their column sums as prefixes inside 64-row groups
 //   k_gf_ab    Eq. (6) stage 1: exact integer box sums -> a, b
 //   k_gf_q     Eq. (6) stage 2: box means of a, b -> refined t (+ fused Eq. (7),
 //              or the stored t map with colour-balance or luma sums)
