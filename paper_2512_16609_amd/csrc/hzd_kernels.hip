@@ -911,16 +911,30 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
       seg_total += c;
     }
     const uint32_t avail = (run + ex < k) ? min(cnt, k - run - ex) : 0u;
-    uint32_t m = mask;
+    // the thread's first `avail` ties: their bits, then their colours with
+    // compile-time register indices (a data-dependent index into iw would
+    // become a chain of selects per byte)
+    uint32_t m = mask, take = 0u;
     for (uint32_t i = 0; i < avail; ++i) {
-      const int j = __ffs(m) - 1;
-      m &= m - 1;
+      const uint32_t low = m & (0u - m);
+      take |= low;
+      m ^= low;
+    }
+    if (avail && run + ex + avail == k) cut_x = x0 + 31 - __clz(take);   // the cut is the last tie taken
+    if (vec) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int byte = 3 * j + c;
-        acc[c] += vec ? (iw[byte >> 2] >> (8 * (byte & 3))) & 0xFFu : (uint32_t)Irow[3 * (x0 + j) + c];
+      for (int j = 0; j < 16; ++j) {
+        if (!((take >> j) & 1u)) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += (iw[(3 * j + c) >> 2] >> (8 * ((3 * j + c) & 3))) & 0xFFu;
       }
-      if (run + ex + i + 1 == k) cut_x = x0 + j;
+    } else {
+      while (take) {
+        const int j = __ffs(take) - 1;
+        take &= take - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += Irow[3 * (x0 + j) + c];
+      }
     }
     run += seg_total;
     if (seg + 16 * kFinT < W && run < k) __syncthreads();  // s_cnt is rewritten by the next segment
