@@ -212,8 +212,9 @@ typedef struct hzd_frame {
  *            status is the selection's own consistency check, 0 when the
  *            per-row counts agree with the histogram of D.  Nonzero means
  *            the device produced inconsistent intermediate data (a fault):
- *            1 = the count of pixels above vstar or the cut pixel disagrees
- *            (A was formed, the result is not trustworthy); 2 = no row holds
+ *            1 = the count of pixels above vstar or the cut pixel disagrees,
+ *            or the histogram does not hold W*H pixels (A was formed, the
+ *            result is not trustworthy); 2 = no row holds
  *            the cut (A is set to 0 and the output is undefined).  A frame
  *            or batch call returns before its kernels run, so a caller that
  *            needs this check passes sel_out (device or host-mapped memory)
@@ -243,8 +244,10 @@ int hzd_workspace_size(const hzd_params* params, const hzd_frame* frames, int32_
 
 /* Dehaze one frame (Sec. V, steps 2-7) on `hip_stream`.
  * workspace: device memory of at least hzd_workspace_size bytes, owned by the
- * caller, used exclusively by this call until it completes in stream order.
- * aux may be NULL.  Errors: INVAL (arguments), NOMEM (workspace too small),
+ * caller, used exclusively by this call until it completes in stream order;
+ * its contents before the call do not matter (the call zeroes the state it
+ * accumulates into, inside its first kernel or, when the launches may be
+ * replayed from a graph, with a kernel of its own).  aux may be NULL.  Errors: INVAL (arguments), NOMEM (workspace too small),
  * UNSUPPORTED (e.g. patch > 31), DEVICE (a launch failed). */
 int hzd_dehaze_frame(const hzd_params* params, const hzd_frame* frame,
                      const hzd_frame_aux* aux, void* workspace, size_t ws_bytes,

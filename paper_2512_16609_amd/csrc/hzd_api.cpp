@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -437,9 +438,36 @@ int stage(bool prof, const char* name, hipStream_t s, F&& launch) {
 }
 }  // namespace
 
+// A launch's epoch (kFdFresh): nonzero and unique in the process.  The start
+// is random, so that state written by another process into the same memory is
+// not mistaken for this launch's.
+static unsigned long long next_epoch() {
+  static std::atomic<unsigned long long> counter{[] {
+    std::random_device rd;
+    return ((unsigned long long)rd() << 32) ^ (unsigned long long)rd();
+  }()};
+  unsigned long long e;
+  do e = counter.fetch_add(1, std::memory_order_relaxed) + 1; while (e == 0);
+  return e;
+}
+
+bool stream_capturing(hipStream_t s) {
+  if (s == nullptr) return false;   // the null stream cannot be captured
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;   // unknown: take the form that is safe to record
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
 // The per-frame algorithm of Sec. V for one launch group of <= kMaxBatch frames;
-// `prof` brackets every launch with timing events.
-int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s, bool prof) {
+// `prof` brackets every launch with timing events.  `fresh` (kFreshYes): the
+// launches run once, directly (no graph records them), so leading blocks of
+// k_dark zero the frames' state and the init kernel is not launched; kFreshAsk
+// decides by whether s is being captured, asked only for frames that would
+// take the init kernel.
+int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s, bool prof, int fresh) {
   int rc;
   // an empty event pair measures what bracketing itself costs
   if (prof) (void)stage(prof, "event_pair", s, [] { return hipSuccess; });
@@ -455,6 +483,12 @@ int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStrea
     for (int i = 0; i < bo.n; ++i) bo.f[i].flags |= kFdNoHist;
     if ((rc = stage(prof, "dark", s, [&] { return launch_dark(bo, g, he, s); })) != HZD_OK) return rc;
     if ((rc = stage(prof, "select", s, [&] { return launch_select_one(bo, s); })) != HZD_OK) return rc;
+  } else if (fresh == kFreshYes || (fresh == kFreshAsk && !stream_capturing(s))) {
+    Batch bf = b;
+    bf.epoch = next_epoch();
+    for (int i = 0; i < bf.n; ++i) bf.f[i].flags |= kFdFresh;
+    if ((rc = stage(prof, "dark", s, [&] { return launch_dark(bf, g, he, s); })) != HZD_OK) return rc;
+    if ((rc = stage(prof, "select", s, [&] { return launch_select(bf, s); })) != HZD_OK) return rc;
   } else {
     if ((rc = stage(prof, "init", s, [&] { return launch_init(b, s); })) != HZD_OK) return rc;
     if ((rc = stage(prof, "dark", s, [&] { return launch_dark(b, g, he, s); })) != HZD_OK) return rc;
@@ -526,22 +560,19 @@ int launch_group(const GroupKey& g, const Batch& bin, const ResizeBatch* rz, hip
     cap = g_graph_cap;
   }
   const bool prof = g_prof_on.load(std::memory_order_relaxed);
-  if (s == nullptr) return run_group(g, b, rz, s, prof);
-  if (cap == 0 && !prof) return run_group(g, b, rz, s, false);
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
-    (void)hipGetLastError();
-    // the caller is capturing: our launches join its graph, without timing
-    // events, which would complete only when that graph runs
-    return run_group(g, b, rz, s, false);
-  }
-  if (cap == 0 || prof) return run_group(g, b, rz, s, prof);
+  if (s == nullptr) return run_group(g, b, rz, s, prof, kFreshYes);
+  if (cap == 0 && !prof) return run_group(g, b, rz, s, false, kFreshAsk);
+  // the caller is capturing: our launches join its graph, in the form that
+  // may be replayed, without timing events (they would complete only when
+  // that graph runs)
+  if (stream_capturing(s)) return run_group(g, b, rz, s, false, kFreshNo);
+  if (cap == 0 || prof) return run_group(g, b, rz, s, prof, kFreshYes);
   // A graph is bound to the device it was captured on, and a freed device
   // address can come back on another device: the device is part of the key.
   int dev = -1;
   if (hipStreamGetDevice(s, &dev) != hipSuccess) {
     (void)hipGetLastError();
-    return run_group(g, b, rz, s, false);
+    return run_group(g, b, rz, s, false, kFreshYes);
   }
   std::string key(reinterpret_cast<const char*>(&dev), sizeof(dev));
   key.append(reinterpret_cast<const char*>(&g), sizeof(g));
@@ -559,7 +590,7 @@ int launch_group(const GroupKey& g, const Batch& bin, const ResizeBatch* rz, hip
   if (!exec) {
     int rc = check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     if (rc) return rc;
-    const int rrc = run_group(g, b, rz, s, false);
+    const int rrc = run_group(g, b, rz, s, false, kFreshNo);
     hipGraph_t graph = nullptr;
     rc = check(hipStreamEndCapture(s, &graph), "end capture");
     if (rrc) {
@@ -718,7 +749,7 @@ int run_frame_direct(const hzd_params* p, const hzd_frame& fr, const hzd_frame_a
   b.f[0] = make_frame_dev(*p, fr, aux, reinterpret_cast<uint8_t*>(ws), &rz.f[0]);
   const GroupKey g = group_key(*p);
   if (g.mode == HZD_MODE_OFFLINE) fit_gf_rows(b);
-  return run_group(g, b, &rz, s, false);
+  return run_group(g, b, &rz, s, false, kFreshAsk);
 }
 
 int dehaze_many(const hzd_params* params, const hzd_frame* frames, int32_t n, const hzd_frame_aux* aux,

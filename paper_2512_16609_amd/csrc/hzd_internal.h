@@ -14,13 +14,20 @@ constexpr int kMaxBatch = 16;   // frames per launch (descriptors travel in kern
 constexpr int kMaxHalfPatch = 15;
 constexpr int kMaxRadius = 64;  // guided-filter radius supported by the 256-column strip kernels
 
-// Per-frame device state at the start of each frame's workspace.  Zeroed by the
-// init kernel at the start of a frame's pipeline (the white-balance histograms
-// only for frames that use them); frames of the one-block selection skip the
-// init kernel, and that selection zeroes the later sums itself.  Sums that many blocks merge
-// with integer atomics are spread over slots (block index mod slots), which
-// keeps same-address contention low; integer sums make the slot choice
-// irrelevant to the result.
+// Per-frame device state at the start of each frame's workspace.  Its sums
+// start at zero in one of three ways:
+//  - direct launches (kFdFresh): a leading block of k_dark per frame zeroes
+//    the frame's state and then publishes the launch's epoch, a value no
+//    earlier launch used, in it; the frame's tile blocks wait for that epoch
+//    before merging their histograms;
+//  - launches recorded into a graph (replays would repeat the epoch): the init
+//    kernel zeroes everything before k_dark (the white-balance histograms only
+//    for frames that use them);
+//  - frames of the one-block selection: k_dark writes per-tile histograms
+//    whole, and that selection zeroes the later sums itself.
+// Sums that many blocks merge with integer atomics are spread over slots (block
+// index mod slots), which keeps same-address contention low; integer sums make
+// the slot choice irrelevant to the result.
 constexpr int kHistSlots = 8;
 constexpr int kCbSlots = 64;
 struct FrameState {
@@ -30,8 +37,13 @@ struct FrameState {
   unsigned long long cb[kCbSlots][4];   // sum of J_gamma^c in 2^-23 fixed point, per slot
   unsigned long long luma[kCbSlots];    // adaptive gamma: sum of the BT.601 luma of J in 2^-16 fixed point
   uint32_t wbh[kHistSlots][3][256];     // percentile white balance: histograms of the codes RNE(J_gamma^c), per slot
+  unsigned long long epoch;             // direct launches: the launch's epoch once the state above is zero
+  unsigned long long pad_;
 };
 static_assert(sizeof(FrameState) <= 40960, "FrameState too large");
+static_assert(offsetof(FrameState, cb) % 16 == 0 && offsetof(FrameState, wbh) % 16 == 0 &&
+                  offsetof(FrameState, epoch) % 16 == 0,
+              "the state is zeroed with 16-byte stores");
 
 // Per-row record of the airlight selection pass: the row's pixels with
 // D == vstar (ties) and D > vstar, counted and summed per channel.  A row's
@@ -89,10 +101,12 @@ constexpr uint32_t kFdEmaFirst = 4u;        // the stream's first frame: ignore 
 constexpr uint32_t kFdGammaAdaptive = 8u;   // per-frame gamma from the luma sums of J
 constexpr uint32_t kFdWbPercentile = 16u;   // balance by percentile stretch (else gray-world)
 constexpr uint32_t kFdNoHist = 32u;         // k_dark skips the histogram (the one-block selection builds it)
+constexpr uint32_t kFdFresh = 64u;          // no init kernel: leading k_dark blocks zero the frames' state
 
 struct Batch {
   int32_t n;
   int32_t tile0[kMaxBatch + 1];  // per-launch prefix of blocks per frame
+  unsigned long long epoch;      // kFdFresh: nonzero, unique to the launch
   FrameDev f[kMaxBatch];
 };
 static_assert(sizeof(Batch) <= 4000, "kernel argument block too large");

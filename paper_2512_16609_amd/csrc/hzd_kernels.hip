@@ -6,8 +6,9 @@
 //   k_resize   Sec. V step 1 (optional): bilinear resampling to the working
 //              size in exact integers; the later stages read the copy
 //   k_init     zero each frame's state (histogram, colour-balance and luma sums,
-//              white-balance histograms when used); frames of the one-block
-//              selection skip it
+//              white-balance histograms when used) for launches recorded into
+//              a graph; in direct launches leading blocks of k_dark do it, for
+//              frames of the one-block selection k_select_one
 //   k_dark     Eq. (2): channel minimum + patch erosion on LDS tiles with halo;
 //              writes D (u8), optionally the per-channel erosions E, and a
 //              256-bin histogram of D
@@ -183,15 +184,16 @@ __device__ __forceinline__ uint32_t rne_u8(float v) {
 __device__ __forceinline__ float round_half(float t) { return __half2float(__float2half_rn(t)); }
 
 // ------------------------------------------------------------------ k_init
-// The white-balance histograms (the larger part of the state) are zeroed only
-// for frames that use them.  16-byte stores.
-__global__ __launch_bounds__(256) void k_init(Batch b) {
-  const FrameDev& fd = b.f[blockIdx.x];
-  static_assert(offsetof(FrameState, wbh) % 16 == 0 && sizeof(FrameState) % 16 == 0, "16-byte stores");
-  const int n16 = (int)(((fd.flags & kFdWbPercentile) ? sizeof(FrameState) : offsetof(FrameState, wbh)) / 16);
+// Zero a frame's state up to its epoch word with 16-byte stores, spread over
+// the 256 threads of a block; the white-balance histograms (the larger part of
+// the state) only for frames that use them.
+__device__ __forceinline__ void zero_state(const FrameDev& fd) {
+  const int n16 = (int)(((fd.flags & kFdWbPercentile) ? offsetof(FrameState, epoch) : offsetof(FrameState, wbh)) / 16);
   uint4* s = reinterpret_cast<uint4*>(fd.st);
   for (int i = threadIdx.x; i < n16; i += 256) s[i] = make_uint4(0u, 0u, 0u, 0u);
 }
+
+__global__ __launch_bounds__(256) void k_init(Batch b) { zero_state(b.f[blockIdx.x]); }
 
 // ------------------------------------------------------------------ k_resize
 // Sec. V step 1: bilinear resampling of the frame to the working size, in
@@ -314,6 +316,23 @@ __global__ __launch_bounds__(256) void k_resize(ResizeBatch rb) {
 // and pixel.  Groups that touch the frame border take a per-cell path.  The
 // outputs are packed with v_perm_b32 as well: per pixel [R, G, B, 0], then 4
 // pixels into 3 dwords of E.
+//
+// Direct launches (kFdFresh) run without the init kernel.  The grid then
+// starts with one block per frame that only zeroes that frame's state (as the
+// init kernel would), makes its stores visible on the device (a release) and
+// publishes the launch's epoch in the state; a tile block reads its frame's
+// epoch before its histogram merge and, until it matches, waits (bounded:
+// after kEpochSpins polls it merges anyway, and the final selection's check of
+// the histogram total against W H flags the frame).  The zeroing blocks come
+// first in the grid, so they are dispatched before any block that waits for
+// them, and they wait for nothing: the wait cannot hold a slot they need.
+// They finish within about 2 us, before the first tile block reaches its merge.
+// The waiting blocks take no acquire fence: their only accesses to the zeroed
+// state are the histogram's atomic adds, which the device performs at its
+// point of coherence, issued after the epoch read has returned; an agent-scope
+// acquire here would also invalidate cached lines that the other blocks are
+// still reading (it made k_dark 5.6 us slower at 1080p).
+constexpr int kEpochSpins = 1 << 15;
 namespace dk {
 typedef __attribute__((address_space(1))) const uint32_t gu32;   // global memory: global_load, not flat
 
@@ -352,10 +371,21 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   constexpr int PLN = ((RH * RWA > TH * RWP ? RH * RWA : TH * RWP) + 3) & ~3;   // dwords per plane
   __shared__ __align__(16) uint32_t s_pl[2][PLN];
   __shared__ uint32_t s_hist[256];
+  __shared__ int s_epoch_ok;   // fresh launches: the frame's state was zeroed before the vertical pass ended
   uint32_t(&s_rb)[TH][RWP] = *reinterpret_cast<uint32_t(*)[TH][RWP]>(&s_pl[0][0]);
   uint32_t(&s_g)[TH][RWP] = *reinterpret_cast<uint32_t(*)[TH][RWP]>(&s_pl[1][0]);
 
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const bool fresh = (b.f[0].flags & kFdFresh) != 0;   // the same for every frame of a launch
+  const int nzero = fresh ? b.n : 0;                    // leading blocks that zero the frames' state
+  if ((int)blockIdx.x < nzero) {
+    const FrameDev& fz = b.f[blockIdx.x];
+    zero_state(fz);
+    __threadfence();   // this thread's stores are visible on the device
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&fz.st->epoch, b.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  const int blk = xcd_remap(blockIdx.x - nzero, gridDim.x - nzero);
   const int f = frame_of(b, blk);
   const FrameDev& fd = b.f[f];
   const int tile = blk - b.tile0[f];
@@ -363,6 +393,11 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   const int tiles_x = (W + TW - 1) / TW;
   const int x0 = (tile % tiles_x) * TW, y0 = (tile / tiles_x) * TH;
   const int tid = threadIdx.x;
+  // The frame's epoch is read once staging is done and compared before the
+  // vertical pass's barrier, while no store of the block is in flight (a wait
+  // for the read later would also wait for the block's output stores); the
+  // merge polls only if that read came before the zeroing block published.
+  unsigned long long seen = 0ull;
 
   s_hist[tid] = 0u;
   {
@@ -428,6 +463,7 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
     }
   }
   __syncthreads();
+  if (fresh && tid == 0) seen = __hip_atomic_load(&fd.st->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
   // vertical pass: RW columns x 2 segments of 16 output rows, one per
   // thread; the outputs replace rows [0, TH) of the planes in place
@@ -456,6 +492,7 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
       }
     }
   }
+  if (fresh && tid == 0) s_epoch_ok = seen == b.epoch;
   __syncthreads();
 
   // horizontal pass: 32 rows x 8 segments of 8 output columns; wave w takes
@@ -526,6 +563,13 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
         }
       }
       atomicAdd(&s_hist[cur], cnt);
+    }
+  }
+  if (fresh && tid == 0 && !s_epoch_ok) {
+    const unsigned long long* ep = &fd.st->epoch;
+    for (int n = 0; seen != b.epoch && n < kEpochSpins; ++n) {
+      __builtin_amdgcn_s_sleep(8);
+      seen = __hip_atomic_load(ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   __syncthreads();
@@ -634,10 +678,12 @@ __device__ __forceinline__ T block_scan_total(T v, T* s_tmp, T& total) {
 // value; an inclusive scan gives #{D >= v}, and vstar is the first v from the
 // top at which it reaches K.  Counts that never reach K (an inconsistent
 // state) give vstar 0, which the final consistency test flags.
-__device__ __forceinline__ void vstar_from_lane_counts(uint4 c, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt) {
+__device__ __forceinline__ void vstar_from_lane_counts(uint4 c, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt,
+                                                       uint32_t* total = nullptr) {
   // in-lane counts of D >= b0 + 3, b0 + 2, b0 + 1, b0
   const uint32_t l3 = c.w, l2 = l3 + c.z, l1 = l2 + c.y, l0 = l1 + c.x;
   const uint32_t incl = wave_incl_scan(l0);
+  if (total) *total = __builtin_amdgcn_readlane(incl, 63);   // every pixel counted once: W H
   const unsigned long long hit = __ballot(incl >= K);
   const int L = hit ? __ffsll((long long)hit) - 1 : 63;
   const uint32_t ex = __builtin_amdgcn_readlane(incl - l0, L);   // #{D > 4(63 - L) + 3}
@@ -656,7 +702,8 @@ __device__ __forceinline__ void vstar_from_lane_counts(uint4 c, uint32_t K, uint
 }
 
 // The same from the frame's slotted histogram, with no LDS and no barrier.
-__device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt) {
+__device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uint32_t& vstar, uint32_t& cnt_gt,
+                                           uint32_t* total = nullptr) {
   const int b0 = 4 * (63 - (int)(threadIdx.x & 63));
   uint4 c = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
@@ -664,7 +711,7 @@ __device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uin
     const uint4 h = *reinterpret_cast<const uint4*>(&st->hist[k][b0]);
     c.x += h.x; c.y += h.y; c.z += h.z; c.w += h.w;
   }
-  vstar_from_lane_counts(c, K, vstar, cnt_gt);
+  vstar_from_lane_counts(c, K, vstar, cnt_gt, total);
 }
 
 __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
@@ -819,8 +866,8 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     }
   };
   load_round(0);
-  uint32_t vstar, cnt_gt;
-  wave_vstar(fd.st, K, vstar, cnt_gt);
+  uint32_t vstar, cnt_gt, total;
+  wave_vstar(fd.st, K, vstar, cnt_gt, &total);
   const uint32_t need = K - cnt_gt;  // >= 1
 
   int rstar = -1;          // the cut row (block-uniform once found)
@@ -954,7 +1001,8 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
       for (int i = 0; i < 5; ++i) S[i] += s_red[w][i];
     const int cx = (int)S[4] - 1;
     // consistency: the rows' count over D > vstar must equal the histogram's
-    store_airlight(fd, K, vstar, rstar * W + cx, S, (S[3] == (unsigned long long)cnt_gt && cx >= 0) ? 0 : 1);
+    const bool ok = S[3] == (unsigned long long)cnt_gt && cx >= 0 && total == (uint32_t)W * (uint32_t)H;
+    store_airlight(fd, K, vstar, rstar * W + cx, S, ok ? 0 : 1);
   }
 }
 
@@ -1028,7 +1076,7 @@ __global__ __launch_bounds__(kOneT) void k_select_one(Batch b) {
   // the frame state's sums of the later passes start at zero
   {
     uint32_t* z = reinterpret_cast<uint32_t*>(&st->cb[0][0]);
-    constexpr int nz = (int)((sizeof(FrameState) - offsetof(FrameState, cb)) / 4);
+    constexpr int nz = (int)((offsetof(FrameState, epoch) - offsetof(FrameState, cb)) / 4);
     for (int i = tid; i < nz; i += kOneT) z[i] = 0u;
   }
   auto dbyte = [&](int i, int j) { return (((&dv[i].x)[j >> 2]) >> (8 * (j & 3))) & 0xFFu; };
@@ -2253,6 +2301,7 @@ int fill_tiles(B& b, Fn blocks_of) {
 
 template <int HP>
 hipError_t dark_hp(const Batch& b, int nblk, bool write_E, hipStream_t s) {
+  if (b.f[0].flags & kFdFresh) nblk += b.n;   // the leading blocks that zero the frames' state
   if (write_E) hipLaunchKernelGGL((k_dark<HP, true>), dim3(nblk), dim3(256), 0, s, b);
   else hipLaunchKernelGGL((k_dark<HP, false>), dim3(nblk), dim3(256), 0, s, b);
   return hipGetLastError();

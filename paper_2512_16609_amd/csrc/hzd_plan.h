@@ -25,7 +25,15 @@ FrameDev make_frame_dev(const hzd_params& p, const hzd_frame& fr, const hzd_fram
                         ResizeDev* rz);
 hzd_tile_config tile_config_for(int W, int H, bool* from_table = nullptr);
 void fit_gf_rows(Batch& b);
-int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s, bool prof);
+// fresh: kFreshYes when the launches run directly and once (not recorded into
+// a graph), so the frames' state is zeroed by leading blocks of k_dark instead of
+// by the init kernel (Batch.epoch is set here); kFreshNo when they may be
+// replayed; kFreshAsk: whether s is being captured decides, asked only when
+// the init kernel would otherwise run
+enum { kFreshNo = 0, kFreshYes = 1, kFreshAsk = 2 };
+int run_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s, bool prof, int fresh);
+// Whether work enqueued on s is being recorded into a graph (true when unknown).
+bool stream_capturing(hipStream_t s);
 // rz: the resampling descriptors of a group with g.resize (else unused, may be NULL)
 int launch_group(const GroupKey& g, const Batch& b, const ResizeBatch* rz, hipStream_t s);
 int check(hipError_t e, const char* what);

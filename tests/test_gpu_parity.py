@@ -235,9 +235,55 @@ def test_graph_replay_matches_direct_launch():
         hzd.graph_cache(0)
 
 
-@pytest.mark.parametrize("w,h,small", [(320, 240, True), (1280, 720, False)])
-def test_stage_profiling_times_every_launch(w, h, small):
-    # a small frame takes the one-block selection, which needs no init kernel
+@pytest.mark.parametrize("variant", ["offline_percentile_adaptive", "realtime_grayworld"])
+def test_state_zeroing_does_not_depend_on_workspace_contents(variant):
+    # Direct launches zero each frame's state inside k_dark (histograms) and the final selection
+    # (the later sums) instead of with the init kernel.  Run a batch on a workspace full of random
+    # bytes, then again with the frames in another order (each frame's state now lies on what
+    # another frame's maps held), and compare with the graph-replayed form, which zeroes the
+    # state with the init kernel.  The selection's status checks that every histogram holds W H.
+    if variant == "offline_percentile_adaptive":
+        p = P(mode=hzd.MODE_OFFLINE, gf_radius=30, color_balance=2, gamma_adaptive=1, gamma_target=0.6)
+    else:
+        p = P(color_balance=1)
+    shapes = [(480, 640), (720, 1280), (1080, 1920), (481, 655)]
+    frames = [make_frame(w, h, 700 + i, beta=0.8 + 0.2 * i).I for i, (h, w) in enumerate(shapes)]
+    srcs = [to_dev(I) for I in frames]
+    stream = torch.cuda.Stream()
+
+    def run(order, ws, graphs):
+        dsts = [torch.zeros_like(srcs[i]) for i in order]
+        auxs = [hzd.make_aux(shapes[i][0], shapes[i][1], J=False) for i in order]
+        torch.cuda.synchronize()
+        hzd.graph_cache(8 if graphs else 0)
+        try:
+            with torch.cuda.stream(stream):
+                hzd.dehaze_batch([srcs[i] for i in order], dsts, p, auxs=auxs, workspace=ws, stream=stream)
+            stream.synchronize()
+        finally:
+            hzd.graph_cache(0)
+        out = {}
+        for k, i in enumerate(order):
+            assert int(auxs[k]["sel"][3].item()) == 0, (variant, order, i)
+            out[i] = (dsts[k].cpu().numpy(), auxs[k]["A"].cpu().numpy(), auxs[k]["t"].cpu().numpy())
+        return out
+
+    order_a, order_b = [0, 1, 2, 3], [3, 2, 0, 1]
+    ws_bytes = max(hzd.workspace_size(p, [shapes[i] for i in o]) for o in (order_a, order_b))
+    ref = run(order_a, torch.zeros(ws_bytes, dtype=torch.uint8, device="cuda"), graphs=True)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    ws = torch.randint(0, 256, (ws_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    for order in (order_a, order_b, order_a):
+        got = run(order, ws, graphs=False)
+        for i in order:
+            for a, b_ in zip(got[i], ref[i]):
+                assert np.array_equal(a, b_), (variant, order, i)
+
+
+@pytest.mark.parametrize("w,h", [(320, 240), (1280, 720)])
+def test_stage_profiling_times_every_launch(w, h):
+    # direct launches run no init kernel: a small frame takes the one-block selection, a larger
+    # one has k_dark and the final selection zero its state
     I = _frame(w, h, 51)
     p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
     ref = run_gpu(I, p, with_J=False)["out"]
@@ -250,21 +296,24 @@ def test_stage_profiling_times_every_launch(w, h, small):
         stages = hzd.profile_read(reset=True)
     finally:
         hzd.profile_enable(False)
-    names = {"event_pair", "dark", "select", "gf_prep", "gf_ab", "gf_q", "recon_apply"} | (set() if small else {"init"})
+    names = {"event_pair", "dark", "select", "gf_prep", "gf_ab", "gf_q", "recon_apply"}
     for name in names:
         launches, ms = stages[name]
         assert launches == 2 and ms >= 0.0, (name, stages[name])
     assert set(stages) == names
 
 
-def test_caller_graph_capture_replays_and_is_not_timed():
+@pytest.mark.parametrize("w,h", [(320, 240), (640, 480)])
+def test_caller_graph_capture_replays_and_is_not_timed(w, h):
     # a call made while the caller captures its stream joins the caller's graph; profiling
-    # stays off for it (its events would complete only when the graph runs)
-    I1, I2 = _frame(320, 240, 52), _frame(320, 240, 53)
+    # stays off for it (its events would complete only when the graph runs).  640x480 takes the
+    # two-kernel selection, whose captured form zeroes the state with the init kernel on every
+    # replay
+    I1, I2 = _frame(w, h, 52), _frame(w, h, 53)
     p = P(mode=hzd.MODE_OFFLINE, gf_radius=16, color_balance=1)
     ref1, ref2 = run_gpu(I1, p, with_J=False)["out"], run_gpu(I2, p, with_J=False)["out"]
-    src, dst = to_dev(I1), torch.zeros((240, 320, 3), dtype=torch.uint8, device="cuda")
-    ws = hzd.alloc_workspace(hzd.workspace_size(p, [(240, 320)]))
+    src, dst = to_dev(I1), torch.zeros((h, w, 3), dtype=torch.uint8, device="cuda")
+    ws = hzd.alloc_workspace(hzd.workspace_size(p, [(h, w)]))
     stream = torch.cuda.Stream()
     graph = torch.cuda.CUDAGraph()
     hzd.profile_read(reset=True)

@@ -57,6 +57,28 @@ def test_noalloc_equals_workspace_entry_two_calls():
             compare(I, p, got, label="noalloc 1080p offline")
 
 
+def test_noalloc_under_graph_capture_replays():
+    # callers that cannot allocate include code under graph capture: the captured call zeroes the
+    # frame state with the init kernel on every replay (direct calls do it inside k_dark and the
+    # final selection); each replay equals the workspace entry point's direct result
+    p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=20, color_balance=1)
+    I1, I2 = make_frame(640, 480, 31).I, make_frame(640, 480, 32, beta=1.4).I
+    ref1, ref2 = _run("workspace", I1, p)["out"], _run("workspace", I2, p)["out"]
+    src = to_dev(I1)
+    dst = torch.zeros((480, 640, 3), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        hzd.dehaze_frame_noalloc(src, dst, p, stream=stream)
+    for rep in range(4):
+        src.copy_(to_dev(I1 if rep % 2 == 0 else I2))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(dst.cpu().numpy(), ref1 if rep % 2 == 0 else ref2), rep
+
+
 def test_noalloc_rejects_oversized_frame():
     I = torch.zeros((2160, 3840, 3), dtype=torch.uint8, device="cuda")
     dst = torch.zeros_like(I)
