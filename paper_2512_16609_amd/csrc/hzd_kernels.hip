@@ -319,14 +319,16 @@ __global__ __launch_bounds__(256) void k_resize(ResizeBatch rb) {
 //
 // Direct launches (kFdFresh) run without the init kernel.  The grid then
 // starts with one block per frame that only zeroes that frame's state (as the
-// init kernel would), makes its stores visible on the device (a release) and
-// publishes the launch's epoch in the state; a tile block reads its frame's
-// epoch before its histogram merge and, until it matches, waits (bounded:
-// after kEpochSpins polls it merges anyway, and the final selection's check of
-// the histogram total against W H flags the frame).  The zeroing blocks come
-// first in the grid, so they are dispatched before any block that waits for
-// them, and they wait for nothing: the wait cannot hold a slot they need.
-// They finish within about 2 us, before the first tile block reaches its merge.
+// init kernel would) with agent-scope atomic stores, waits until they have
+// completed and publishes the launch's epoch in the state.  A tile block reads
+// its frame's epoch after its staging and, if it does not match yet, polls it
+// before its histogram merge (bounded: after kEpochSpins polls it merges
+// anyway, and the final selection's check of the histogram total against W H
+// flags the frame).  The zeroing blocks come first in the grid, so they are
+// dispatched before any block that waits for them, and they wait for nothing:
+// the wait cannot hold a slot they need.  At 8 x 720p per launch they publish
+// about 4 us into the kernel, and fewer than 1% of the first round's tile
+// blocks find the epoch missing after their vertical pass.
 // The waiting blocks take no acquire fence: their only accesses to the zeroed
 // state are the histogram's atomic adds, which the device performs at its
 // point of coherence, issued after the epoch read has returned; an agent-scope
@@ -379,10 +381,16 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   const int nzero = fresh ? b.n : 0;                    // leading blocks that zero the frames' state
   if ((int)blockIdx.x < nzero) {
     const FrameDev& fz = b.f[blockIdx.x];
-    zero_state(fz);
-    __threadfence();   // this thread's stores are visible on the device
+    // agent-scope atomic stores are written through to the device's point of
+    // coherence; once the wave's counter says they completed, they are
+    // visible to every XCD, and no L2 write-back (what a release fence would
+    // add) is needed before the epoch goes out
+    const int n4 = (int)(((fz.flags & kFdWbPercentile) ? offsetof(FrameState, epoch) : offsetof(FrameState, wbh)) / 4);
+    uint32_t* z = reinterpret_cast<uint32_t*>(fz.st);
+    for (int i = threadIdx.x; i < n4; i += 256) __hip_atomic_store(&z[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);   // every counter at zero: this wave's stores have completed
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(&fz.st->epoch, b.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(&fz.st->epoch, b.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
   const int blk = xcd_remap(blockIdx.x - nzero, gridDim.x - nzero);
