@@ -42,7 +42,7 @@ ALG_BYTES_PER_PX = 6.0
 # Keys are the library's stage names.
 STAGE_BYTES_PER_PX = {
     "dark": 7.0,          # I (3) in; D (1) + per-channel erosions E (3) out
-    "select": 1.0,        # D (1) in (+ I at the pixels with D >= vstar); two kernels
+    "select": 1.0,        # D (1) in (+ I at the pixels with D >= vstar); row records are 32 B per row
     "gf_prep": 17.0,      # I (3) + E (3) in; luma/t fixed point LP (8) + 8-row chunk sums (3) out
     "gf_ab": 18.0,        # LP (8) in; a/b fixed point (8) + chunk sums (2) out
     "gf_q": 15.0,         # a/b (8) + I (3) in; refined t (4) out
@@ -52,8 +52,8 @@ STAGE_BYTES_PER_PX = {
     "init": 0.0,
 }
 # kernel symbols of this workload's stages, as rocprofv3 names them
-# (the select stage is two kernels; its traffic entry is the row pass)
-STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": "hzd::k_select_rows",
+# (the select stage is one kernel: the row pass, then the final step in the frame's last row block)
+STAGE_KERNEL = {"init": "hzd::k_init", "dark": "hzd::k_dark<7,true>", "select": "hzd::k_select_rows<512>",
                 "gf_prep": "hzd::k_gf_prep<0>", "gf_ab": "hzd::k_gf_ab<2,false>",
                 "gf_q": "hzd::k_gf_q<2,1,false,false,false>", "recon_apply": "hzd::k_recon<2,2,false,false>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1080p_offline.txt")

@@ -34,6 +34,8 @@ struct FrameState {
   uint32_t hist[kHistSlots][256];       // histogram of the dark channel D, per slot
   float A[4];                           // airlight A^c (0..255 scale)
   int32_t sel[4];                       // K, vstar, cutoff, consistency flag (0 = ok)
+  uint32_t rows_done;                   // row blocks of the selection that have written their records
+  uint32_t rows_pad[3];
   unsigned long long cb[kCbSlots][4];   // sum of J_gamma^c in 2^-23 fixed point, per slot
   unsigned long long luma[kCbSlots];    // adaptive gamma: sum of the BT.601 luma of J in 2^-16 fixed point
   uint32_t wbh[kHistSlots][3][256];     // percentile white balance: histograms of the codes RNE(J_gamma^c), per slot
@@ -158,7 +160,7 @@ int device_cu_count();
 hipError_t launch_resize(ResizeBatch r, hipStream_t s);
 hipError_t launch_init(Batch b, hipStream_t s);
 hipError_t launch_dark(Batch b, const GroupKey& g, bool write_E, hipStream_t s);
-hipError_t launch_select(Batch b, hipStream_t s);        // two kernels: rows, then one block per frame
+hipError_t launch_select(Batch b, hipStream_t s);        // row records; the frame's last row block ends the selection
 // One block per frame for small frames (select_one_fits); the frames' k_dark
 // launch skips its histogram (kFdNoHist) and the init kernel is not needed.
 hipError_t launch_select_one(Batch b, hipStream_t s);

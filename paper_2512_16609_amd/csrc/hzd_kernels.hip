@@ -13,9 +13,10 @@
 //              writes D (u8), optionally the per-channel erosions E, and a
 //              256-bin histogram of D
 //   k_select_rows   Eq. (3): vstar from the histogram, per-row counts and
-//              exact sums of the ties and of the pixels above vstar
-//   k_select_final  Eq. (3): the tie cut in raster order, A from exact sums
-//              (optionally averaged with the stream's previous airlight)
+//              exact sums of the ties and of the pixels above vstar; the
+//              frame's last row block then finds the tie cut in raster order
+//              and forms A from exact sums (optionally averaged with the
+//              stream's previous airlight)
 //   k_select_one    Eq. (3) for small frames in one block, from per-tile
 //              histograms written by k_dark
 //   k_gf_prep  offline: per-pixel luma and coarse t (Eqs. (4)-(5)) in fixed point,
@@ -589,18 +590,18 @@ __global__ __launch_bounds__(256) void k_dark(Batch b) {
   }
 }
 
-// ------------------------------------------------ k_select_rows, k_select_final
+// ------------------------------------------------------------ k_select_rows
 // Eq. (3) with a unique top-K set: order pixels by (D descending, raster
 // index ascending) and take the first K.
 //   vstar  = largest v with #{D >= v} >= K (from the histogram)
 //   need   = K - #{D > vstar} >= 1 pixels with D == vstar are taken, the
 //            first `need` of them in raster order.
-// Two kernels with no atomics between them.  k_select_rows: each wave reads
-// one row of D, gathers I where D >= vstar and writes the row's record
-// (counts and exact sums of the ties D == vstar and of D > vstar).
-// k_select_final: one block per frame scans the row records, finds the row
-// holding the cut, finds the cutoff pixel inside it with a block-wide scan of
-// per-lane tie counts, and forms A^c = alpha * S^c / K from exact integer sums.
+// Row pass: each wave reads one row of D, gathers I where D >= vstar and
+// writes the row's record (counts and exact sums of the ties D == vstar and
+// of D > vstar).  Final step, in the frame's last row block to finish: scan
+// the row records, find the row holding the cut, find the cutoff pixel inside
+// it with a block-wide scan of per-lane tie counts, and form
+// A^c = alpha * S^c / K from exact integer sums.
 
 // The end of Eq. (3) for one frame, by one thread: A^c = alpha S^c / K from the
 // exact integer sums (in double; optionally averaged with the stream's stored
@@ -722,18 +723,44 @@ __device__ __forceinline__ void wave_vstar(const FrameState* st, uint32_t K, uin
   vstar_from_lane_counts(c, K, vstar, cnt_gt, total);
 }
 
-__global__ __launch_bounds__(256) void k_select_rows(Batch b) {
-  const int blk = blockIdx.x;
-  const int f = frame_of(b, blk);
-  const FrameDev& fd = b.f[f];
-  const int tile = blk - b.tile0[f];
+// A row record as four 8-byte words, written and read with agent-scope atomic
+// accesses: the frame's last row block reads every record in the same kernel.
+__device__ __forceinline__ void store_rowsel(RowSel* p, const RowSel& r) {
+  unsigned long long w[4];
+  __builtin_memcpy(w, &r, sizeof(w));
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ RowSel load_rowsel(const RowSel* p) {
+  unsigned long long w[4];
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  RowSel r;
+  __builtin_memcpy(&r, w, sizeof(w));
+  return r;
+}
+static_assert(sizeof(RowSel) == 32 && alignof(RowSel) <= 8, "a row record is four 8-byte words");
+
+// A k_select_rows block has kFinT threads (512 for launches of one frame,
+// whose final step then spreads over twice the threads; 256 for batches, so
+// that their row pass has more, shorter blocks): one row per wave, and the
+// final step of the frame's last block.
+constexpr int kFinRows = 5;            // sweeps of kFinT rows per round of the final step
+
+// The row pass of one block of k_select_rows: its kFinW rows' records.
+template <int kFinT>
+__device__ __forceinline__ void row_pass(const FrameDev& fd, int tile, uint32_t& s_vstar) {
+  constexpr int kFinW = kFinT / 64;
   const int W = fd.W, H = fd.H;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
 
   // one row per wave; each lane reads 16 consecutive bytes of D per step.
   // The first segment's D does not depend on vstar: it is loaded before the
   // histogram is read, so the two round trips overlap.
-  const int y = tile * 4 + wv;
+  const int y = tile * kFinW + wv;
   const bool row_ok = y < H;
   const uint8_t* Drow = fd.D + (int64_t)min(y, H - 1) * fd.D_pitch;
   uint4 dvs[kSelVec];  // all of this lane's D vectors of a segment, loaded up front
@@ -747,7 +774,6 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   load_d(0);
   // wave 0 forms vstar from the histogram and shares it (one histogram read
   // per block instead of per wave; the barrier wait overlaps the D loads)
-  __shared__ uint32_t s_vstar;
   if (wv == 0) {
     uint32_t v, cnt_gt;
     wave_vstar(fd.st, (uint32_t)fd.K, v, cnt_gt);
@@ -755,7 +781,7 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
   }
   __syncthreads();
   const uint32_t vstar = s_vstar;
-  if (!row_ok) return;
+  if (!row_ok) return;   // wave-uniform; the block's barriers come after the call
   uint32_t gR = 0, gG = 0, gB = 0, tR = 0, tG = 0, tB = 0;   // < W * 255 < 2^32
   uint32_t gN = 0, tN = 0;
   const uint8_t* Irow = fd.src + (int64_t)y * fd.src_pitch;
@@ -824,15 +850,12 @@ __global__ __launch_bounds__(256) void k_select_rows(Batch b) {
     r.ties = tN; r.above = gN;
     r.tsum[0] = tR; r.tsum[1] = tG; r.tsum[2] = tB;
     r.gsum[0] = gR; r.gsum[1] = gG; r.gsum[2] = gB;
-    fd.rowsel[y] = r;
+    store_rowsel(&fd.rowsel[y], r);
   }
 }
 
-constexpr int kFinT = 512;             // threads of the final selection block
-constexpr int kFinW = kFinT / 64;
-constexpr int kFinRows = 5;            // sweeps of kFinT rows per round (one round when H <= 2560)
 
-// The end of Eq. (3) for one frame, in one block.  Rows are dealt round-robin,
+// The final step of Eq. (3) for one frame, in one block.  Rows are dealt round-robin,
 // row = base + t + kFinT u for sweep u of a round, so a wave loads consecutive
 // records.  Per round of kFinRows sweeps:
 //   1. the records (with, in the first round, vstar and #{D > vstar} from the
@@ -847,13 +870,22 @@ constexpr int kFinRows = 5;            // sweeps of kFinT rows per round (one ro
 // first need - (ties before) ties; 4. one block sum of the sums over
 // D > vstar, the tie sums of the rows before the cut row and the cut row's
 // share, from which thread 0 forms A.
-__global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
-  __shared__ uint32_t s_ties[kFinRows][kFinT];   // tie counts of the round's rows, by sweep and thread
-  __shared__ uint32_t s_tw[kFinRows][kFinW];     // tie total of each wave of each sweep
-  __shared__ uint32_t s_cnt[kFinW];
-  __shared__ unsigned long long s_red[kFinW][5];
+template <int kFinT>
+struct FinShared {
+  static constexpr int kFinW = kFinT / 64;
+  uint32_t ties[kFinRows][kFinT];   // tie counts of the round's rows, by sweep and thread
+  uint32_t tw[kFinRows][kFinW];     // tie total of each wave of each sweep
+  uint32_t cnt[kFinW];
+  unsigned long long red[kFinW][5];
+};
 
-  const FrameDev& fd = b.f[blockIdx.x];  // one block per frame
+template <int kFinT>
+__device__ void final_selection(const FrameDev& fd, FinShared<kFinT>& sh) {
+  constexpr int kFinW = kFinT / 64;
+  uint32_t(&s_ties)[kFinRows][kFinT] = sh.ties;
+  uint32_t(&s_tw)[kFinRows][kFinW] = sh.tw;
+  uint32_t(&s_cnt)[kFinW] = sh.cnt;
+  unsigned long long(&s_red)[kFinW][5] = sh.red;
   const int W = fd.W, H = fd.H;
   const uint32_t K = (uint32_t)fd.K;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -864,7 +896,7 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     for (int u = 0; u < kFinRows; ++u) {
       const int y = base + tid + kFinT * u;
       if (y < H) {
-        r[u] = fd.rowsel[y];
+        r[u] = load_rowsel(&fd.rowsel[y]);
       } else {
         r[u].ties = 0u;
         r[u].above = 0u;
@@ -1012,6 +1044,33 @@ __global__ __launch_bounds__(kFinT) void k_select_final(Batch b) {
     const bool ok = S[3] == (unsigned long long)cnt_gt && cx >= 0 && total == (uint32_t)W * (uint32_t)H;
     store_airlight(fd, K, vstar, rstar * W + cx, S, ok ? 0 : 1);
   }
+}
+
+// The row pass, then, in the frame's last row block to finish, the final step.
+// Every block's records are agent-scope atomic stores, complete (the wave's
+// counters at zero) before the block counts itself in the frame's state; the
+// block that counts last reads all of them with agent-scope atomic loads
+// issued after its count returned.  Nothing else crosses blocks, so no L2
+// write-back is needed (a release fence per block, which writes back the XCD's
+// L2, made this 6 us slower than a kernel boundary).
+template <int kFinT>
+__global__ __launch_bounds__(kFinT) void k_select_rows(Batch b) {
+  __shared__ uint32_t s_vstar;
+  __shared__ int s_last;
+  __shared__ FinShared<kFinT> s_fin;
+  const int blk = blockIdx.x;
+  const int f = frame_of(b, blk);
+  const FrameDev& fd = b.f[f];
+  const int tile = blk - b.tile0[f];
+  row_pass<kFinT>(fd, tile, s_vstar);
+  __builtin_amdgcn_s_waitcnt(0);   // every counter at zero: this wave's record stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t blocks = (uint32_t)(b.tile0[f + 1] - b.tile0[f]);
+    s_last = atomicAdd(&fd.st->rows_done, 1u) == blocks - 1u;
+  }
+  __syncthreads();
+  if (s_last) final_selection(fd, s_fin);
 }
 
 // ------------------------------------------------------------ k_select_one
@@ -2391,11 +2450,10 @@ hipError_t launch_select_one(Batch b, hipStream_t s) {
 }
 
 hipError_t launch_select(Batch b, hipStream_t s) {
-  const int nblk = fill_tiles(b, [](const FrameDev& f) { return (f.H + 3) / 4; });
-  hipLaunchKernelGGL(k_select_rows, dim3(nblk), dim3(256), 0, s, b);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_select_final, dim3(b.n), dim3(kFinT), 0, s, b);
+  const int rows = b.n == 1 ? 8 : 4;   // rows (waves) per block
+  const int nblk = fill_tiles(b, [rows](const FrameDev& f) { return (f.H + rows - 1) / rows; });
+  if (rows == 8) hipLaunchKernelGGL(k_select_rows<512>, dim3(nblk), dim3(512), 0, s, b);
+  else hipLaunchKernelGGL(k_select_rows<256>, dim3(nblk), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ struct Arena {
 
 constexpr int kSlotsPerStream = 2;   // frames of one stream on the device at once
 
-// Host-coherent pinned cells of 4 int32 that k_select_final writes a served
+// Host-coherent pinned cells of 4 int32 that the selection writes a served
 // frame's {K, vstar, cutoff, status} into, so that the scheduler reads the
 // selection's consistency status when the launch completes, without a copy.
 // Process-wide pool, allocated in blocks and never freed (a block is reused by
