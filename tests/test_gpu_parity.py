@@ -237,8 +237,8 @@ def test_graph_replay_matches_direct_launch():
 
 @pytest.mark.parametrize("variant", ["offline_percentile_adaptive", "realtime_grayworld"])
 def test_state_zeroing_does_not_depend_on_workspace_contents(variant):
-    # Direct launches zero each frame's state inside k_dark (histograms) and the final selection
-    # (the later sums) instead of with the init kernel.  Run a batch on a workspace full of random
+    # Direct launches zero each frame's state in leading blocks of k_dark instead of with the
+    # init kernel.  Run a batch on a workspace full of random
     # bytes, then again with the frames in another order (each frame's state now lies on what
     # another frame's maps held), and compare with the graph-replayed form, which zeroes the
     # state with the init kernel.  The selection's status checks that every histogram holds W H.
@@ -283,7 +283,7 @@ def test_state_zeroing_does_not_depend_on_workspace_contents(variant):
 @pytest.mark.parametrize("w,h", [(320, 240), (1280, 720)])
 def test_stage_profiling_times_every_launch(w, h):
     # direct launches run no init kernel: a small frame takes the one-block selection, a larger
-    # one has k_dark and the final selection zero its state
+    # one has leading blocks of k_dark zero its state
     I = _frame(w, h, 51)
     p = P(mode=hzd.MODE_OFFLINE, gf_radius=60, color_balance=1)
     ref = run_gpu(I, p, with_J=False)["out"]
@@ -307,7 +307,7 @@ def test_stage_profiling_times_every_launch(w, h):
 def test_caller_graph_capture_replays_and_is_not_timed(w, h):
     # a call made while the caller captures its stream joins the caller's graph; profiling
     # stays off for it (its events would complete only when the graph runs).  640x480 takes the
-    # two-kernel selection, whose captured form zeroes the state with the init kernel on every
+    # row-record selection, whose captured form zeroes the state with the init kernel on every
     # replay
     I1, I2 = _frame(w, h, 52), _frame(w, h, 53)
     p = P(mode=hzd.MODE_OFFLINE, gf_radius=16, color_balance=1)

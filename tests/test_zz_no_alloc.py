@@ -59,8 +59,8 @@ def test_noalloc_equals_workspace_entry_two_calls():
 
 def test_noalloc_under_graph_capture_replays():
     # callers that cannot allocate include code under graph capture: the captured call zeroes the
-    # frame state with the init kernel on every replay (direct calls do it inside k_dark and the
-    # final selection); each replay equals the workspace entry point's direct result
+    # frame state with the init kernel on every replay (direct calls do it in leading blocks of
+    # k_dark); each replay equals the workspace entry point's direct result
     p = hzd.Params(mode=hzd.MODE_OFFLINE, gf_radius=20, color_balance=1)
     I1, I2 = make_frame(640, 480, 31).I, make_frame(640, 480, 32, beta=1.4).I
     ref1, ref2 = _run("workspace", I1, p)["out"], _run("workspace", I2, p)["out"]
