@@ -162,6 +162,33 @@ def test_batch_equals_frame():
             assert np.array_equal(auxs[i][k].cpu().numpy(), alone[k]), (i, k)
 
 
+def test_row_record_selection_batch_of_sixteen():
+    # sixteen frames too large for the one-block selection, of sixteen different heights (from
+    # 4 rows to a 4K frame's 2160), in one launch: the row pass runs in 256-thread blocks and
+    # each frame's last block ends its selection; a frame alone runs it in 512-thread blocks.
+    # Every frame's selection, A and output equal its single-frame result, and two frames are
+    # also checked against the FP64 oracle
+    rng = np.random.default_rng(91)
+    heights = [4, 17, 64, 65, 129, 200, 255, 256, 257, 511, 700, 1023, 1080, 1300, 2049, 2160]
+    widths = [int(w) for w in rng.integers(1100, 2000, size=len(heights))]
+    widths[-1] = 3840
+    p = P()
+    frames = [make_frame(w, h, 900 + i, beta=0.7 + 0.05 * i).I for i, (w, h) in enumerate(zip(widths, heights))]
+    srcs = [to_dev(I) for I in frames]
+    dsts = [torch.zeros_like(s) for s in srcs]
+    auxs = [hzd.make_aux(h, w, J=False) for w, h in zip(widths, heights)]
+    hzd.dehaze_batch(srcs, dsts, p, auxs=auxs)
+    torch.cuda.synchronize()
+    for i, I in enumerate(frames):
+        alone = run_gpu(I, p, with_J=False)
+        assert int(auxs[i]["sel"][3].item()) == 0, i
+        assert np.array_equal(auxs[i]["sel"].cpu().numpy(), alone["sel"]), i
+        assert np.array_equal(auxs[i]["A"].cpu().numpy(), alone["A"]), i
+        assert np.array_equal(dsts[i].cpu().numpy(), alone["out"]), i
+        if i in (3, 12):
+            compare(I, p, alone, label=f"batch of sixteen, frame {i}")
+
+
 def test_same_shape_batch_of_eight_720p_fp16():
     # one launch of 8 real-time 720p frames (FP16 t), every frame equal to its single-frame result
     from synth import make_video
